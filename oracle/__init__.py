@@ -1,0 +1,181 @@
+"""CPU oracle for the checkerboard Metropolis sweep (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never does.
+
+The arithmetic lives in ``ising_oracle.c`` (plain scalar C, optional OpenMP
+over rows of one colour, which is bit-identical because sites of one colour
+never neighbour each other).  This module only compiles it with gcc and
+marshals numpy buffers through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ising_oracle.c")
+_LIB = os.path.join(_HERE, "libising_oracle.so")
+
+MODE_SITE = 0
+MODE_PLANE = 1
+START_COLD_UP = 0
+START_RANDOM = 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, no FP contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    i8p = ctypes.POINTER(ctypes.c_int8)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_thresholds.argtypes = [ctypes.c_double, u32p, u8p]
+    lib.oracle_thresholds.restype = ctypes.c_int
+    lib.oracle_accept.argtypes = [ctypes.c_int, ctypes.c_uint32, u32p, u8p]
+    lib.oracle_accept.restype = ctypes.c_int
+    lib.oracle_local_u.argtypes = [i8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_local_u.restype = ctypes.c_int
+    lib.oracle_init.argtypes = [i8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                ctypes.c_uint32]
+    lib.oracle_init.restype = ctypes.c_int
+    lib.oracle_fill_uniforms.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                         ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                                         u32p, ctypes.c_int]
+    lib.oracle_fill_uniforms.restype = ctypes.c_int
+    lib.oracle_halfsweep.argtypes = [i8p, ctypes.c_int, ctypes.c_int, u32p, u32p, u8p,
+                                     i64p, i64p, ctypes.c_int]
+    lib.oracle_halfsweep.restype = ctypes.c_int
+    lib.oracle_measure.argtypes = [i8p, ctypes.c_int, i64p, i64p]
+    lib.oracle_measure.restype = None
+    lib.oracle_sweep.argtypes = [i8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64,
+                                 ctypes.c_double, i64p, i64p, ctypes.c_int]
+    lib.oracle_sweep.restype = ctypes.c_int
+    lib.oracle_max_threads.argtypes = []
+    lib.oracle_max_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of one 128-bit counter under a 64-bit key (two words)."""
+    lib = _load()
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    lib.oracle_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
+                             _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def thresholds(beta: float):
+    """(T[5], always[5]) for u = -4,-2,0,2,4; raises on invalid beta."""
+    lib = _load()
+    T = np.zeros(5, dtype=np.uint32)
+    a = np.zeros(5, dtype=np.uint8)
+    if lib.oracle_thresholds(float(beta), _ptr(T, ctypes.c_uint32),
+                             _ptr(a, ctypes.c_uint8)):
+        raise ValueError(f"invalid beta {beta!r}")
+    return T, a
+
+
+def accept(u: int, r: int, T: np.ndarray, always: np.ndarray) -> bool:
+    lib = _load()
+    return bool(lib.oracle_accept(int(u), int(r), _ptr(T, ctypes.c_uint32),
+                                  _ptr(always, ctypes.c_uint8)))
+
+
+def local_u(s: np.ndarray, x: int, y: int) -> int:
+    lib = _load()
+    L = s.shape[0]
+    return int(lib.oracle_local_u(_ptr(s, ctypes.c_int8), L, x, y))
+
+
+def init(L: int, start: int, seed: int, lattice_id: int = 0) -> np.ndarray:
+    lib = _load()
+    s = np.zeros((L, L), dtype=np.int8)
+    if lib.oracle_init(_ptr(s, ctypes.c_int8), L, start, seed, lattice_id):
+        raise ValueError("oracle_init rejected its arguments")
+    return s
+
+
+def fill_uniforms(L: int, mode: int, seed: int, lattice_id: int, t: int, c: int,
+                  nthreads: int = 1) -> np.ndarray:
+    """Draws r[y, x] for the sites of colour c in half-sweep 2t+c (others 0)."""
+    lib = _load()
+    r = np.zeros((L, L), dtype=np.uint32)
+    if lib.oracle_fill_uniforms(L, mode, seed, lattice_id, t, c,
+                                _ptr(r, ctypes.c_uint32), nthreads):
+        raise ValueError("oracle_fill_uniforms rejected its arguments")
+    return r
+
+
+def halfsweep(s: np.ndarray, c: int, r: np.ndarray, T: np.ndarray, always: np.ndarray,
+              nthreads: int = 1):
+    """In-place update of colour c with draws r; returns (dE, dM)."""
+    lib = _load()
+    L = s.shape[0]
+    dE = ctypes.c_int64(0)
+    dM = ctypes.c_int64(0)
+    if lib.oracle_halfsweep(_ptr(s, ctypes.c_int8), L, c, _ptr(r, ctypes.c_uint32),
+                            _ptr(T, ctypes.c_uint32), _ptr(always, ctypes.c_uint8),
+                            ctypes.byref(dE), ctypes.byref(dM), nthreads):
+        raise ValueError("oracle_halfsweep rejected its arguments")
+    return dE.value, dM.value
+
+
+def measure(s: np.ndarray):
+    lib = _load()
+    L = s.shape[0]
+    E = ctypes.c_int64(0)
+    M = ctypes.c_int64(0)
+    lib.oracle_measure(_ptr(s, ctypes.c_int8), L, ctypes.byref(E), ctypes.byref(M))
+    return E.value, M.value
+
+
+def sweep(s: np.ndarray, mode: int, seed: int, lattice_id: int, t0: int, n: int,
+          beta: float, record: bool = True, nthreads: int = 1):
+    """n sweeps in place from sweep index t0; returns (E_trace, M_trace)."""
+    lib = _load()
+    L = s.shape[0]
+    E = np.zeros(max(n, 0), dtype=np.int64)
+    M = np.zeros(max(n, 0), dtype=np.int64)
+    Ep = _ptr(E, ctypes.c_int64) if record else None
+    Mp = _ptr(M, ctypes.c_int64) if record else None
+    if lib.oracle_sweep(_ptr(s, ctypes.c_int8), L, mode, seed, lattice_id, t0, n,
+                        float(beta), Ep, Mp, nthreads):
+        raise ValueError("oracle_sweep rejected its arguments")
+    return (E, M) if record else (None, None)
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
