@@ -1,0 +1,169 @@
+/*
+ * ising.h - C ABI of the MI355X checkerboard Metropolis library (libising.so).
+ *
+ * The library runs the Metropolis single-spin-flip Monte Carlo of the 2D
+ * Ising model H = -sum_<ij> s_i s_j on an L x L periodic square lattice,
+ * updating the two checkerboard sublattices alternately.  This is the hot
+ * path of "Many-body computing on Field Programmable Gate Arrays"
+ * (arXiv 2402.06415): the Hamiltonian is the paper's Eq. (1) restricted to
+ * theta in {0, pi}; the bipartite, alternating update is the one of the
+ * Results section "Parallel design of MC simulation for the XY model" and
+ * Fig. 2a-b; each trial follows the three steps of Fig. 2c and of the
+ * Supplementary section "Detail of the MC calculation for the XY model":
+ * draw p uniform in [0,1), compute dE and P = exp(-beta dE), accept iff p < P.
+ * The per-site LCG of the paper is replaced by the counter-based
+ * Philox4x32-10 generator (Salmon et al., SC'11).
+ *
+ * Conventions (identical in every entry point):
+ *   site n = y*L + x, colour(x,y) = (x+y) & 1; colour 0 is updated first in
+ *   each sweep; a sweep is one update of colour 0 then one of colour 1.
+ *   Spin s = +1 or -1.  INT8 layout: s[n] as int8, row-major, L*L bytes.
+ *   BIT1 layout (L % 64 == 0): two colour planes, plane c at byte offset
+ *   c*L*L/16, each L rows of L/64 uint32 words; bit b of word w in row y
+ *   of plane c is the colour-c site of row y with compact column 32w+b
+ *   (x = 2*(32w+b) + ((y+c)&1)); bit value 1 means s = -1.
+ *   Draws: p = r / 2^32, accepted iff r < T = ceil(2^32 exp(-beta dE)),
+ *   thresholds computed on the host in IEEE double; dE <= 0 always flips.
+ *   The Philox key is (seed lo, seed hi); the counter of a draw is
+ *     INT8 (per site):  (q >> 2, lattice_id, 2t + c, 0),  r = out[q & 3],
+ *     BIT1 (bit planes): (q >> 5, lattice_id, 2t + c, 1 | b << 8), and bit
+ *       (31 - k) of r is bit (q & 31) of out[k & 3] of block b = k >> 2,
+ *   with q = n >> 1 the compact index of site n within its colour and t
+ *   the sweep index.  Random start: s = -1 iff the top bit of out[n & 3]
+ *   of counter (n >> 2, lattice_id, 0, 2) is set.
+ *   E = -sum over right and down bonds of s_i s_j, M = sum s_i (int64).
+ *
+ * Memory and streams: every device pointer is caller-owned (the Python
+ * binding allocates them as torch tensors); the library allocates nothing.
+ * Every call enqueues its work on the given HIP stream (NULL = the null
+ * stream) and returns without synchronising; results are valid once the
+ * stream has reached that point.  A lattice handle must not be used from
+ * two host threads at once, and two calls on the same spins must not
+ * overlap on different streams.
+ *
+ * Errors: every int-returning call returns ISING_OK (0) or an error code.
+ * ISING_E_INVALID and ISING_E_UNSUPPORTED leave the lattice and all device
+ * memory untouched.  ISING_E_HIP reports a failed HIP call (launch or
+ * configuration); device contents are then undefined.  ISING_E_STATE
+ * reports a device-side failure detected after the fact (see
+ * ising_check_device_error).  ising_last_error() returns a thread-local
+ * message describing the last failure of the calling thread.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISING_ABI_VERSION 1
+
+#if defined(__GNUC__) || defined(__clang__)
+#define ISING_API __attribute__((visibility("default")))
+#else
+#define ISING_API
+#endif
+
+enum ising_layout { ISING_LAYOUT_INT8 = 0, ISING_LAYOUT_BIT1 = 1 };
+enum ising_start { ISING_START_COLD_UP = 0, ISING_START_RANDOM = 1 };
+
+/* Kernel-choice flags.  Every choice computes the same chain bit for bit;
+ * they exist so that each variant can be tested and timed. */
+enum ising_flags {
+    /* one launch per half-sweep reading the spins from global memory,
+     * instead of the resident single-workgroup (INT8, L <= 128) or the
+     * persistent tile-resident (BIT1) kernel */
+    ISING_FLAG_GLOBAL_HALFSWEEP = 1u
+};
+enum ising_status {
+    ISING_OK = 0,
+    ISING_E_INVALID = 1,     /* bad argument; nothing was changed          */
+    ISING_E_UNSUPPORTED = 2, /* valid request this build does not run      */
+    ISING_E_HIP = 3,         /* a HIP runtime call failed                  */
+    ISING_E_STATE = 4        /* device reported an inconsistent state      */
+};
+
+/* Plain-old-data description of one lattice.  The caller fills every field
+ * before ising_init (or ising_from_int8) and keeps it alive; the library
+ * only advances sweep_index. */
+typedef struct ising_lattice {
+    int32_t abi_version;  /* must equal ISING_ABI_VERSION                   */
+    int32_t dim;          /* 2                                              */
+    int32_t L;            /* even, 4 <= L <= 65536; BIT1: L % 64 == 0       */
+    int32_t layout;       /* enum ising_layout                              */
+    uint64_t seed;        /* Philox key                                     */
+    uint32_t lattice_id;  /* second Philox counter word                     */
+    uint32_t flags;       /* ISING_FLAG_* bits; 0 = automatic kernel choice  */
+    uint64_t sweep_index; /* t of the next sweep; < 2^31                    */
+    void *spins;          /* device, >= ising_spins_bytes(), 256-B aligned  */
+    void *workspace;      /* device, >= ising_workspace_bytes(), 256-B aligned,
+                             NULL allowed when that size is 0               */
+} ising_lattice;
+
+/* Bytes of spin storage for (dim, L, layout); 0 if the combination is
+ * invalid.  INT8: L*L.  BIT1: L*L/8. */
+ISING_API size_t ising_spins_bytes(int32_t dim, int32_t L, int32_t layout);
+
+/* Bytes of device workspace the calls on such a lattice need (partial
+ * sums, synchronisation flags, halo rows); 0 if invalid. */
+ISING_API size_t ising_workspace_bytes(int32_t dim, int32_t L, int32_t layout);
+
+/* ABI version of the loaded library (== ISING_ABI_VERSION when matched). */
+ISING_API int32_t ising_abi_version(void);
+
+/* Host-only: acceptance table for u = s_i h_i = -4,-2,0,2,4 (index
+ * (u+4)/2): T[k] = ceil(2^32 exp(-2 beta u)) for u > 0, always[k] = 1 when
+ * the flip needs no draw (u <= 0, or 2^32 P rounds up to 2^32).  Follows
+ * step 2 and 3 of the trial (P(dE) = exp(-beta dE), accept iff p < P).
+ * Errors: beta negative, NaN or infinite -> ISING_E_INVALID. */
+ISING_API int ising_thresholds(double beta, uint32_t T[5], uint8_t always_flip[5]);
+
+/* Fill the spins: ISING_START_COLD_UP (all +1) or ISING_START_RANDOM
+ * (Philox draw per site, see above) and set sweep_index = 0.
+ * Errors: invalid lattice description or start -> ISING_E_INVALID. */
+ISING_API int ising_init(ising_lattice *lat, int32_t start, void *hip_stream);
+
+/* Run n >= 0 sweeps at inverse temperature beta from sweep index
+ * lat->sweep_index, then advance it by n.  E_dev / M_dev, when non-NULL,
+ * are device int64[n] receiving E and M after each sweep of this call.
+ * sweep(b, n1) followed by sweep(b, n2) equals sweep(b, n1 + n2) bit for
+ * bit.  Errors: beta negative, NaN or infinite; n < 0;
+ * sweep_index + n > 2^31; invalid lattice -> ISING_E_INVALID. */
+ISING_API int ising_sweep(ising_lattice *lat, double beta, int64_t n, int64_t *E_dev,
+                int64_t *M_dev, void *hip_stream);
+
+/* Recount E and M of the current spins from scratch into E_dev[0] and
+ * M_dev[0] (device int64; either may be NULL). */
+ISING_API int ising_measure(const ising_lattice *lat, int64_t *E_dev, int64_t *M_dev,
+                  void *hip_stream);
+
+/* Copy the spins to / from the canonical INT8 row-major form (device
+ * int8[L*L] of +1/-1, 4-byte aligned).  ising_from_int8 does not change
+ * sweep_index.
+ * Values other than +1/-1 in the input are read as -1 if negative, else +1. */
+ISING_API int ising_to_int8(const ising_lattice *lat, int8_t *out_dev, void *hip_stream);
+ISING_API int ising_from_int8(ising_lattice *lat, const int8_t *in_dev, void *hip_stream);
+
+/* Read back (synchronising hip_stream) how many Philox4x32-10 blocks
+ * (128 random bits each) the sweeps on this lattice have drawn since the
+ * last ising_init: the random-number work the method actually consumed,
+ * which sets the integer-ALU cost of a sweep.  Diagnostic only. */
+ISING_API int ising_rng_blocks(const ising_lattice *lat, uint64_t *blocks_host,
+                               void *hip_stream);
+
+/* Read back (synchronising hip_stream) the device error word written by
+ * kernels that wait on each other; returns ISING_OK if clear, else
+ * ISING_E_STATE with a message, and clears it. */
+ISING_API int ising_check_device_error(const ising_lattice *lat, void *hip_stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+ISING_API const char *ising_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISING_H */

@@ -1,0 +1,246 @@
+"""Thin ctypes binding of libising.so (declared in include/ising.h).
+
+Functions carry the C names and only marshal arguments; every step of the
+sweep runs in the HIP kernels of the library.  There is no CPU fallback: if
+the library is missing or fails to load, every call raises.
+
+Device memory and streams come from PyTorch: ``Lattice`` allocates the spin
+and workspace buffers as torch tensors on the current HIP device and passes
+``torch.cuda.current_stream()`` to the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libising.so")
+
+ABI_VERSION = 1
+LAYOUT_INT8 = 0
+LAYOUT_BIT1 = 1
+START_COLD_UP = 0
+START_RANDOM = 1
+OK, E_INVALID, E_UNSUPPORTED, E_HIP, E_STATE = 0, 1, 2, 3, 4
+FLAG_GLOBAL_HALFSWEEP = 1
+
+EXPORTED = (
+    "ising_spins_bytes", "ising_workspace_bytes", "ising_abi_version", "ising_thresholds",
+    "ising_init", "ising_sweep", "ising_measure", "ising_to_int8", "ising_from_int8",
+    "ising_check_device_error", "ising_last_error", "ising_rng_blocks",
+)
+
+
+class IsingError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"libising error {code}: {message}")
+        self.code = code
+
+
+class ising_lattice(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("dim", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("lattice_id", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("sweep_index", ctypes.c_uint64),
+        ("spins", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libising.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lat_p = P(ising_lattice)
+    vp = ctypes.c_void_p
+    lib.ising_spins_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.ising_spins_bytes.restype = ctypes.c_size_t
+    lib.ising_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.ising_workspace_bytes.restype = ctypes.c_size_t
+    lib.ising_abi_version.argtypes = []
+    lib.ising_abi_version.restype = ctypes.c_int32
+    lib.ising_thresholds.argtypes = [ctypes.c_double, P(ctypes.c_uint32), P(ctypes.c_uint8)]
+    lib.ising_thresholds.restype = ctypes.c_int
+    lib.ising_init.argtypes = [lat_p, ctypes.c_int32, vp]
+    lib.ising_init.restype = ctypes.c_int
+    lib.ising_sweep.argtypes = [lat_p, ctypes.c_double, ctypes.c_int64, vp, vp, vp]
+    lib.ising_sweep.restype = ctypes.c_int
+    lib.ising_measure.argtypes = [lat_p, vp, vp, vp]
+    lib.ising_measure.restype = ctypes.c_int
+    lib.ising_to_int8.argtypes = [lat_p, vp, vp]
+    lib.ising_to_int8.restype = ctypes.c_int
+    lib.ising_from_int8.argtypes = [lat_p, vp, vp]
+    lib.ising_from_int8.restype = ctypes.c_int
+    lib.ising_rng_blocks.argtypes = [lat_p, P(ctypes.c_uint64), vp]
+    lib.ising_rng_blocks.restype = ctypes.c_int
+    lib.ising_check_device_error.argtypes = [lat_p, vp]
+    lib.ising_check_device_error.restype = ctypes.c_int
+    lib.ising_last_error.argtypes = []
+    lib.ising_last_error.restype = ctypes.c_char_p
+    if lib.ising_abi_version() != ABI_VERSION:
+        raise RuntimeError("libising.so ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise IsingError(rc, ising_last_error())
+
+
+# ------------------------------------------------------------ C-named calls
+def ising_last_error() -> str:
+    return load_library().ising_last_error().decode()
+
+
+def ising_abi_version() -> int:
+    return int(load_library().ising_abi_version())
+
+
+def ising_spins_bytes(dim: int, L: int, layout: int) -> int:
+    return int(load_library().ising_spins_bytes(dim, L, layout))
+
+
+def ising_workspace_bytes(dim: int, L: int, layout: int) -> int:
+    return int(load_library().ising_workspace_bytes(dim, L, layout))
+
+
+def ising_thresholds(beta: float):
+    T = np.zeros(5, dtype=np.uint32)
+    a = np.zeros(5, dtype=np.uint8)
+    _check(load_library().ising_thresholds(
+        float(beta), T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+        a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return T, a
+
+
+def ising_init(lat: ising_lattice, start: int, stream: int = 0):
+    _check(load_library().ising_init(ctypes.byref(lat), start, stream))
+
+
+def ising_sweep(lat: ising_lattice, beta: float, n: int, E_dev: int = 0, M_dev: int = 0,
+                stream: int = 0):
+    _check(load_library().ising_sweep(ctypes.byref(lat), float(beta), int(n), E_dev or None,
+                                      M_dev or None, stream))
+
+
+def ising_measure(lat: ising_lattice, E_dev: int = 0, M_dev: int = 0, stream: int = 0):
+    _check(load_library().ising_measure(ctypes.byref(lat), E_dev or None, M_dev or None, stream))
+
+
+def ising_to_int8(lat: ising_lattice, out_dev: int, stream: int = 0):
+    _check(load_library().ising_to_int8(ctypes.byref(lat), out_dev, stream))
+
+
+def ising_from_int8(lat: ising_lattice, in_dev: int, stream: int = 0):
+    _check(load_library().ising_from_int8(ctypes.byref(lat), in_dev, stream))
+
+
+def ising_rng_blocks(lat: ising_lattice, stream: int = 0) -> int:
+    v = ctypes.c_uint64(0)
+    _check(load_library().ising_rng_blocks(ctypes.byref(lat), ctypes.byref(v), stream))
+    return int(v.value)
+
+
+def ising_check_device_error(lat: ising_lattice, stream: int = 0):
+    _check(load_library().ising_check_device_error(ctypes.byref(lat), stream))
+
+
+# ------------------------------------------------------------ torch-backed lattice
+def _aligned_buffer(nbytes: int, device):
+    """A uint8 device tensor whose data pointer is 256-byte aligned."""
+    import torch
+
+    raw = torch.zeros(max(nbytes, 1) + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw, raw[off:off + max(nbytes, 1)]
+
+
+class Lattice:
+    """One lattice whose spin and workspace memory are torch tensors."""
+
+    def __init__(self, L: int, layout: str = "int8", seed: int = 1, lattice_id: int = 0,
+                 start: str = "cold", device=None, init: bool = True, flags: int = 0):
+        import torch
+
+        self.device = torch.device(device or "cuda")
+        lay = {"int8": LAYOUT_INT8, "bit1": LAYOUT_BIT1}[layout]
+        nb = ising_spins_bytes(2, L, lay)
+        if nb == 0:
+            raise IsingError(E_INVALID, f"L={L} is invalid for layout {layout}")
+        nw = ising_workspace_bytes(2, L, lay)
+        self._spins_raw, self.spins = _aligned_buffer(nb, self.device)
+        self._ws_raw, self.workspace = _aligned_buffer(nw, self.device)
+        self.c = ising_lattice(ABI_VERSION, 2, L, lay, seed, lattice_id, flags, 0,
+                               self.spins.data_ptr(), self.workspace.data_ptr())
+        self.L = L
+        self.layout = layout
+        if init:
+            self.init(start)
+
+    @staticmethod
+    def _stream() -> int:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+
+    @property
+    def sweep_index(self) -> int:
+        return int(self.c.sweep_index)
+
+    def init(self, start: str = "cold"):
+        ising_init(self.c, {"cold": START_COLD_UP, "random": START_RANDOM}[start], self._stream())
+
+    def sweep(self, beta: float, n: int, record: bool = True):
+        """n sweeps; returns device int64 tensors (E, M) after each sweep."""
+        import torch
+
+        if record:
+            E = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+            M = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+            ising_sweep(self.c, beta, n, E.data_ptr(), M.data_ptr(), self._stream())
+            return E[:n], M[:n]
+        ising_sweep(self.c, beta, n, 0, 0, self._stream())
+        return None, None
+
+    def measure(self):
+        import torch
+
+        out = torch.empty(2, dtype=torch.int64, device=self.device)
+        ising_measure(self.c, out.data_ptr(), out.data_ptr() + 8, self._stream())
+        return out
+
+    def to_int8(self):
+        import torch
+
+        out = torch.empty((self.L, self.L), dtype=torch.int8, device=self.device)
+        ising_to_int8(self.c, out.data_ptr(), self._stream())
+        return out
+
+    def from_int8(self, s):
+        import torch
+
+        s = s.to(device=self.device, dtype=torch.int8).contiguous()
+        assert s.shape == (self.L, self.L)
+        ising_from_int8(self.c, s.data_ptr(), self._stream())
+
+    def check(self):
+        ising_check_device_error(self.c, self._stream())
+
+    def rng_blocks(self) -> int:
+        return ising_rng_blocks(self.c, self._stream())

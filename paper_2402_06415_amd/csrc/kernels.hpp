@@ -1,0 +1,68 @@
+// Host-side launchers of the sweep kernels (internal to libising.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace ising {
+
+// Workspace layout (device bytes, caller-owned, 256-B aligned base).
+struct WsLayout {
+    static constexpr size_t kAcc = 0;        // int64[4]: raw E, raw M, E0, M0
+    static constexpr size_t kRngBlocks = 32; // uint64: Philox blocks drawn since init
+    static constexpr size_t kErr = 64;       // uint32 device error word
+    static constexpr size_t kFlags = 256;    // uint32 per workgroup, 128-B stride
+    static constexpr size_t kFlagStride = 128;
+    static constexpr int kMaxTiles = 256;
+    static size_t halo_offset() { return kFlags + kMaxTiles * kFlagStride; }
+};
+
+// INT8 layout ---------------------------------------------------------------
+hipError_t launch_init_int8(int8_t* s, int L, int start, Key key, uint32_t lid,
+                            hipStream_t st);
+hipError_t launch_sweep_int8_resident(int8_t* s, int L, int64_t n, uint32_t t0, Key key,
+                                      uint32_t lid, Accept acc, int64_t* Etr, int64_t* Mtr,
+                                      unsigned long long* nblk, hipStream_t st);
+bool int8_resident_fits(int L);
+hipError_t launch_halfsweep_int8(int8_t* s, int L, int c, uint32_t h, Key key, uint32_t lid,
+                                 Accept acc, long long* dE, long long* dM,
+                                 unsigned long long* nblk, hipStream_t st);
+hipError_t launch_measure_int8(const int8_t* s, int L, long long* acc, hipStream_t st);
+hipError_t launch_convert_int8(const int8_t* in, int8_t* out, int64_t N, hipStream_t st);
+
+// BIT1 layout ---------------------------------------------------------------
+hipError_t launch_init_bit1(uint32_t* planes, int L, int start, Key key, uint32_t lid,
+                            hipStream_t st);
+hipError_t launch_halfsweep_bit1(uint32_t* planes, int L, int c, uint32_t h, Key key,
+                                 uint32_t lid, Accept acc, long long* dE, long long* dM,
+                                 unsigned long long* nblk, hipStream_t st);
+hipError_t launch_measure_bit1(const uint32_t* planes, int L, long long* acc, hipStream_t st);
+hipError_t launch_to_int8_bit1(const uint32_t* planes, int L, int8_t* out, hipStream_t st);
+hipError_t launch_from_int8_bit1(uint32_t* planes, int L, const int8_t* in, hipStream_t st);
+
+// Persistent tile-resident sweep (BIT1); returns hipErrorNotSupported when
+// the lattice does not fit the resident scheme on this device.
+struct Bit1TilePlan {
+    int ntiles = 0;     // workgroups, one tile of rows each
+    int rows = 0;       // rows per tile
+    size_t lds = 0;     // dynamic LDS bytes
+};
+bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan);
+hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& plan,
+                                   int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
+                                   long long* dE, long long* dM, unsigned char* ws,
+                                   uint32_t spin_limit, hipStream_t st);
+
+// Shared small kernels ------------------------------------------------------
+hipError_t launch_fill_i64(long long* p, int64_t n, long long v, hipStream_t st);
+// out[j] = base + sum_{i<=j} d[i] in place (d == out allowed); base read
+// from device memory.
+hipError_t launch_prefix_i64(long long* d, int64_t n, const long long* base, hipStream_t st);
+// E_out = a*acc[0] + b ; M_out = c*acc[1] + d   (either output may be NULL)
+hipError_t launch_finish_measure(const long long* acc, long long aE, long long bE, long long aM,
+                                 long long bM, long long* E_out, long long* M_out,
+                                 long long* E_copy, long long* M_copy, hipStream_t st);
+
+}  // namespace ising

@@ -1,0 +1,144 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and its host-only logic (sizes, thresholds, argument validation) is right.
+No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2402_06415_amd as lib
+from paper_2402_06415_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ising.h")).read()
+    return sorted(set(re.findall(r"ISING_API\s+[\w\s\*]*?\b(ising_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    declared = _declared_symbols()
+    assert len(declared) >= 12
+    so = ctypes.CDLL(binding.LIB_PATH)
+    for name in declared:
+        assert hasattr(so, name), name
+    assert sorted(binding.EXPORTED) == declared
+
+
+def test_abi_version():
+    assert lib.ising_abi_version() == lib.ABI_VERSION
+
+
+def test_struct_layout_matches_header():
+    # int32 x4, uint64, uint32 x2, uint64, two pointers
+    assert ctypes.sizeof(binding.ising_lattice) == 56
+    assert binding.ising_lattice.spins.offset == 40
+    assert binding.ising_lattice.sweep_index.offset == 32
+
+
+@pytest.mark.parametrize("L,layout,want", [(16, 0, 256), (4096, 1, 2 ** 21), (6, 0, 36),
+                                           (7, 0, 0), (2, 0, 0), (96, 1, 0), (128, 1, 2048),
+                                           (65536, 1, 2 ** 29), (65538, 0, 0)])
+def test_spins_bytes(L, layout, want):
+    assert lib.ising_spins_bytes(2, L, layout) == want
+    assert lib.ising_spins_bytes(3, L, layout) == 0
+
+
+def test_workspace_bytes():
+    for L, layout in ((16, 0), (4096, 1), (64, 1)):
+        ws = lib.ising_workspace_bytes(2, L, layout)
+        assert ws > 0 and ws % 256 == 0
+    assert lib.ising_workspace_bytes(2, 4096, 1) >= 256 * 128 + 256 * 4 * 64 * 4
+
+
+@pytest.mark.parametrize("beta", [0.0, 1e-12, 0.1, 0.3, 0.4, 0.4406868, 0.48, 0.6, 1.2, 5.0])
+def test_thresholds_equal_oracle(beta):
+    T, a = lib.ising_thresholds(beta)
+    To, ao = oracle.thresholds(beta)
+    assert (T == To).all() and (a == ao).all()
+
+
+@pytest.mark.parametrize("beta", [-1e-9, float("nan"), float("inf"), -float("inf")])
+def test_thresholds_reject(beta):
+    with pytest.raises(lib.IsingError) as e:
+        lib.ising_thresholds(beta)
+    assert e.value.code == binding.E_INVALID
+    assert "beta" in lib.ising_last_error()
+
+
+def _lat(**kw):
+    d = dict(abi_version=1, dim=2, L=16, layout=0, seed=1, lattice_id=0, flags=0,
+             sweep_index=0, spins=0x1000, workspace=0x2000)
+    d.update(kw)
+    return binding.ising_lattice(**d)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(abi_version=2), binding.E_INVALID),
+    (dict(dim=3), binding.E_UNSUPPORTED),
+    (dict(L=7), binding.E_INVALID),
+    (dict(L=2), binding.E_INVALID),
+    (dict(layout=1, L=96), binding.E_INVALID),
+    (dict(layout=5), binding.E_INVALID),
+    (dict(flags=8), binding.E_INVALID),
+    (dict(spins=0), binding.E_INVALID),
+    (dict(spins=0x1001), binding.E_INVALID),
+    (dict(workspace=0), binding.E_INVALID),
+    (dict(workspace=0x2080), binding.E_INVALID),
+    (dict(sweep_index=2 ** 31 + 1), binding.E_INVALID),
+])
+def test_invalid_lattices_are_rejected_before_any_launch(kw, code):
+    lat = _lat(**kw)
+    before = bytes(lat)
+    for call in (lambda: lib.ising_init(lat, 0), lambda: lib.ising_sweep(lat, 0.4, 1),
+                 lambda: lib.ising_measure(lat, 0x3000, 0x3008),
+                 lambda: lib.ising_to_int8(lat, 0x4000),
+                 lambda: lib.ising_from_int8(lat, 0x4000)):
+        with pytest.raises(lib.IsingError) as e:
+            call()
+        assert e.value.code == code
+        assert bytes(lat) == before  # the lattice description is untouched
+
+
+@pytest.mark.parametrize("beta,n,t0", [(-0.1, 1, 0), (float("nan"), 1, 0), (0.4, -1, 0),
+                                       (0.4, 2, 2 ** 31 - 1)])
+def test_sweep_argument_errors(beta, n, t0):
+    lat = _lat(sweep_index=t0)
+    with pytest.raises(lib.IsingError) as e:
+        lib.ising_sweep(lat, beta, n)
+    assert e.value.code == binding.E_INVALID
+    assert lat.sweep_index == t0
+
+
+def test_bad_start_and_null_buffers():
+    lat = _lat()
+    with pytest.raises(lib.IsingError):
+        lib.ising_init(lat, 7)
+    with pytest.raises(lib.IsingError):
+        lib.ising_to_int8(lat, 0)
+    with pytest.raises(lib.IsingError):
+        lib.ising_from_int8(lat, 0)
+
+
+def test_sweep_of_zero_sweeps_launches_nothing():
+    lat = _lat(sweep_index=5)
+    lib.ising_sweep(lat, 0.4, 0)  # host-only early return, no device touched
+    assert lat.sweep_index == 5
+
+
+def test_product_path_does_not_import_oracle():
+    import sys
+    import subprocess
+
+    code = ("import sys; import paper_2402_06415_amd as m; m.load_library(); "
+            "assert not any(k == 'oracle' or k.startswith('oracle.') for k in sys.modules)")
+    subprocess.check_call([sys.executable, "-c", code], cwd=ROOT)
+    for dirpath, _, files in os.walk(os.path.join(ROOT, "paper_2402_06415_amd")):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "ising_oracle" not in text, f

@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer work, so the bar is bit-exact: the spin configuration (through
+ising_to_int8) and the int64 E and M after every sweep must equal the
+oracle's under the same Philox streams and thresholds.  Cases span the
+parity workload (L = 16, int8, cold start, beta = 0.4406868, 10^4 sweeps,
+E and M every sweep), ragged and tiny lattices, every kernel variant (the
+resident single-workgroup, the persistent tile-resident, and the
+one-launch-per-half-sweep kernels), beta edge cases, and the throughput
+workload (L = 4096, one bit per spin, random start seed 7) at full size on
+sampled sweeps.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2402_06415_amd as lib  # noqa: E402
+
+BC = 0.4406868
+SITE, PLANE = oracle.MODE_SITE, oracle.MODE_PLANE
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lib.load_library()
+    yield
+    torch.cuda.synchronize()
+
+
+def _mode(layout):
+    return SITE if layout == "int8" else PLANE
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _gpu_lattice(L, layout, seed, start, flags=0, lattice_id=0):
+    lat = lib.Lattice(L, layout, seed=seed, lattice_id=lattice_id, start=start, flags=flags)
+    return lat
+
+
+def _compare_stepwise(L, layout, seed, start, beta, n, flags=0, chunk=1, lattice_id=0):
+    """Sweep GPU and oracle side by side; compare spins, E, M after each call."""
+    say(f"L={L} layout={layout} seed={seed} start={start} beta={beta} n={n} flags={flags} chunk={chunk}")
+    g = _gpu_lattice(L, layout, seed, start, flags, lattice_id)
+    s = oracle.init(L, oracle.START_COLD_UP if start == "cold" else oracle.START_RANDOM, seed,
+                    lattice_id)
+    assert (_host(g.to_int8()) == s).all(), "initial configuration differs"
+    done = 0
+    while done < n:
+        k = min(chunk, n - done)
+        E, M = g.sweep(beta, k)
+        Eo, Mo = oracle.sweep(s, _mode(layout), seed, lattice_id, done, k, beta, nthreads=8)
+        Eg, Mg = _host(E), _host(M)
+        assert (Eg == Eo).all() and (Mg == Mo).all(), f"E/M differ in sweeps {done}..{done + k}"
+        got = _host(g.to_int8())
+        if not (got == s).all():
+            bad = np.argwhere(got != s)
+            raise AssertionError(f"spins differ after sweep {done + k}: {len(bad)} sites, "
+                                 f"first {bad[:5].tolist()}")
+        done += k
+    m = _host(g.measure())
+    assert tuple(m.tolist()) == oracle.measure(s)
+    assert g.sweep_index == n
+    g.check()
+
+
+def test_parity_workload_L16_int8_every_sweep():
+    """L=16 int8, cold start, beta=0.4406868, Philox seed 1, 10^4 sweeps,
+    E and M every sweep: whole traces and final spins bit-exact."""
+    L, n, seed = 16, 10_000, 1
+    say("parity workload L=16 n=10000")
+    g = _gpu_lattice(L, "int8", seed, "cold")
+    E, M = g.sweep(BC, n)
+    s = oracle.init(L, oracle.START_COLD_UP, seed)
+    Eo, Mo = oracle.sweep(s, SITE, seed, 0, 0, n, BC)
+    assert (_host(E) == Eo).all()
+    assert (_host(M) == Mo).all()
+    assert (_host(g.to_int8()) == s).all()
+    g.check()
+
+
+def test_parity_workload_L16_spins_after_every_sweep():
+    _compare_stepwise(16, "int8", 1, "cold", BC, 300)
+
+
+@pytest.mark.parametrize("L", [4, 6, 10, 14, 64, 128])
+def test_int8_resident_kernel(L):
+    _compare_stepwise(L, "int8", 3, "random", BC, 40, chunk=7)
+
+
+@pytest.mark.parametrize("L", [4, 6, 16, 130, 256])
+def test_int8_global_halfsweep_kernel(L):
+    _compare_stepwise(L, "int8", 5, "random", BC, 12, flags=lib.FLAG_GLOBAL_HALFSWEEP, chunk=5)
+
+
+@pytest.mark.parametrize("L", [64, 128, 192, 320, 1024])
+def test_bit1_tile_kernel(L):
+    _compare_stepwise(L, "bit1", 7, "random", BC, 12, chunk=5)
+
+
+@pytest.mark.parametrize("L", [64, 192, 512])
+def test_bit1_global_halfsweep_kernel(L):
+    _compare_stepwise(L, "bit1", 9, "random", BC, 8, flags=lib.FLAG_GLOBAL_HALFSWEEP, chunk=3)
+
+
+@pytest.mark.parametrize("beta", [0.0, 1e-12, 0.3, 0.6, 3.0])
+@pytest.mark.parametrize("layout,L", [("int8", 12), ("bit1", 128)])
+def test_beta_edge_cases(layout, L, beta):
+    _compare_stepwise(L, layout, 2, "random", beta, 6, chunk=3)
+
+
+def test_seed_high_word_and_lattice_id():
+    _compare_stepwise(16, "int8", (123 << 32) | 77, "random", BC, 5, lattice_id=9)
+    _compare_stepwise(128, "bit1", (5 << 32) | 3, "random", BC, 5, lattice_id=4)
+
+
+@pytest.mark.parametrize("layout,L", [("int8", 16), ("int8", 200), ("bit1", 256)])
+def test_measure_and_roundtrip_on_random_states(layout, L):
+    say(f"measure/roundtrip {layout} L={L}")
+    rng = np.random.default_rng(L)
+    g = _gpu_lattice(L, layout, 1, "cold")
+    for _ in range(3):
+        s = rng.choice(np.array([-1, 1], dtype=np.int8), size=(L, L))
+        g.from_int8(torch.from_numpy(s))
+        assert (_host(g.to_int8()) == s).all()
+        assert tuple(_host(g.measure()).tolist()) == oracle.measure(s)
+
+
+@pytest.mark.parametrize("layout,L", [("int8", 16), ("bit1", 128)])
+def test_z2_and_split_invariance(layout, L):
+    say(f"z2/split {layout} L={L}")
+    a = _gpu_lattice(L, layout, 4, "random")
+    s0 = _host(a.to_int8())
+    b = _gpu_lattice(L, layout, 4, "cold")
+    b.from_int8(torch.from_numpy(-s0))
+    Ea, Ma = a.sweep(BC, 30)
+    Eb1, Mb1 = b.sweep(BC, 13)
+    Eb2, Mb2 = b.sweep(BC, 17)
+    assert (_host(a.to_int8()) == -_host(b.to_int8())).all()
+    assert (_host(Ea) == np.concatenate([_host(Eb1), _host(Eb2)])).all()
+    assert (_host(Ma) == -np.concatenate([_host(Mb1), _host(Mb2)])).all()
+
+
+def test_no_trace_equals_trace_run():
+    for layout, L in (("int8", 16), ("bit1", 256)):
+        say(f"record=False {layout} L={L}")
+        a = _gpu_lattice(L, layout, 6, "random")
+        b = _gpu_lattice(L, layout, 6, "random")
+        a.sweep(BC, 9, record=False)
+        b.sweep(BC, 9, record=True)
+        assert (_host(a.to_int8()) == _host(b.to_int8())).all()
+
+
+def test_throughput_workload_L4096_bit1_first_sweeps():
+    """L=4096, 1 bit/spin, random start seed 7, beta=0.4406868: the first
+    sweeps bit-exact against the oracle at full size, in the kernel the
+    benchmark times."""
+    _compare_stepwise(4096, "bit1", 7, "random", BC, 6, chunk=2)
+
+
+def test_throughput_workload_L4096_sampled_over_1000_sweeps():
+    """Full 10^3-sweep run: one call equals the split run, and sampled
+    sweeps are checked one by one against the oracle from the GPU state."""
+    L, seed, n = 4096, 7, 1000
+    say("L=4096 1000 sweeps sampled")
+    full = _gpu_lattice(L, "bit1", seed, "random")
+    Ef, Mf = full.sweep(BC, n)
+    samples = [0, 1, 250, 777, 999]
+    g = _gpu_lattice(L, "bit1", seed, "random")
+    done = 0
+    for t in samples:
+        if t > done:
+            g.sweep(BC, t - done, record=False)
+            done = t
+        before = _host(g.to_int8())
+        E, M = g.sweep(BC, 1)
+        done += 1
+        s = before.copy()
+        Eo, Mo = oracle.sweep(s, PLANE, seed, 0, t, 1, BC, nthreads=16)
+        assert (_host(g.to_int8()) == s).all(), f"sweep {t}"
+        assert _host(E)[0] == Eo[0] and _host(M)[0] == Mo[0]
+        assert _host(Ef)[t] == Eo[0] and _host(Mf)[t] == Mo[0]
+    if done < n:
+        g.sweep(BC, n - done, record=False)
+    assert (_host(g.to_int8()) == _host(full.to_int8())).all()
+    assert tuple(_host(full.measure()).tolist()) == (int(_host(Ef)[-1]), int(_host(Mf)[-1]))
+    full.check()
+    g.check()
