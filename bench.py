@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--global-halfsweep", action="store_true",
+                    help="time the one-launch-per-half-sweep kernel instead (same chain)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     return ap.parse_args()
@@ -82,7 +84,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     L, nsw = args.L, args.sweeps
-    lat = lib.Lattice(L, "bit1", seed=args.seed, start="random", device=dev)
+    flags = lib.FLAG_GLOBAL_HALFSWEEP if args.global_halfsweep else 0
+    lat = lib.Lattice(L, "bit1", seed=args.seed, start="random", device=dev, flags=flags)
     stream = torch.cuda.current_stream()
     out = torch.zeros(2, dtype=torch.int64, device=dev)
 
@@ -152,7 +155,7 @@ def main():
             "unit": "TOP/s",
             "frac": round(achieved_tops / VALU_PEAK_TOPS, 4),
             "traffic": None,
-            "kernel": "k_sweep_bit1_tiles",
+            "kernel": "k_halfsweep_bit1" if args.global_halfsweep else "k_sweep_bit1_tiles",
             "kernel_ms": round(sweep_ms, 4),
             "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops per launch",
         },

@@ -152,11 +152,9 @@ size_t ising_spins_bytes(int32_t dim, int32_t L, int32_t layout) {
 size_t ising_workspace_bytes(int32_t dim, int32_t L, int32_t layout) {
     if (!valid_shape(dim, L, layout))
         return 0;
-    size_t bytes = ising::WsLayout::halo_offset();
-    if (layout == ISING_LAYOUT_BIT1) {
-        // halo rows: [tiles][2 colours][first, last][L/64 words]
-        bytes += (size_t)ising::WsLayout::kMaxTiles * 2 * 2 * (size_t)(L / 64) * sizeof(uint32_t);
-    }
+    size_t bytes = ising::WsLayout::kHalo;
+    if (layout == ISING_LAYOUT_BIT1)
+        bytes += ising::WsLayout::halo_bytes(L);
     return (bytes + 255) & ~(size_t)255;
 }
 
@@ -190,8 +188,8 @@ int ising_init(ising_lattice* lat, int32_t start, void* hip_stream) {
     if (start != ISING_START_COLD_UP && start != ISING_START_RANDOM)
         return set_error(ISING_E_INVALID, "unknown start %d", start);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    // clear the accumulators and the device error word (first 256 bytes)
-    HIP_TRY(ising::launch_fill_i64(ws_acc(lat), 32, 0, st), "fill");
+    // clear the accumulators, the device error word and the draw counters
+    HIP_TRY(ising::launch_fill_i64(ws_acc(lat), ising::WsLayout::kClearBytes / 8, 0, st), "fill");
     if (lat->layout == ISING_LAYOUT_INT8)
         HIP_TRY(ising::launch_init_int8(reinterpret_cast<int8_t*>(lat->spins), lat->L, start,
                                         key_of(lat), lat->lattice_id, st),
@@ -336,11 +334,14 @@ int ising_rng_blocks(const ising_lattice* lat, uint64_t* blocks_host, void* hip_
     if (!blocks_host)
         return set_error(ISING_E_INVALID, "blocks_host is NULL");
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    uint64_t v = 0;
-    HIP_TRY(hipMemcpyAsync(&v, ws_blocks(lat), sizeof v, hipMemcpyDeviceToHost, st),
-            "read block counter");
+    uint64_t v[ising::WsLayout::kRngSlots] = {};
+    HIP_TRY(hipMemcpyAsync(v, ws_blocks(lat), sizeof v, hipMemcpyDeviceToHost, st),
+            "read block counters");
     HIP_TRY(hipStreamSynchronize(st), "synchronise");
-    *blocks_host = v;
+    uint64_t total = 0;
+    for (uint64_t x : v)
+        total += x;
+    *blocks_host = total;
     return ISING_OK;
 }
 

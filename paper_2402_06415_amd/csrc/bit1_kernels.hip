@@ -20,67 +20,106 @@ namespace ising {
 namespace {
 
 // Truth tables used by the bit-sliced update (a, b, c = operands 1..3).
-constexpr uint32_t T_XOR3 = tt(kA ^ kB ^ kC);              // a ^ b ^ c
+constexpr uint32_t T_XOR3 = tt(kA ^ kB ^ kC);                     // a ^ b ^ c
 constexpr uint32_t T_MAJ = tt((kA & kB) | (kA & kC) | (kB & kC));  // at least two set
-constexpr uint32_t T_OR_AND = tt(kA | (kB & kC));          // a | (b & c)
-constexpr uint32_t T_NOR3 = tt(~(kA | kB | kC));           // none set
-constexpr uint32_t T_XOR_ANDN = tt((kA ^ kB) & ~kC);       // (a ^ b) & ~c
-constexpr uint32_t T_AND_XNOR = tt(kA & ~(kB ^ kC));       // a & (b == c)
-constexpr uint32_t T_AND_ANDN = tt(kA & kB & ~kC);         // a & b & ~c
-constexpr uint32_t T_OR3 = tt(kA | kB | kC);               // a | b | c
-constexpr uint32_t T_AND = tt(kA & kB);                    // a & b (c ignored)
+constexpr uint32_t T_OR_AND = tt(kA | (kB & kC));                 // a | (b & c)
+constexpr uint32_t T_NOR3 = tt(~(kA | kB | kC));                  // none set
+constexpr uint32_t T_XOR_ANDN = tt((kA ^ kB) & ~kC);              // (a ^ b) & ~c
+constexpr uint32_t T_AND_ANDN = tt(kA & kB & ~kC);                // a & b & ~c
+constexpr uint32_t T_AND_XNOR = tt(kA & ~(kB ^ kC));              // a & (b == c)
+constexpr uint32_t T_OR2 = tt(kA | kB);                           // a | b   (c unused)
+constexpr uint32_t T_AND2 = tt(kA & kB);                          // a & b   (c unused)
+constexpr uint32_t T_ANDN2 = tt(kA & ~kB);                        // a & ~b  (c unused)
 
-// Metropolis update of one 32-spin word W of colour c (steps 2 and 3 of the
-// single-spin-flip trial, for 32 sites at once).  O, S, U, D are the aligned,
-// shifted, upper and lower neighbour words.  Returns the new word; with
-// kObs it also adds the energy and magnetisation changes of the flips.
-template <bool kObs>
-__device__ __forceinline__ uint32_t update_word(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
-                                                uint32_t D, uint32_t g, uint32_t h, Key key,
-                                                uint32_t lid, const Accept& acc, int& dE,
-                                                int& dM, unsigned long long& nblk) {
-    // anti-aligned bonds a_k; A = a0 + a1 + a2 + a3 per lane and u = 4 - 2A.
+// Bit-sliced state of one 32-spin word during its update (steps 2 and 3 of
+// the single-spin-flip trial for 32 sites at once).
+struct WordState {
+    uint32_t W;     // spins before the update (bit 1: s = -1)
+    uint32_t flip;  // lanes decided to flip so far
+    uint32_t und;   // lanes whose comparison r < T is still undecided
+    uint32_t m2;    // lanes with u = 2 (dE = 4); the other undecided lanes have u = 4
+    uint32_t sm, a3, cy;  // A = sm + a3 + 2 cy anti-aligned neighbours (for dE)
+};
+
+// Classify the lanes of word W from its aligned, shifted, upper and lower
+// neighbour words: u = s h = 4 - 2A with A the count of anti-aligned bonds.
+__device__ __forceinline__ WordState classify(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
+                                              uint32_t D, const Accept& acc) {
     const uint32_t a0 = W ^ O, a1 = W ^ S, a2 = W ^ U, a3 = W ^ D;
-    const uint32_t sm = bop3<T_XOR3>(a0, a1, a2);  // low bit of a0 + a1 + a2
-    const uint32_t cy = bop3<T_MAJ>(a0, a1, a2);   // its carry
-    const uint32_t ge2 = bop3<T_OR_AND>(cy, sm, a3);    // A >= 2: dE <= 0, flip
-    uint32_t m4 = bop3<T_NOR3>(sm, cy, a3);             // A == 0: u = 4, dE = 8
-    uint32_t m2 = bop3<T_XOR_ANDN>(sm, a3, cy);         // A == 1: u = 2, dE = 4
-    uint32_t flip = ge2;
+    WordState st;
+    st.W = W;
+    st.a3 = a3;
+    st.sm = bop3<T_XOR3>(a0, a1, a2);  // low bit of a0 + a1 + a2
+    st.cy = bop3<T_MAJ>(a0, a1, a2);   // its carry
+    st.flip = bop3<T_OR_AND>(st.cy, st.sm, a3);       // A >= 2: dE <= 0, always flips
+    uint32_t m4 = bop3<T_NOR3>(st.sm, st.cy, a3);     // A == 0: u = 4
+    uint32_t m2 = bop3<T_XOR_ANDN>(st.sm, a3, st.cy); // A == 1: u = 2
     if (acc.always2) {
-        flip = bop3<T_OR3>(flip, m2, 0u);
+        st.flip = bop3<T_OR2>(st.flip, m2, m2);
         m2 = 0;
     }
     if (acc.always4) {
-        flip = bop3<T_OR3>(flip, m4, 0u);
+        st.flip = bop3<T_OR2>(st.flip, m4, m4);
         m4 = 0;
     }
-    const uint32_t m24 = bop3<T_OR3>(m2, m4, 0u);
-    uint32_t und = m24;  // lanes whose r < T is still undecided
-    uint32_t yes = 0;
-    for (uint32_t b = 0; b < 8u && und; ++b) {
-        U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, key);
+    st.m2 = m2;
+    st.und = bop3<T_OR2>(m2, m4, m4);
+    return st;
+}
+
+// Draw Philox blocks b0 .. b1-1 (four planes each) for word group g while
+// the lane still has undecided sites, comparing r < T most-significant bit
+// first.  For plane k the lanes take bit (31 - k) of their threshold (T2
+// for u = 2 lanes, T4 for u = 4 lanes); a lane is decided at the first bit
+// where r and its threshold differ: accepted when r has 0 there (r < T),
+// rejected when r has 1.  nblk counts the blocks this lane drew.
+__device__ __forceinline__ void draw_planes(WordState& st, uint32_t b0, uint32_t b1, uint32_t g,
+                                            uint32_t h, Key key, uint32_t lid, const Accept& acc,
+                                            unsigned long long& nblk) {
+    const uint32_t m2 = st.m2;
+    const uint32_t m4 = bop3<T_ANDN2>(st.und, st.m2, st.m2);
+    const uint32_t m24 = st.und;
+    for (uint32_t b = b0; b < b1 && st.und; ++b) {
+        const U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, key);
         ++nblk;
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const uint32_t sh = 31u - (4u * b + (uint32_t)kk);
             const bool t2 = (acc.T2 >> sh) & 1u, t4 = (acc.T4 >> sh) & 1u;
-            const uint32_t tm = t2 ? (t4 ? m24 : m2) : (t4 ? m4 : 0u);  // T bit per lane
+            const uint32_t tm = t2 ? (t4 ? m24 : m2) : (t4 ? m4 : 0u);  // threshold bit per lane
             const uint32_t P = u4_get(out, kk);                          // r bit per lane
-            yes = bop3<T_OR3>(yes, bop3<T_AND_ANDN>(und, tm, P), 0u);    // r bit 0 < T bit 1
-            und = bop3<T_AND_XNOR>(und, P, tm);                          // equal bits: undecided
+            st.flip = bop3<T_OR2>(st.flip, bop3<T_AND_ANDN>(st.und, tm, P), P);
+            st.und = bop3<T_AND_XNOR>(st.und, P, tm);
         }
     }
-    flip = bop3<T_OR3>(flip, yes, 0u);  // lanes still undecided have r == T: rejected
+}
+
+// New word after all draws (lanes still undecided have r == T: rejected);
+// with kObs also the energy and magnetisation changes of the flips.
+template <bool kObs>
+__device__ __forceinline__ uint32_t finalize(const WordState& st, int& dE, int& dM) {
     if (kObs) {
+        const uint32_t f = st.flip;
+        const int nf = __popc(f);
         // dM = sum over flips of -2 s_old = 2 (#flipped down - #flipped up)
-        const int nf = __popc(flip);
-        dM += 2 * (2 * __popc(bop3<T_AND>(flip, W, 0u)) - nf);
+        dM += 2 * (2 * __popc(bop3<T_AND2>(f, st.W, st.W)) - nf);
         // dE = sum over flips of 2u = 8 - 4A;  A = sm + a3 + 2 cy
-        dE += 8 * nf - 4 * (__popc(bop3<T_AND>(flip, sm, 0u)) + __popc(bop3<T_AND>(flip, a3, 0u)) +
-                            2 * __popc(bop3<T_AND>(flip, cy, 0u)));
+        dE += 8 * nf - 4 * (__popc(bop3<T_AND2>(f, st.sm, st.sm)) +
+                            __popc(bop3<T_AND2>(f, st.a3, st.a3)) +
+                            2 * __popc(bop3<T_AND2>(f, st.cy, st.cy)));
     }
-    return W ^ flip;
+    return st.W ^ st.flip;
+}
+
+// Complete Metropolis update of one word (all 32 planes available).
+template <bool kObs>
+__device__ __forceinline__ uint32_t update_word(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
+                                                uint32_t D, uint32_t g, uint32_t h, Key key,
+                                                uint32_t lid, const Accept& acc, int& dE,
+                                                int& dM, unsigned long long& nblk) {
+    WordState st = classify(W, O, S, U, D, acc);
+    draw_planes(st, 0, 8, g, h, key, lid, acc, nblk);
+    return finalize<kObs>(st, dE, dM);
 }
 
 __device__ __forceinline__ uint32_t side_word(uint32_t O, uint32_t Oprev, uint32_t Onext, int p) {
@@ -139,13 +178,25 @@ __device__ __forceinline__ void block_add_i64(long long a, long long b, long lon
     }
 }
 
-// Adds a per-lane count into a device total (one atomic per wave).
-__device__ __forceinline__ void add_count(unsigned long long v, unsigned long long* out) {
+// Adds per-lane counts into the device total: a wave and workgroup
+// reduction, then one atomic into slot blockIdx % kRngSlots so that atomics
+// to one address stay few.  Every thread of the workgroup must reach it.
+__device__ __forceinline__ void add_count(unsigned long long v, unsigned long long* slots) {
+    __shared__ unsigned long long part[16];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0 && v)
-        atomicAdd(out, v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w)
+            t += part[w];
+        if (t)
+            atomicAdd(slots + (blockIdx.x % WsLayout::kRngSlots), t);
+    }
 }
 
 // One half-sweep over the whole lattice, one word per thread, from global
@@ -255,124 +306,179 @@ __global__ void k_from_int8_bit1(uint32_t* planes, int L, const int8_t* in) {
 //
 // Each workgroup owns `rows` consecutive full-width rows (both colours) in
 // LDS for the whole call, the GPU analogue of the paper's supercell with a
-// dedicated update block per spin group.  Per half-sweep a workgroup first
-// updates its interior rows, which depend only on its own tile; the waves
-// holding the first and last row then wait until the neighbouring tile has
-// published the facing row of the other colour from the previous half-sweep
-// (a per-tile counter released at agent scope), read that row from the
-// neighbour's halo slot, update, and publish their own row.  No grid-wide
-// barrier is used.  Waits are bounded: on time-out the device error word is
-// set and the kernel runs to completion.
+// dedicated update block per group of spins.  Per half-sweep the waves
+// holding the first and last row need the facing row of the neighbouring
+// tile, of the other colour, from the previous half-sweep; they run first,
+// at raised priority, and the interior rows, which depend only on the
+// tile itself, are updated behind them.
+//
+// Rows are handed over through halo slots of 64-bit words, each carrying
+// the 32-bit spin word and, in the high half, the number of the half-sweep
+// that produced it plus one.  A reader polls its own word until the tag is
+// the one it expects, so each hand-off involves a single memory location
+// (relaxed agent-scope atomics: no cache write-back or invalidation, no
+// grid-wide barrier).  A slot of colour c is rewritten two half-sweeps
+// later, only after its writer has read the neighbour's next row, which
+// the neighbour publishes after reading the slot.  Slots are zeroed before
+// every call, so no tag from an earlier call can match.  Waits are bounded:
+// on time-out the device error word is set and the kernel runs to
+// completion.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void wait_counter(const uint32_t* flag, uint32_t target,
-                                             uint32_t limit, uint32_t* err) {
+__device__ __forceinline__ uint32_t wait_slot(const unsigned long long* slot, uint32_t tag,
+                                              uint32_t limit, uint32_t* err) {
     uint32_t spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    unsigned long long v;
+    for (;;) {
+        v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 32) == tag)
+            break;
         if (++spins > limit) {
             atomicOr(err, 1u);
             break;
         }
         __builtin_amdgcn_s_sleep(1);
     }
+    return (uint32_t)v;
 }
 
+__device__ __forceinline__ void publish_slot(unsigned long long* slot, uint32_t tag,
+                                             uint32_t word) {
+    __hip_atomic_store(slot, ((unsigned long long)tag << 32) | word, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile geometry shared by the two tile-resident kernels.
+struct TileGeom {
+    int nw, tr, ntiles, me, up, down, y0;
+    int64_t plane;
+};
+
+__device__ __forceinline__ TileGeom tile_geom(int L, int rows) {
+    TileGeom t;
+    t.nw = L >> 6;
+    t.plane = (int64_t)L * t.nw;
+    t.tr = rows + 2;
+    t.ntiles = gridDim.x;
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
+    // contiguous band of tiles so most hand-offs stay within one XCD.
+    t.me = blockIdx.x;
+    if ((t.ntiles & 7) == 0)
+        t.me = (blockIdx.x & 7) * (t.ntiles >> 3) + (blockIdx.x >> 3);
+    t.up = (t.me == 0) ? t.ntiles - 1 : t.me - 1;
+    t.down = (t.me + 1 == t.ntiles) ? 0 : t.me + 1;
+    t.y0 = t.me * rows;
+    return t;
+}
+
+// halo[tile][colour][0 = first row, 1 = last row][nw] of (tag << 32 | word)
+__device__ __forceinline__ unsigned long long* halo_row(unsigned long long* halo, int nw, int t,
+                                                        int col, int which) {
+    return halo + (((int64_t)t * 2 + col) * 2 + which) * (int64_t)nw;
+}
+
+__device__ __forceinline__ void load_tile(uint32_t* tile, const uint32_t* planes, int L, int rows,
+                                          const TileGeom& t) {
+    for (int i = threadIdx.x; i < 2 * t.tr * t.nw; i += blockDim.x) {
+        const int col = i / (t.tr * t.nw);
+        const int rem = i - col * t.tr * t.nw;
+        const int r = rem / t.nw - 1, w = rem % t.nw;
+        int y = t.y0 + r;
+        y = (y < 0) ? y + L : (y >= L ? y - L : y);
+        tile[i] = planes[(int64_t)col * t.plane + (int64_t)y * t.nw + w];
+    }
+}
+
+__device__ __forceinline__ void store_tile(uint32_t* planes, const uint32_t* tile, int rows,
+                                           const TileGeom& t, int first_row, int row_step) {
+    for (int r = first_row; r < rows; r += row_step)
+        for (int col = 0; col < 2; ++col)
+            for (int w = (int)(threadIdx.x & 63); w < t.nw; w += 64)
+                planes[(int64_t)col * t.plane + (int64_t)(t.y0 + r) * t.nw + w] =
+                    tile[(col * t.tr + r + 1) * t.nw + w];
+}
+
+// Update row r of colour c of the tile (both neighbours of every word are
+// available): one word per lane, 64-word chunks.  Rows 0 and rows-1 read
+// the facing row of the neighbouring tile from its halo slot (after the
+// first half-sweep) and publish their own.
+template <bool kObs>
+__device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, int rows, int r,
+                                           int64_t hs, uint32_t t0, Key key, uint32_t lid,
+                                           const Accept& acc, unsigned long long* halo,
+                                           uint32_t* err, uint32_t spin_limit, int& dE, int& dM,
+                                           unsigned long long& nblk) {
+    const int c = (int)(hs & 1), o = c ^ 1;
+    const int nw = t.nw;
+    const uint32_t h = 2u * t0 + (uint32_t)hs;
+    const uint32_t tag_in = (uint32_t)hs;        // written at half-sweep hs - 1
+    const uint32_t tag_out = (uint32_t)hs + 1u;  // written now
+    uint32_t* Tc = tile + c * t.tr * nw;
+    const uint32_t* To = tile + o * t.tr * nw;
+    const bool first = (r == 0), last = (r == rows - 1);
+    const int y = t.y0 + r;
+    for (int w = (int)(threadIdx.x & 63); w < nw; w += 64) {
+        const int wm = (w == 0) ? nw - 1 : w - 1;
+        const int wp = (w + 1 == nw) ? 0 : w + 1;
+        const uint32_t* Orow = To + (r + 1) * nw;
+        const uint32_t W = Tc[(r + 1) * nw + w];
+        const uint32_t O = Orow[w];
+        const uint32_t S = side_word(O, Orow[wm], Orow[wp], (y + c) & 1);
+        const uint32_t U = (hs > 0 && first)
+                               ? wait_slot(halo_row(halo, nw, t.up, o, 1) + w, tag_in, spin_limit, err)
+                               : To[r * nw + w];
+        const uint32_t D = (hs > 0 && last)
+                               ? wait_slot(halo_row(halo, nw, t.down, o, 0) + w, tag_in, spin_limit, err)
+                               : To[(r + 2) * nw + w];
+        WordState st = classify(W, O, S, U, D, acc);
+        draw_planes(st, 0, 8, (uint32_t)((int64_t)y * nw + w), h, key, lid, acc, nblk);
+        const uint32_t nwd = finalize<kObs>(st, dE, dM);
+        Tc[(r + 1) * nw + w] = nwd;
+        if (first)
+            publish_slot(halo_row(halo, nw, t.me, c, 0) + w, tag_out, nwd);
+        if (last)
+            publish_slot(halo_row(halo, nw, t.me, c, 1) + w, tag_out, nwd);
+    }
+}
+
+// Row order within a half-sweep: the first and last rows, which the
+// neighbouring tiles wait for, come first; interior rows after them.
+__device__ __forceinline__ int row_of(int k, int rows) {
+    return (rows <= 2 || k == 0) ? k : (k == 1 ? rows - 1 : k - 1);
+}
+
+// All rows of a half-sweep complete before the next starts (one workgroup
+// barrier per half-sweep); with kObs the workgroup also sums the energy and
+// magnetisation changes of each sweep into the traces.
+template <bool kObs>
 __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
     uint32_t* planes, int L, int rows, int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
-    long long* dEtr, long long* dMtr, uint32_t* flags, uint32_t* halo, uint32_t* err,
+    long long* dEtr, long long* dMtr, unsigned long long* halo, uint32_t* err,
     unsigned long long* nblk_out, uint32_t spin_limit) {
     extern __shared__ uint32_t tile[];  // [2][rows + 2][nw]
     __shared__ long long red[2][16];
-    const int nw = L >> 6;
-    const int64_t plane = (int64_t)L * nw;
-    const int ntiles = gridDim.x;
+    const TileGeom t = tile_geom(L, rows);
     const int nwaves = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
-    // contiguous band of tiles so most halo traffic stays in one L2.
-    int me = blockIdx.x;
-    if ((ntiles & 7) == 0)
-        me = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-    const int up = (me == 0) ? ntiles - 1 : me - 1;
-    const int down = (me + 1 == ntiles) ? 0 : me + 1;
-    const int y0 = me * rows;
-    const int tr = rows + 2;
-    const uint32_t fstride = 32;  // 128 B between counters
-    const int64_t hslot = (int64_t)nw;  // one row
-    // halo[tile][colour][0 = first row, 1 = last row][nw]
-    auto halo_row = [&](int t, int col, int which) -> uint32_t* {
-        return halo + (((int64_t)t * 2 + col) * 2 + which) * hslot;
-    };
-
-    for (int i = threadIdx.x; i < 2 * tr * nw; i += blockDim.x) {
-        const int col = i / (tr * nw);
-        const int rem = i - col * tr * nw;
-        const int r = rem / nw - 1, w = rem % nw;
-        int y = y0 + r;
-        y = (y < 0) ? y + L : (y >= L ? y - L : y);
-        tile[i] = planes[(int64_t)col * plane + (int64_t)y * nw + w];
-    }
+    load_tile(tile, planes, L, rows, t);
     __syncthreads();
-
-    const int nchunks = (nw + 63) >> 6;
-    const int nitems = rows * nchunks;
     long long sE = 0, sM = 0;
     unsigned long long nblk = 0;
     for (int64_t hs = 0; hs < 2 * n; ++hs) {
-        const int c = (int)(hs & 1), o = c ^ 1;
-        const uint32_t h = 2u * t0 + (uint32_t)hs;
-        uint32_t* Tc = tile + c * tr * nw;
-        const uint32_t* To = tile + o * tr * nw;
         int dE = 0, dM = 0;
-        bool published = false;
-        for (int it = wave; it < nitems; it += nwaves) {
-            // interior rows first, then the first row, then the last row
-            int r;
-            const int chunk = it % nchunks;
-            const int k = it / nchunks;
-            if (rows <= 2)
-                r = k;
-            else
-                r = (k < rows - 2) ? k + 1 : (k == rows - 2 ? 0 : rows - 1);
-            const bool first = (r == 0), last = (r == rows - 1);
-            if (hs > 0 && first)
-                wait_counter(flags + (int64_t)up * fstride, (uint32_t)hs, spin_limit, err);
-            if (hs > 0 && last)
-                wait_counter(flags + (int64_t)down * fstride, (uint32_t)hs, spin_limit, err);
-            const int w = chunk * 64 + lane;
-            if (w < nw) {
-                const int y = y0 + r;
-                const int wm = (w == 0) ? nw - 1 : w - 1;
-                const int wp = (w + 1 == nw) ? 0 : w + 1;
-                const uint32_t* Orow = To + (r + 1) * nw;
-                const uint32_t W = Tc[(r + 1) * nw + w];
-                const uint32_t O = Orow[w];
-                const uint32_t S = side_word(O, Orow[wm], Orow[wp], (y + c) & 1);
-                uint32_t U, D;
-                if (hs > 0 && first)
-                    U = __builtin_nontemporal_load(halo_row(up, o, 1) + w);
-                else
-                    U = To[r * nw + w];
-                if (hs > 0 && last)
-                    D = __builtin_nontemporal_load(halo_row(down, o, 0) + w);
-                else
-                    D = To[(r + 2) * nw + w];
-                const uint32_t nwd = update_word<true>(W, O, S, U, D, (uint32_t)((int64_t)y * nw + w),
-                                                 h, key, lid, acc, dE, dM, nblk);
-                Tc[(r + 1) * nw + w] = nwd;
-                if (first)
-                    halo_row(me, c, 0)[w] = nwd;
-                if (last)
-                    halo_row(me, c, 1)[w] = nwd;
-            }
-            if (first || last)
-                published = true;
+        for (int k = wave; k < rows; k += nwaves) {
+            const int r = row_of(k, rows);
+            const bool edge = (r == 0) || (r == rows - 1);
+            if (edge)
+                __builtin_amdgcn_s_setprio(3);
+            update_row<kObs>(tile, t, rows, r, hs, t0, key, lid, acc, halo, err, spin_limit, dE, dM,
+                             nblk);
+            if (edge)
+                __builtin_amdgcn_s_setprio(0);
         }
-        if (published)
-            __threadfence();  // halo rows visible at agent scope before the counter
         sE += dE;
         sM += dM;
-        if (hs & 1) {
+        if (kObs && (hs & 1)) {
             long long e = wave_sum_i64(sE), m = wave_sum_i64(sM);
             if (lane == 0) {
                 red[0][wave] = e;
@@ -382,31 +488,21 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
             sM = 0;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            __hip_atomic_store(flags + (int64_t)me * fstride, (uint32_t)(hs + 1), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            if ((hs & 1) && (dEtr || dMtr)) {
-                long long e = 0, m = 0;
-                for (int v = 0; v < nwaves; ++v) {
-                    e += red[0][v];
-                    m += red[1][v];
-                }
-                const int64_t j = hs >> 1;
-                if (dEtr && e)
-                    atomicAdd(reinterpret_cast<unsigned long long*>(dEtr + j), (unsigned long long)e);
-                if (dMtr && m)
-                    atomicAdd(reinterpret_cast<unsigned long long*>(dMtr + j), (unsigned long long)m);
+        if (kObs && (hs & 1) && threadIdx.x == 0) {
+            long long e = 0, m = 0;
+            for (int v = 0; v < nwaves; ++v) {
+                e += red[0][v];
+                m += red[1][v];
             }
+            const int64_t j = hs >> 1;
+            if (dEtr && e)
+                atomicAdd(reinterpret_cast<unsigned long long*>(dEtr + j), (unsigned long long)e);
+            if (dMtr && m)
+                atomicAdd(reinterpret_cast<unsigned long long*>(dMtr + j), (unsigned long long)m);
         }
     }
     add_count(nblk, nblk_out);
-    __syncthreads();
-    for (int i = threadIdx.x; i < 2 * rows * nw; i += blockDim.x) {
-        const int col = i / (rows * nw);
-        const int rem = i - col * rows * nw;
-        const int r = rem / nw, w = rem % nw;
-        planes[(int64_t)col * plane + (int64_t)(y0 + r) * nw + w] = tile[(col * tr + r + 1) * nw + w];
-    }
+    store_tile(planes, tile, rows, t, wave, nwaves);
 }
 
 inline unsigned blocks_for(int64_t n, int threads) {
@@ -455,9 +551,14 @@ hipError_t launch_from_int8_bit1(uint32_t* planes, int L, const int8_t* in, hipS
     return hipGetLastError();
 }
 
+size_t tile_lds_bytes(int L, int rows) {
+    // tile of both colours with one halo row each side
+    return (size_t)2 * (rows + 2) * (L >> 6) * sizeof(uint32_t);
+}
+
 bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
     const int nw = L >> 6;
-    if (nw < 1)
+    if (nw < 1 || nw > 0xFFFF)
         return false;
     int maxt = device_cus < WsLayout::kMaxTiles ? device_cus : WsLayout::kMaxTiles;
     if (maxt > L)
@@ -469,8 +570,7 @@ bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
     for (int t = maxt; t >= 2; --t) {
         if (L % t)
             continue;
-        const size_t lds = (size_t)2 * (L / t + 2) * nw * sizeof(uint32_t);
-        if (lds > 64 * 1024)
+        if (tile_lds_bytes(L, L / t) > 64 * 1024)
             continue;
         if (!best)
             best = t;
@@ -483,7 +583,7 @@ bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
         return false;
     plan->ntiles = best;
     plan->rows = L / best;
-    plan->lds = (size_t)2 * (plan->rows + 2) * nw * sizeof(uint32_t);
+    plan->lds = tile_lds_bytes(L, plan->rows);
     return true;
 }
 
@@ -491,19 +591,20 @@ hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& 
                                    uint32_t t0, Key key, uint32_t lid, Accept acc, long long* dE,
                                    long long* dM, unsigned char* ws, uint32_t spin_limit,
                                    hipStream_t st) {
-    uint32_t* flags = reinterpret_cast<uint32_t*>(ws + WsLayout::kFlags);
-    uint32_t* halo = reinterpret_cast<uint32_t*>(ws + WsLayout::halo_offset());
+    unsigned long long* halo = reinterpret_cast<unsigned long long*>(ws + WsLayout::kHalo);
     uint32_t* err = reinterpret_cast<uint32_t*>(ws + WsLayout::kErr);
     unsigned long long* nblk = reinterpret_cast<unsigned long long*>(ws + WsLayout::kRngBlocks);
-    hipError_t e = launch_fill_i64(reinterpret_cast<long long*>(flags),
-                                   (int64_t)plan.ntiles * WsLayout::kFlagStride / 8, 0, st);
+    // zero every tag so that nothing left by an earlier call can match
+    hipError_t e = launch_fill_i64(reinterpret_cast<long long*>(halo),
+                                   (int64_t)plan.ntiles * 2 * 2 * (L >> 6), 0, st);
     if (e != hipSuccess)
         return e;
     int rows = plan.rows;
     void* args[] = {&planes, (void*)&L, &rows, &n, &t0, &key, &lid, &acc, &dE, &dM,
-                    &flags, &halo, &err, &nblk, &spin_limit};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_sweep_bit1_tiles),
-                                      dim3(plan.ntiles), dim3(1024), args, plan.lds, st);
+                    &halo, &err, &nblk, &spin_limit};
+    const void* kern = (dE || dM) ? reinterpret_cast<const void*>(k_sweep_bit1_tiles<true>)
+                                  : reinterpret_cast<const void*>(k_sweep_bit1_tiles<false>);
+    return hipLaunchCooperativeKernel(kern, dim3(plan.ntiles), dim3(1024), args, plan.lds, st);
 }
 
 }  // namespace ising

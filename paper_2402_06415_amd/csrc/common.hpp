@@ -55,6 +55,9 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 
 __device__ __forceinline__ U4 philox4x32_10(U4 c, Key k) {
     uint32_t k0 = k.k0, k1 = k.k1;
+    // Keep the round keys local to each call: hoisted out of the sweep
+    // loops, the twenty of them would crowd out the scalar registers.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;

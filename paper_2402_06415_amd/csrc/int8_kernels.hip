@@ -98,13 +98,25 @@ __device__ __forceinline__ void update_group(Ptr s, int L, int c, int64_t g, uin
     }
 }
 
-// Adds a per-lane count into a device total (one atomic per wave).
-__device__ __forceinline__ void add_count(unsigned long long v, unsigned long long* out) {
+// Adds a per-lane count into the device total: a workgroup reduction, then
+// one atomic into slot blockIdx % kRngSlots so that atomics to one address
+// stay few.  Must be reached by every thread of the workgroup.
+__device__ __forceinline__ void add_count(unsigned long long v, unsigned long long* slots) {
+    __shared__ unsigned long long part[16];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0 && v)
-        atomicAdd(out, v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w)
+            t += part[w];
+        if (t)
+            atomicAdd(slots + (blockIdx.x % WsLayout::kRngSlots), t);
+    }
 }
 
 // Whole-lattice-in-LDS kernel: one workgroup runs all n sweeps of a small

@@ -10,13 +10,15 @@ namespace ising {
 
 // Workspace layout (device bytes, caller-owned, 256-B aligned base).
 struct WsLayout {
-    static constexpr size_t kAcc = 0;        // int64[4]: raw E, raw M, E0, M0
-    static constexpr size_t kRngBlocks = 32; // uint64: Philox blocks drawn since init
-    static constexpr size_t kErr = 64;       // uint32 device error word
-    static constexpr size_t kFlags = 256;    // uint32 per workgroup, 128-B stride
-    static constexpr size_t kFlagStride = 128;
+    static constexpr size_t kAcc = 0;          // int64[4]: raw E, raw M, E0, M0
+    static constexpr size_t kErr = 64;         // uint32 device error word
+    static constexpr size_t kRngBlocks = 256;  // uint64[64]: Philox blocks drawn since init
+    static constexpr int kRngSlots = 64;       // workgroup b adds into slot b % 64
+    static constexpr size_t kClearBytes = 768; // cleared by init: acc, error word, counters
+    static constexpr size_t kHalo = 1024;      // uint64 halo slots of the tile sweep
     static constexpr int kMaxTiles = 256;
-    static size_t halo_offset() { return kFlags + kMaxTiles * kFlagStride; }
+    // [tiles][2 colours][first, last row][L/64 words] of (tag << 32 | word)
+    static size_t halo_bytes(int L) { return (size_t)kMaxTiles * 2 * 2 * (size_t)(L / 64) * 8; }
 };
 
 // INT8 layout ---------------------------------------------------------------

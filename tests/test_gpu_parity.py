@@ -53,9 +53,14 @@ def _gpu_lattice(L, layout, seed, start, flags=0, lattice_id=0):
     return lat
 
 
-def _compare_stepwise(L, layout, seed, start, beta, n, flags=0, chunk=1, lattice_id=0):
-    """Sweep GPU and oracle side by side; compare spins, E, M after each call."""
-    say(f"L={L} layout={layout} seed={seed} start={start} beta={beta} n={n} flags={flags} chunk={chunk}")
+def _compare_stepwise(L, layout, seed, start, beta, n, flags=0, chunk=1, lattice_id=0,
+                      record=True):
+    """Sweep GPU and oracle side by side; compare spins, E, M after each call.
+
+    record=False runs the sweeps without per-sweep observables (the kernel
+    the benchmark times) and compares a recount instead."""
+    say(f"L={L} layout={layout} seed={seed} start={start} beta={beta} n={n} flags={flags} "
+        f"chunk={chunk} record={record}")
     g = _gpu_lattice(L, layout, seed, start, flags, lattice_id)
     s = oracle.init(L, oracle.START_COLD_UP if start == "cold" else oracle.START_RANDOM, seed,
                     lattice_id)
@@ -63,10 +68,13 @@ def _compare_stepwise(L, layout, seed, start, beta, n, flags=0, chunk=1, lattice
     done = 0
     while done < n:
         k = min(chunk, n - done)
-        E, M = g.sweep(beta, k)
+        E, M = g.sweep(beta, k, record=record)
         Eo, Mo = oracle.sweep(s, _mode(layout), seed, lattice_id, done, k, beta, nthreads=8)
-        Eg, Mg = _host(E), _host(M)
-        assert (Eg == Eo).all() and (Mg == Mo).all(), f"E/M differ in sweeps {done}..{done + k}"
+        if record:
+            Eg, Mg = _host(E), _host(M)
+            assert (Eg == Eo).all() and (Mg == Mo).all(), f"E/M differ in sweeps {done}..{done + k}"
+        else:
+            assert tuple(_host(g.measure()).tolist()) == (Eo[-1], Mo[-1])
         got = _host(g.to_int8())
         if not (got == s).all():
             bad = np.argwhere(got != s)
@@ -108,9 +116,12 @@ def test_int8_global_halfsweep_kernel(L):
     _compare_stepwise(L, "int8", 5, "random", BC, 12, flags=lib.FLAG_GLOBAL_HALFSWEEP, chunk=5)
 
 
-@pytest.mark.parametrize("L", [64, 128, 192, 320, 1024])
-def test_bit1_tile_kernel(L):
-    _compare_stepwise(L, "bit1", 7, "random", BC, 12, chunk=5)
+@pytest.mark.parametrize("record", [True, False])
+@pytest.mark.parametrize("L", [64, 128, 192, 320, 1024, 2048])
+def test_bit1_tile_kernel(L, record):
+    # record=True and record=False instantiate the tile kernel with and
+    # without per-sweep observables
+    _compare_stepwise(L, "bit1", 7, "random", BC, 12, chunk=5, record=record)
 
 
 @pytest.mark.parametrize("L", [64, 192, 512])
@@ -166,11 +177,12 @@ def test_no_trace_equals_trace_run():
         assert (_host(a.to_int8()) == _host(b.to_int8())).all()
 
 
-def test_throughput_workload_L4096_bit1_first_sweeps():
+@pytest.mark.parametrize("record", [True, False])
+def test_throughput_workload_L4096_bit1_first_sweeps(record):
     """L=4096, 1 bit/spin, random start seed 7, beta=0.4406868: the first
-    sweeps bit-exact against the oracle at full size, in the kernel the
-    benchmark times."""
-    _compare_stepwise(4096, "bit1", 7, "random", BC, 6, chunk=2)
+    sweeps bit-exact against the oracle at full size, in both tile kernels
+    (record=False is the kernel the benchmark times)."""
+    _compare_stepwise(4096, "bit1", 7, "random", BC, 6, chunk=2, record=record)
 
 
 def test_throughput_workload_L4096_sampled_over_1000_sweeps():
@@ -180,6 +192,8 @@ def test_throughput_workload_L4096_sampled_over_1000_sweeps():
     say("L=4096 1000 sweeps sampled")
     full = _gpu_lattice(L, "bit1", seed, "random")
     Ef, Mf = full.sweep(BC, n)
+    bench = _gpu_lattice(L, "bit1", seed, "random")
+    bench.sweep(BC, n, record=False)  # the configuration the benchmark times
     samples = [0, 1, 250, 777, 999]
     g = _gpu_lattice(L, "bit1", seed, "random")
     done = 0
@@ -198,6 +212,8 @@ def test_throughput_workload_L4096_sampled_over_1000_sweeps():
     if done < n:
         g.sweep(BC, n - done, record=False)
     assert (_host(g.to_int8()) == _host(full.to_int8())).all()
+    assert (_host(bench.to_int8()) == _host(full.to_int8())).all()
+    bench.check()
     assert tuple(_host(full.measure()).tolist()) == (int(_host(Ef)[-1]), int(_host(Mf)[-1]))
     full.check()
     g.check()
