@@ -13,6 +13,7 @@ oracle timed on the host cores on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -44,6 +45,23 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     return ap.parse_args()
+
+
+def profiled_traffic(kernel_name: str):
+    """HBM bytes per launch of the sweep kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or
+    None when the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "sweep_bit1_L4096_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("paper_2402_06415_amd/csrc/bit1_kernels.hip", "paper_2402_06415_amd/csrc/common.hpp",
+              "paper_2402_06415_amd/csrc/kernels.hpp"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("kernel") != kernel_name or rec.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return rec
 
 
 def cpu_baseline(L: int, seed: int, target_s: float):
@@ -129,6 +147,9 @@ def main():
     # effective HBM roofline: 2 bits per attempt (read + write once per sweep)
     alg_bytes = attempts * 0.25
     eff_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    kernel_name = "k_halfsweep_bit1" if args.global_halfsweep else "k_sweep_bit1_tiles"
+    prof = profiled_traffic(kernel_name) if (L == 4096 and nsw == 1000) else None
+    traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None
     rec = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -154,10 +175,12 @@ def main():
             "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "TOP/s",
             "frac": round(achieved_tops / VALU_PEAK_TOPS, 4),
-            "traffic": None,
-            "kernel": "k_halfsweep_bit1" if args.global_halfsweep else "k_sweep_bit1_tiles",
+            "traffic": round(traffic) if traffic else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "kernel": kernel_name,
             "kernel_ms": round(sweep_ms, 4),
             "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops per launch",
+            "valu_issue_utilisation": round(prof["valu_utilisation"], 3) if prof else None,
         },
         "hbm_roofline": {
             "achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
