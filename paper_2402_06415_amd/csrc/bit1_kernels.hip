@@ -30,6 +30,7 @@ constexpr uint32_t T_AND_XNOR = tt(kA & ~(kB ^ kC));              // a & (b == c
 constexpr uint32_t T_OR2 = tt(kA | kB);                           // a | b   (c unused)
 constexpr uint32_t T_AND2 = tt(kA & kB);                          // a & b   (c unused)
 constexpr uint32_t T_ANDN2 = tt(kA & ~kB);                        // a & ~b  (c unused)
+constexpr uint32_t T_ORAND_OR = tt((kA & kB) | kC);                // (a & b) | c
 
 // Bit-sliced state of one 32-spin word during its update (steps 2 and 3 of
 // the single-spin-flip trial for 32 sites at once).
@@ -67,29 +68,66 @@ __device__ __forceinline__ WordState classify(uint32_t W, uint32_t O, uint32_t S
     return st;
 }
 
-// Draw Philox blocks b0 .. b1-1 (four planes each) for word group g while
-// the lane still has undecided sites, comparing r < T most-significant bit
-// first.  For plane k the lanes take bit (31 - k) of their threshold (T2
-// for u = 2 lanes, T4 for u = 4 lanes); a lane is decided at the first bit
-// where r and its threshold differ: accepted when r has 0 there (r < T),
-// rejected when r has 1.  nblk counts the blocks this lane drew.
-__device__ __forceinline__ void draw_planes(WordState& st, uint32_t b0, uint32_t b1, uint32_t g,
-                                            uint32_t h, Key key, uint32_t lid, const Accept& acc,
+// Per-thread constants of the comparison: the Philox round keys and, for
+// the first eight planes, the threshold bits as all-ones/all-zero masks
+// (t2m[k] for T2, t4m[k] for T4), both in vector registers.
+struct DrawConsts {
+    RoundKeys rk;
+    uint32_t t2m[8], t4m[8];
+};
+
+__device__ __forceinline__ DrawConsts draw_consts(Key key, const Accept& acc) {
+    DrawConsts dc;
+    dc.rk = round_keys(key);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        dc.t2m[k] = 0u - ((acc.T2 >> (31 - k)) & 1u);
+        dc.t4m[k] = 0u - ((acc.T4 >> (31 - k)) & 1u);
+        asm volatile("" : "+v"(dc.t2m[k]), "+v"(dc.t4m[k]));
+    }
+    return dc;
+}
+
+// One plane of the most-significant-bit-first comparison r < T: P holds bit
+// (31 - k) of r for the 32 lanes and tm the threshold bit of each lane (T2's
+// for u = 2 lanes, T4's for u = 4 lanes).  A lane is decided at the first
+// bit where r and its threshold differ: accepted when r has 0 there
+// (r < T), rejected when r has 1.
+__device__ __forceinline__ void compare_plane(WordState& st, uint32_t P, uint32_t tm) {
+    st.flip = bop3<T_OR2>(st.flip, bop3<T_AND_ANDN>(st.und, tm, P), P);
+    st.und = bop3<T_AND_XNOR>(st.und, P, tm);
+}
+
+// Draw the Philox blocks of word group g and compare r < T plane by plane.
+// Blocks 0 and 1 (planes 0-7) are drawn unconditionally: some lane of a
+// wave needs them almost always.  Further blocks are drawn while the lane
+// still has undecided sites.  nblk counts the blocks the lane needed (those
+// drawn while it still had an undecided site).
+__device__ __forceinline__ void draw_planes(WordState& st, uint32_t g, uint32_t h, uint32_t lid,
+                                            const Accept& acc, const DrawConsts& dc,
                                             unsigned long long& nblk) {
     const uint32_t m2 = st.m2;
     const uint32_t m4 = bop3<T_ANDN2>(st.und, st.m2, st.m2);
     const uint32_t m24 = st.und;
-    for (uint32_t b = b0; b < b1 && st.und; ++b) {
-        const U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, key);
+#pragma unroll
+    for (uint32_t b = 0; b < 2; ++b) {
+        nblk += st.und ? 1u : 0u;
+        const U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, dc.rk);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * (int)b + kk;
+            const uint32_t tm = bop3<T_ORAND_OR>(m2, dc.t2m[k], bop3<T_AND2>(m4, dc.t4m[k], m4));
+            compare_plane(st, u4_get(out, kk), tm);
+        }
+    }
+    for (uint32_t b = 2; b < 8u && st.und; ++b) {
         ++nblk;
+        const U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, dc.rk);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const uint32_t sh = 31u - (4u * b + (uint32_t)kk);
             const bool t2 = (acc.T2 >> sh) & 1u, t4 = (acc.T4 >> sh) & 1u;
-            const uint32_t tm = t2 ? (t4 ? m24 : m2) : (t4 ? m4 : 0u);  // threshold bit per lane
-            const uint32_t P = u4_get(out, kk);                          // r bit per lane
-            st.flip = bop3<T_OR2>(st.flip, bop3<T_AND_ANDN>(st.und, tm, P), P);
-            st.und = bop3<T_AND_XNOR>(st.und, P, tm);
+            compare_plane(st, u4_get(out, kk), t2 ? (t4 ? m24 : m2) : (t4 ? m4 : 0u));
         }
     }
 }
@@ -114,11 +152,11 @@ __device__ __forceinline__ uint32_t finalize(const WordState& st, int& dE, int& 
 // Complete Metropolis update of one word (all 32 planes available).
 template <bool kObs>
 __device__ __forceinline__ uint32_t update_word(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
-                                                uint32_t D, uint32_t g, uint32_t h, Key key,
-                                                uint32_t lid, const Accept& acc, int& dE,
+                                                uint32_t D, uint32_t g, uint32_t h, uint32_t lid,
+                                                const Accept& acc, const DrawConsts& dc, int& dE,
                                                 int& dM, unsigned long long& nblk) {
     WordState st = classify(W, O, S, U, D, acc);
-    draw_planes(st, 0, 8, g, h, key, lid, acc, nblk);
+    draw_planes(st, g, h, lid, acc, dc, nblk);
     return finalize<kObs>(st, dE, dM);
 }
 
@@ -226,7 +264,8 @@ __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L,
         const uint32_t S = side_word(O, Q[row + wm], Q[row + wp], p);
         const uint32_t U = Q[(int64_t)ym * nw + w];
         const uint32_t D = Q[(int64_t)yp * nw + w];
-        P[row + w] = update_word<true>(W, O, S, U, D, (uint32_t)(row + w), h, key, lid, acc, dE, dM,
+        const DrawConsts dc = draw_consts(key, acc);
+        P[row + w] = update_word<true>(W, O, S, U, D, (uint32_t)(row + w), h, lid, acc, dc, dE, dM,
                                        nblk);
     }
     add_count(nblk, nblk_out);
@@ -404,8 +443,9 @@ __device__ __forceinline__ void store_tile(uint32_t* planes, const uint32_t* til
 // first half-sweep) and publish their own.
 template <bool kObs>
 __device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, int rows, int r,
-                                           int64_t hs, uint32_t t0, Key key, uint32_t lid,
-                                           const Accept& acc, unsigned long long* halo,
+                                           int64_t hs, uint32_t t0, uint32_t lid,
+                                           const Accept& acc, const DrawConsts& dc,
+                                           unsigned long long* halo,
                                            uint32_t* err, uint32_t spin_limit, int& dE, int& dM,
                                            unsigned long long& nblk) {
     const int c = (int)(hs & 1), o = c ^ 1;
@@ -431,7 +471,7 @@ __device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, in
                                ? wait_slot(halo_row(halo, nw, t.down, o, 0) + w, tag_in, spin_limit, err)
                                : To[(r + 2) * nw + w];
         WordState st = classify(W, O, S, U, D, acc);
-        draw_planes(st, 0, 8, (uint32_t)((int64_t)y * nw + w), h, key, lid, acc, nblk);
+        draw_planes(st, (uint32_t)((int64_t)y * nw + w), h, lid, acc, dc, nblk);
         const uint32_t nwd = finalize<kObs>(st, dE, dM);
         Tc[(r + 1) * nw + w] = nwd;
         if (first)
@@ -460,6 +500,7 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
     const TileGeom t = tile_geom(L, rows);
     const int nwaves = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const DrawConsts dc = draw_consts(key, acc);
     load_tile(tile, planes, L, rows, t);
     __syncthreads();
     long long sE = 0, sM = 0;
@@ -471,7 +512,7 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
             const bool edge = (r == 0) || (r == rows - 1);
             if (edge)
                 __builtin_amdgcn_s_setprio(3);
-            update_row<kObs>(tile, t, rows, r, hs, t0, key, lid, acc, halo, err, spin_limit, dE, dM,
+            update_row<kObs>(tile, t, rows, r, hs, t0, lid, acc, dc, halo, err, spin_limit, dE, dM,
                              nblk);
             if (edge)
                 __builtin_amdgcn_s_setprio(0);
@@ -556,21 +597,26 @@ size_t tile_lds_bytes(int L, int rows) {
     return (size_t)2 * (rows + 2) * (L >> 6) * sizeof(uint32_t);
 }
 
-bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
+bool plan_bit1_tiles(int L, int device_cus, int tiles_per_cu, Bit1TilePlan* plan) {
     const int nw = L >> 6;
-    if (nw < 1 || nw > 0xFFFF)
+    if (nw < 1 || nw > 0xFFFF || tiles_per_cu < 1)
         return false;
-    int maxt = device_cus < WsLayout::kMaxTiles ? device_cus : WsLayout::kMaxTiles;
+    int maxt = device_cus * tiles_per_cu;
+    if (maxt > WsLayout::kMaxTiles)
+        maxt = WsLayout::kMaxTiles;
     if (maxt > L)
         maxt = L;
-    // Largest tile count that divides L and fits 64 KiB of LDS; a multiple of
-    // 8 (one band of tiles per XCD) is preferred when it is at least half
-    // as large.
+    // Largest tile count that divides L and whose tiles fit their share of
+    // the CU's LDS (at most 64 KiB each); a multiple of 8 (one band of tiles
+    // per XCD) is preferred when it is at least half as large.
+    const size_t lds_cap = (size_t)(160 * 1024) / (size_t)tiles_per_cu < (size_t)(64 * 1024)
+                               ? (size_t)(160 * 1024) / (size_t)tiles_per_cu
+                               : (size_t)(64 * 1024);
     int best = 0, best8 = 0;
     for (int t = maxt; t >= 2; --t) {
         if (L % t)
             continue;
-        if (tile_lds_bytes(L, L / t) > 64 * 1024)
+        if (tile_lds_bytes(L, L / t) > lds_cap)
             continue;
         if (!best)
             best = t;
@@ -583,6 +629,7 @@ bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
         return false;
     plan->ntiles = best;
     plan->rows = L / best;
+    plan->threads = 64 * (plan->rows < 16 ? plan->rows : 16);
     plan->lds = tile_lds_bytes(L, plan->rows);
     return true;
 }
@@ -604,7 +651,8 @@ hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& 
                     &halo, &err, &nblk, &spin_limit};
     const void* kern = (dE || dM) ? reinterpret_cast<const void*>(k_sweep_bit1_tiles<true>)
                                   : reinterpret_cast<const void*>(k_sweep_bit1_tiles<false>);
-    return hipLaunchCooperativeKernel(kern, dim3(plan.ntiles), dim3(1024), args, plan.lds, st);
+    return hipLaunchCooperativeKernel(kern, dim3(plan.ntiles), dim3(plan.threads), args, plan.lds,
+                                      st);
 }
 
 }  // namespace ising

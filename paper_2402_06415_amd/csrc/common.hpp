@@ -53,25 +53,47 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, kTableXor3);
 }
 
-__device__ __forceinline__ U4 philox4x32_10(U4 c, Key k) {
-    uint32_t k0 = k.k0, k1 = k.k1;
-    // Keep the round keys local to each call: hoisted out of the sweep
-    // loops, the twenty of them would crowd out the scalar registers.
-    asm volatile("" : "+s"(k0), "+s"(k1));
+// The ten round keys (k + r W), computed once per thread.  They are held in
+// vector registers on purpose: recomputing them in every call costs twenty
+// scalar instructions per block, and keeping twenty in scalar registers
+// across the sweep loops spills; as VGPR operands of v_bitop3_b32 they cost
+// nothing per call.
+struct RoundKeys {
+    uint32_t k[20];
+};
+
+__device__ __forceinline__ RoundKeys round_keys(Key key) {
+    RoundKeys rk;
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        rk.k[2 * r] = k0;
+        rk.k[2 * r + 1] = k1;
+        asm volatile("" : "+v"(rk.k[2 * r]), "+v"(rk.k[2 * r + 1]));
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    return rk;
+}
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, const RoundKeys& rk) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
         uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
         U4 n;
-        n.x = xor3((uint32_t)(p1 >> 32), c.y, k0);
+        n.x = xor3((uint32_t)(p1 >> 32), c.y, rk.k[2 * r]);
         n.y = (uint32_t)p1;
-        n.z = xor3((uint32_t)(p0 >> 32), c.w, k1);
+        n.z = xor3((uint32_t)(p0 >> 32), c.w, rk.k[2 * r + 1]);
         n.w = (uint32_t)p0;
         c = n;
-        k0 += kPhiloxW0;
-        k1 += kPhiloxW1;
     }
     return c;
+}
+
+// Convenience form for kernels that draw only a few blocks per thread.
+__device__ __forceinline__ U4 philox4x32_10(U4 c, Key key) {
+    return philox4x32_10(c, round_keys(key));
 }
 
 __device__ __forceinline__ uint32_t u4_get(const U4& v, int i) {

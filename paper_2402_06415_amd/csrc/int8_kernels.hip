@@ -51,9 +51,9 @@ __global__ void k_init_int8(int8_t* s, int64_t N, int start, Key key, uint32_t l
 // Update the four sites of group g (colour c) of lattice `s` (global or
 // LDS); returns the energy and magnetisation change of the accepted flips.
 template <typename Ptr>
-__device__ __forceinline__ void update_group(Ptr s, int L, int c, int64_t g, uint32_t h, Key key,
-                                             uint32_t lid, const Accept& acc, int& dE, int& dM,
-                                             unsigned long long& nblk) {
+__device__ __forceinline__ void update_group(Ptr s, int L, int c, int64_t g, uint32_t h,
+                                             const RoundKeys& rk, uint32_t lid, const Accept& acc,
+                                             int& dE, int& dM, unsigned long long& nblk) {
     const int halfL = L >> 1;
     const int64_t nhalf = (int64_t)L * halfL;  // sites per colour
     int u[4];
@@ -84,7 +84,7 @@ __device__ __forceinline__ void update_group(Ptr s, int L, int c, int64_t g, uin
     }
     U4 r = {0u, 0u, 0u, 0u};
     if (draw) {
-        r = philox4x32_10({(uint32_t)g, lid, h, kTagSite}, key);
+        r = philox4x32_10({(uint32_t)g, lid, h, kTagSite}, rk);
         ++nblk;
     }
 #pragma unroll
@@ -158,13 +158,14 @@ __global__ void __launch_bounds__(1024) k_sweep_int8_resident(int8_t* s_glob, in
     }
     __syncthreads();
     const int64_t groups = ((N >> 1) + 3) >> 2;  // N/2 sites per colour, 4 per group
+    const RoundKeys rk = round_keys(key);
     unsigned long long nblk = 0;
     for (int64_t j = 0; j < n; ++j) {
         int dE = 0, dM = 0;
         for (int c = 0; c < 2; ++c) {
             uint32_t h = 2u * (t0 + (uint32_t)j) + (uint32_t)c;
             for (int64_t g = tid; g < groups; g += blockDim.x)
-                update_group(sh, L, c, g, h, key, lid, acc, dE, dM, nblk);
+                update_group(sh, L, c, g, h, rk, lid, acc, dE, dM, nblk);
             __syncthreads();
         }
         dE = wave_sum_i32(dE);
@@ -225,7 +226,7 @@ __global__ void __launch_bounds__(256) k_halfsweep_int8(int8_t* s, int L, int c,
     int dE = 0, dM = 0;
     unsigned long long nblk = 0;
     if (g < groups)
-        update_group(s, L, c, g, h, key, lid, acc, dE, dM, nblk);
+        update_group(s, L, c, g, h, round_keys(key), lid, acc, dE, dM, nblk);
     add_count(nblk, nblk_out);
     if (dEo || dMo)
         block_add_i64(dE, dM, dEo, dMo);

@@ -16,7 +16,7 @@ struct WsLayout {
     static constexpr int kRngSlots = 64;       // workgroup b adds into slot b % 64
     static constexpr size_t kClearBytes = 768; // cleared by init: acc, error word, counters
     static constexpr size_t kHalo = 1024;      // uint64 halo slots of the tile sweep
-    static constexpr int kMaxTiles = 256;
+    static constexpr int kMaxTiles = 1024;
     // [tiles][2 colours][first, last row][L/64 words] of (tag << 32 | word)
     static size_t halo_bytes(int L) { return (size_t)kMaxTiles * 2 * 2 * (size_t)(L / 64) * 8; }
 };
@@ -49,9 +49,11 @@ hipError_t launch_from_int8_bit1(uint32_t* planes, int L, const int8_t* in, hipS
 struct Bit1TilePlan {
     int ntiles = 0;     // workgroups, one tile of rows each
     int rows = 0;       // rows per tile
+    int threads = 0;    // workgroup size: one wave per row, at most 16 waves
     size_t lds = 0;     // dynamic LDS bytes
 };
-bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan);
+// tiles_per_cu: how many tiles (workgroups) may share one CU.
+bool plan_bit1_tiles(int L, int device_cus, int tiles_per_cu, Bit1TilePlan* plan);
 hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& plan,
                                    int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
                                    long long* dE, long long* dM, unsigned char* ws,
