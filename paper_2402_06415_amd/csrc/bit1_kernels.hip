@@ -29,8 +29,7 @@ constexpr uint32_t T_AND_ANDN = tt(kA & kB & ~kC);                // a & b & ~c
 constexpr uint32_t T_AND_XNOR = tt(kA & ~(kB ^ kC));              // a & (b == c)
 constexpr uint32_t T_OR2 = tt(kA | kB);                           // a | b   (c unused)
 constexpr uint32_t T_AND2 = tt(kA & kB);                          // a & b   (c unused)
-constexpr uint32_t T_ANDN2 = tt(kA & ~kB);                        // a & ~b  (c unused)
-constexpr uint32_t T_ORAND_OR = tt((kA & kB) | kC);                // (a & b) | c
+constexpr uint32_t T_BITSEL = tt((kA & kB) | (~kA & kC));         // a ? b : c, bitwise
 
 // Bit-sliced state of one 32-spin word during its update (steps 2 and 3 of
 // the single-spin-flip trial for 32 sites at once).
@@ -88,9 +87,19 @@ __device__ __forceinline__ DrawConsts draw_consts(Key key, const Accept& acc) {
     return dc;
 }
 
+// Bit-select with the middle operand in a scalar register (a wave-uniform
+// value; one scalar source is within the VALU's constant-bus limit).
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t bop3_vsv(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:%4" : "=v"(r) : "v"(a), "s"(b), "v"(c), "i"(TT));
+    return r;
+}
+
 // One plane of the most-significant-bit-first comparison r < T: P holds bit
 // (31 - k) of r for the 32 lanes and tm the threshold bit of each lane (T2's
-// for u = 2 lanes, T4's for u = 4 lanes).  A lane is decided at the first
+// for u = 2 lanes, T4's for u = 4 lanes).  Lanes that are already decided
+// ignore tm, so tm = m2 ? t2 : t4 suffices.  A lane is decided at the first
 // bit where r and its threshold differ: accepted when r has 0 there
 // (r < T), rejected when r has 1.
 __device__ __forceinline__ void compare_plane(WordState& st, uint32_t P, uint32_t tm) {
@@ -107,8 +116,6 @@ __device__ __forceinline__ void draw_planes(WordState& st, uint32_t g, uint32_t 
                                             const Accept& acc, const DrawConsts& dc,
                                             unsigned long long& nblk) {
     const uint32_t m2 = st.m2;
-    const uint32_t m4 = bop3<T_ANDN2>(st.und, st.m2, st.m2);
-    const uint32_t m24 = st.und;
 #pragma unroll
     for (uint32_t b = 0; b < 2; ++b) {
         nblk += st.und ? 1u : 0u;
@@ -116,8 +123,7 @@ __device__ __forceinline__ void draw_planes(WordState& st, uint32_t g, uint32_t 
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const int k = 4 * (int)b + kk;
-            const uint32_t tm = bop3<T_ORAND_OR>(m2, dc.t2m[k], bop3<T_AND2>(m4, dc.t4m[k], m4));
-            compare_plane(st, u4_get(out, kk), tm);
+            compare_plane(st, u4_get(out, kk), bop3<T_BITSEL>(m2, dc.t2m[k], dc.t4m[k]));
         }
     }
     for (uint32_t b = 2; b < 8u && st.und; ++b) {
@@ -126,8 +132,8 @@ __device__ __forceinline__ void draw_planes(WordState& st, uint32_t g, uint32_t 
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const uint32_t sh = 31u - (4u * b + (uint32_t)kk);
-            const bool t2 = (acc.T2 >> sh) & 1u, t4 = (acc.T4 >> sh) & 1u;
-            compare_plane(st, u4_get(out, kk), t2 ? (t4 ? m24 : m2) : (t4 ? m4 : 0u));
+            const uint32_t t2m = 0u - ((acc.T2 >> sh) & 1u), t4m = 0u - ((acc.T4 >> sh) & 1u);
+            compare_plane(st, u4_get(out, kk), bop3_vsv<T_BITSEL>(m2, t2m, t4m));
         }
     }
 }
