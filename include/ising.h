@@ -159,6 +159,128 @@ ISING_API int ising_rng_blocks(const ising_lattice *lat, uint64_t *blocks_host,
  * ISING_E_STATE with a message, and clears it. */
 ISING_API int ising_check_device_error(const ising_lattice *lat, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of small lattices in one persistent launch.
+ *
+ * Many independent L x L lattices (INT8 layout, SITE draws, each with its
+ * own beta), for example a grid of temperatures, a set of replicas or the
+ * independent chains of a finite-size study.  The update rule, draws and
+ * observables are those above, applied to every lattice; lattice j of the
+ * batch draws with lattice_id = lattice_id0 + j.  One workgroup owns one
+ * lattice at a time and keeps it in LDS for all n sweeps of a call; the
+ * workgroups take lattices from a device work queue, largest L first.
+ * The sweep index t of the batch lives in device memory (in the
+ * workspace) and is advanced on the device, so that the launches of
+ * ising_batch_sweep can be captured once in a HIP graph and replayed: each
+ * replay continues the chain.  The launch shape (threads, groups_per_cu)
+ * never changes the chain, only the speed.
+ * ------------------------------------------------------------------------ */
+
+#define ISING_BATCH_MAX_L 256      /* whole lattice in LDS: L*L bytes <= 64 KiB */
+#define ISING_BATCH_MAX_COUNT 65536
+
+typedef struct ising_batch {
+    int32_t abi_version;    /* must equal ISING_ABI_VERSION                    */
+    int32_t count;          /* lattices, 1..ISING_BATCH_MAX_COUNT              */
+    uint64_t seed;          /* Philox key shared by the batch                  */
+    uint32_t lattice_id0;   /* lattice j draws with lattice_id0 + j (no wrap)  */
+    int32_t max_L;          /* >= every L of the batch; sizes the LDS of the
+                               sweep: L % 8 == 0, 8 <= max_L <= 256            */
+    int32_t threads;        /* threads per workgroup: 0 = library choice, else
+                               a multiple of 64 in 64..1024                    */
+    int32_t groups_per_cu;  /* workgroups per compute unit: 0 = library choice,
+                               else 1..16 (fewer if LDS or threads do not fit) */
+    uint64_t spins_bytes;   /* size of the spins buffer in bytes               */
+    int8_t *spins;          /* device, 256-B aligned: lattice j at byte offset
+                               offsets[j] (see ising_batch_spins_bytes),
+                               INT8 row-major +1/-1                            */
+    void *workspace;        /* device, 256-B aligned,
+                               >= ising_batch_workspace_bytes(count)           */
+} ising_batch;
+
+/* Bytes of the spins buffer for lattices of sides L_host[0..count-1] and,
+ * when offsets_host is non-NULL, the byte offset of each lattice (each a
+ * multiple of 256, in order).  Every L must be a multiple of 8 in
+ * 8..ISING_BATCH_MAX_L.  Returns 0 if count or an L is invalid. */
+ISING_API size_t ising_batch_spins_bytes(int32_t count, const int32_t *L_host,
+                                         uint64_t *offsets_host);
+
+/* Bytes of device workspace of a batch of count lattices (0 if invalid):
+ * sweep index, work queue, error word, draw counters, the per-lattice
+ * descriptor table and the queue order. */
+ISING_API size_t ising_batch_workspace_bytes(int32_t count);
+
+/* Write the per-lattice descriptors into the workspace: sides L_host[j],
+ * byte offsets as ising_batch_spins_bytes lays them out, and the
+ * acceptance thresholds of beta_host[j] (as ising_thresholds).  Does not
+ * touch the spins or the sweep index, so it may be called again between
+ * sweeps to change the temperatures.  The copy is complete when the call
+ * returns (it synchronises hip_stream); the host arrays may be freed then.
+ * Errors: invalid batch description, an L that is invalid or above max_L,
+ * a beta that is negative, NaN or infinite, spins_bytes too small ->
+ * ISING_E_INVALID, nothing written. */
+ISING_API int ising_batch_setup(const ising_batch *b, const int32_t *L_host,
+                                const double *beta_host, void *hip_stream);
+
+/* Fill every lattice (ISING_START_COLD_UP or ISING_START_RANDOM, each with
+ * its own lattice id) and set the device sweep index to 0.  Requires a
+ * prior ising_batch_setup on this workspace. */
+ISING_API int ising_batch_init(const ising_batch *b, int32_t start, void *hip_stream);
+
+/* Run n >= 0 sweeps of every lattice at its beta, from the device sweep
+ * index t, then advance t by n on the device.  Only kernel launches are
+ * enqueued (no copies, no memsets, no host reads), so the call may be
+ * captured in a HIP graph.  When moments_dev is non-NULL it is device
+ * int64[count][8] and receives, for lattice j and the states after each
+ * of the n sweeps of this call:
+ *   [0] E after the last sweep        [1] M after the last sweep
+ *   [2] sum E     [3] sum E^2         [4] sum |M|     [5] sum M^2
+ *   [6], [7] sum M^4 as an unsigned 128-bit integer (low, high 64 bits)
+ * (exact while n * E^2 < 2^63; n < 2^29 suffices for every L <= 256).
+ * These are the energy and magnetisation moments behind U = <H>/L^2, the
+ * specific heat and the Binder cumulant.
+ * Errors (host): invalid batch, n < 0 or n > 2^31 -> ISING_E_INVALID.
+ * Errors (device, reported by ising_batch_check_device_error): the
+ * workspace was not set up for this batch, a descriptor does not fit the
+ * spins buffer or max_L, or t + n > 2^31; then no lattice is changed and
+ * t is not advanced. */
+ISING_API int ising_batch_sweep(const ising_batch *b, int64_t n, int64_t *moments_dev,
+                                void *hip_stream);
+
+/* Recount E and M of every lattice from scratch into E_dev[j], M_dev[j]
+ * (device int64[count]; either may be NULL). */
+ISING_API int ising_batch_measure(const ising_batch *b, int64_t *E_dev, int64_t *M_dev,
+                                  void *hip_stream);
+
+/* Read back (synchronising hip_stream) the device sweep index. */
+ISING_API int ising_batch_sweep_index(const ising_batch *b, uint64_t *t_host,
+                                      void *hip_stream);
+
+/* Read back (synchronising hip_stream) the Philox blocks drawn by the
+ * batch sweeps since ising_batch_init.  Diagnostic only. */
+ISING_API int ising_batch_rng_blocks(const ising_batch *b, uint64_t *blocks_host,
+                                     void *hip_stream);
+
+/* Read back (synchronising hip_stream) and clear the device error word of
+ * the batch: ISING_OK if clear, else ISING_E_STATE with a message. */
+ISING_API int ising_batch_check_device_error(const ising_batch *b, void *hip_stream);
+
+/* Autotuner: time every launch shape (threads per workgroup x workgroups
+ * per CU) that fits the device, each running probe_sweeps sweeps on a copy
+ * of the spins in scratch_spins (device, >= spins_bytes, 256-B aligned),
+ * and store the fastest in b->threads and b->groups_per_cu.  The spins,
+ * the sweep index and the draw counters of the batch are not changed.
+ * Synchronises hip_stream.  The chain does not depend on the shape, so a
+ * tuned batch continues exactly as an untuned one would.  When
+ * times_ms_host is non-NULL it receives up to max_times entries of
+ * (threads, groups_per_cu, milliseconds) as three doubles each; the number
+ * of shapes timed is returned in *n_times (may be NULL).
+ * Errors: invalid batch, probe_sweeps < 1 or > 10^6, scratch invalid ->
+ * ISING_E_INVALID. */
+ISING_API int ising_batch_autotune(ising_batch *b, int8_t *scratch_spins, int64_t probe_sweeps,
+                                   double *times_ms_host, int32_t max_times, int32_t *n_times,
+                                   void *hip_stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 ISING_API const char *ising_last_error(void);
 

@@ -179,3 +179,31 @@ def sweep(s: np.ndarray, mode: int, seed: int, lattice_id: int, t0: int, n: int,
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+def moments(E_trace, M_trace) -> dict:
+    """Energy and magnetisation moments of a chain segment, as exact Python
+    integers: sums over the states after each sweep of E, E^2, |M|, M^2 and
+    M^4, plus the last E and M.  Divided by the number of sweeps (and powers
+    of L^2) they estimate U = <H>/L^2 of the Supplementary Eq. S3, the
+    specific heat and the Binder cumulant."""
+    E = [int(v) for v in E_trace]
+    M = [int(v) for v in M_trace]
+    return {
+        "E": E[-1], "M": M[-1],
+        "sum_E": sum(E), "sum_E2": sum(e * e for e in E),
+        "sum_absM": sum(abs(m) for m in M), "sum_M2": sum(m * m for m in M),
+        "sum_M4": sum(m ** 4 for m in M),
+    }
+
+
+def batch_sweep(states, betas, seed: int, lattice_id0: int, t0: int, n: int, nthreads: int = 1):
+    """A batch is a set of independent lattices: lattice j runs its own
+    per-site-draw chain with lattice id lattice_id0 + j at betas[j].  Sweeps
+    every state in place from sweep index t0 and returns the moments of
+    each lattice over these n sweeps."""
+    out = []
+    for j, s in enumerate(states):
+        E, M = sweep(s, MODE_SITE, seed, lattice_id0 + j, t0, n, betas[j], nthreads=nthreads)
+        out.append(moments(E, M))
+    return out

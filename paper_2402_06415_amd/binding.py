@@ -30,7 +30,13 @@ EXPORTED = (
     "ising_spins_bytes", "ising_workspace_bytes", "ising_abi_version", "ising_thresholds",
     "ising_init", "ising_sweep", "ising_measure", "ising_to_int8", "ising_from_int8",
     "ising_check_device_error", "ising_last_error", "ising_rng_blocks",
+    "ising_batch_spins_bytes", "ising_batch_workspace_bytes", "ising_batch_setup",
+    "ising_batch_init", "ising_batch_sweep", "ising_batch_measure", "ising_batch_sweep_index",
+    "ising_batch_rng_blocks", "ising_batch_check_device_error", "ising_batch_autotune",
 )
+BATCH_MAX_L = 256
+BATCH_MAX_COUNT = 65536
+MOMENT_FIELDS = ("E", "M", "sum_E", "sum_E2", "sum_absM", "sum_M2", "sum_M4_lo", "sum_M4_hi")
 
 
 class IsingError(RuntimeError):
@@ -49,6 +55,21 @@ class ising_lattice(ctypes.Structure):
         ("lattice_id", ctypes.c_uint32),
         ("flags", ctypes.c_uint32),
         ("sweep_index", ctypes.c_uint64),
+        ("spins", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+    ]
+
+
+class ising_batch(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("count", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("lattice_id0", ctypes.c_uint32),
+        ("max_L", ctypes.c_int32),
+        ("threads", ctypes.c_int32),
+        ("groups_per_cu", ctypes.c_int32),
+        ("spins_bytes", ctypes.c_uint64),
         ("spins", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
     ]
@@ -92,6 +113,24 @@ def load_library():
     lib.ising_check_device_error.restype = ctypes.c_int
     lib.ising_last_error.argtypes = []
     lib.ising_last_error.restype = ctypes.c_char_p
+    bat_p = P(ising_batch)
+    i32p, u64p, f64p = P(ctypes.c_int32), P(ctypes.c_uint64), P(ctypes.c_double)
+    lib.ising_batch_spins_bytes.argtypes = [ctypes.c_int32, i32p, u64p]
+    lib.ising_batch_spins_bytes.restype = ctypes.c_size_t
+    lib.ising_batch_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.ising_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.ising_batch_setup.argtypes = [bat_p, i32p, f64p, vp]
+    lib.ising_batch_init.argtypes = [bat_p, ctypes.c_int32, vp]
+    lib.ising_batch_sweep.argtypes = [bat_p, ctypes.c_int64, vp, vp]
+    lib.ising_batch_measure.argtypes = [bat_p, vp, vp, vp]
+    lib.ising_batch_sweep_index.argtypes = [bat_p, u64p, vp]
+    lib.ising_batch_rng_blocks.argtypes = [bat_p, u64p, vp]
+    lib.ising_batch_check_device_error.argtypes = [bat_p, vp]
+    lib.ising_batch_autotune.argtypes = [bat_p, vp, ctypes.c_int64, f64p, ctypes.c_int32, i32p, vp]
+    for name in ("ising_batch_setup", "ising_batch_init", "ising_batch_sweep", "ising_batch_measure",
+                 "ising_batch_sweep_index", "ising_batch_rng_blocks",
+                 "ising_batch_check_device_error", "ising_batch_autotune"):
+        getattr(lib, name).restype = ctypes.c_int
     if lib.ising_abi_version() != ABI_VERSION:
         raise RuntimeError("libising.so ABI version mismatch")
     _lib = lib
@@ -159,6 +198,77 @@ def ising_rng_blocks(lat: ising_lattice, stream: int = 0) -> int:
 
 def ising_check_device_error(lat: ising_lattice, stream: int = 0):
     _check(load_library().ising_check_device_error(ctypes.byref(lat), stream))
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def ising_batch_spins_bytes(L_host):
+    """(bytes, offsets) of the spins buffer of a batch; bytes == 0 if invalid."""
+    L, Lp = _i32(L_host)
+    off = np.zeros(max(len(L), 1), dtype=np.uint64)
+    nb = load_library().ising_batch_spins_bytes(
+        len(L), Lp, off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return int(nb), off[:len(L)]
+
+
+def ising_batch_workspace_bytes(count: int) -> int:
+    return int(load_library().ising_batch_workspace_bytes(int(count)))
+
+
+def ising_batch_setup(b: ising_batch, L_host, beta_host, stream: int = 0):
+    L, Lp = _i32(L_host)
+    be, bp = _f64(beta_host)
+    if len(L) != b.count or len(be) != b.count:
+        raise IsingError(E_INVALID, "L_host and beta_host need one entry per lattice")
+    _check(load_library().ising_batch_setup(ctypes.byref(b), Lp, bp, stream))
+
+
+def ising_batch_init(b: ising_batch, start: int, stream: int = 0):
+    _check(load_library().ising_batch_init(ctypes.byref(b), start, stream))
+
+
+def ising_batch_sweep(b: ising_batch, n: int, moments_dev: int = 0, stream: int = 0):
+    _check(load_library().ising_batch_sweep(ctypes.byref(b), int(n), moments_dev or None, stream))
+
+
+def ising_batch_measure(b: ising_batch, E_dev: int = 0, M_dev: int = 0, stream: int = 0):
+    _check(load_library().ising_batch_measure(ctypes.byref(b), E_dev or None, M_dev or None,
+                                              stream))
+
+
+def ising_batch_sweep_index(b: ising_batch, stream: int = 0) -> int:
+    v = ctypes.c_uint64(0)
+    _check(load_library().ising_batch_sweep_index(ctypes.byref(b), ctypes.byref(v), stream))
+    return int(v.value)
+
+
+def ising_batch_rng_blocks(b: ising_batch, stream: int = 0) -> int:
+    v = ctypes.c_uint64(0)
+    _check(load_library().ising_batch_rng_blocks(ctypes.byref(b), ctypes.byref(v), stream))
+    return int(v.value)
+
+
+def ising_batch_check_device_error(b: ising_batch, stream: int = 0):
+    _check(load_library().ising_batch_check_device_error(ctypes.byref(b), stream))
+
+
+def ising_batch_autotune(b: ising_batch, scratch_dev: int, probe_sweeps: int, stream: int = 0):
+    """Returns [(threads, groups_per_cu, ms), ...] of every shape timed."""
+    times = np.zeros(3 * 64, dtype=np.float64)
+    nt = ctypes.c_int32(0)
+    _check(load_library().ising_batch_autotune(
+        ctypes.byref(b), scratch_dev, int(probe_sweeps),
+        times.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 64, ctypes.byref(nt), stream))
+    t = times[:3 * nt.value].reshape(-1, 3)
+    return [(int(a), int(g), float(ms)) for a, g, ms in t]
 
 
 # ------------------------------------------------------------ torch-backed lattice
@@ -244,3 +354,86 @@ class Lattice:
 
     def rng_blocks(self) -> int:
         return ising_rng_blocks(self.c, self._stream())
+
+
+class Batch:
+    """Many small INT8 lattices (sides L_list, temperatures betas) swept in
+    one persistent launch; spins and workspace are torch tensors."""
+
+    def __init__(self, L_list, betas, seed: int = 1, lattice_id0: int = 0, start: str = "random",
+                 device=None, threads: int = 0, groups_per_cu: int = 0, init: bool = True):
+        import torch
+
+        self.device = torch.device(device or "cuda")
+        self.L = np.ascontiguousarray(L_list, dtype=np.int32)
+        self.count = len(self.L)
+        nb, self.offsets = ising_batch_spins_bytes(self.L)
+        if nb == 0 or self.count == 0:
+            raise IsingError(E_INVALID, "every L must be a multiple of 8 in 8..256")
+        nw = ising_batch_workspace_bytes(self.count)
+        self._spins_raw, self.spins = _aligned_buffer(nb, self.device)
+        self._ws_raw, self.workspace = _aligned_buffer(nw, self.device)
+        self.c = ising_batch(ABI_VERSION, self.count, seed, lattice_id0, int(self.L.max()),
+                             threads, groups_per_cu, nb, self.spins.data_ptr(),
+                             self.workspace.data_ptr())
+        self.set_beta(betas)
+        if init:
+            self.init(start)
+
+    _stream = staticmethod(Lattice._stream)
+
+    def set_beta(self, betas):
+        self.beta = np.ascontiguousarray(betas, dtype=np.float64)
+        ising_batch_setup(self.c, self.L, self.beta, self._stream())
+
+    def init(self, start: str = "random"):
+        ising_batch_init(self.c, {"cold": START_COLD_UP, "random": START_RANDOM}[start],
+                         self._stream())
+
+    def sweep(self, n: int, moments: bool = True, out=None):
+        """n sweeps of every lattice; returns the int64 [count, 8] moments
+        (fields MOMENT_FIELDS) of this call, or None."""
+        import torch
+
+        if moments and out is None:
+            out = torch.empty((self.count, 8), dtype=torch.int64, device=self.device)
+        ising_batch_sweep(self.c, n, out.data_ptr() if moments else 0, self._stream())
+        return out if moments else None
+
+    def measure(self):
+        import torch
+
+        E = torch.empty(self.count, dtype=torch.int64, device=self.device)
+        M = torch.empty(self.count, dtype=torch.int64, device=self.device)
+        ising_batch_measure(self.c, E.data_ptr(), M.data_ptr(), self._stream())
+        return E, M
+
+    def lattice(self, j: int):
+        """View of lattice j as an int8 [L, L] tensor."""
+        import torch
+
+        L, o = int(self.L[j]), int(self.offsets[j])
+        return self.spins[o:o + L * L].view(torch.int8).view(L, L)
+
+    def set_lattice(self, j: int, s):
+        import torch
+
+        self.lattice(j).copy_(s.to(device=self.device, dtype=torch.int8))
+
+    @property
+    def sweep_index(self) -> int:
+        return ising_batch_sweep_index(self.c, self._stream())
+
+    def rng_blocks(self) -> int:
+        return ising_batch_rng_blocks(self.c, self._stream())
+
+    def check(self):
+        ising_batch_check_device_error(self.c, self._stream())
+
+    def autotune(self, probe_sweeps: int = 20):
+        import torch
+
+        scratch_raw, scratch = _aligned_buffer(int(self.c.spins_bytes), self.device)
+        times = ising_batch_autotune(self.c, scratch.data_ptr(), probe_sweeps, self._stream())
+        del scratch_raw, scratch
+        return times

@@ -9,12 +9,16 @@
 #include <mutex>
 #include <string>
 
+#include "abi_common.hpp"
 #include "ising.h"
 #include "kernels.hpp"
 
-namespace {
+namespace ising {
+namespace abi {
 
+namespace {
 thread_local std::string g_last_error;
+}
 
 int set_error(int code, const char* fmt, ...) {
     char buf[512];
@@ -30,12 +34,26 @@ int hip_fail(hipError_t e, const char* what) {
     return set_error(ISING_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, what)                      \
-    do {                                         \
-        hipError_t e_ = (expr);                  \
-        if (e_ != hipSuccess)                    \
-            return hip_fail(e_, what);           \
-    } while (0)
+int device_cus() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return cus;
+}
+
+const char* last_error() { return g_last_error.c_str(); }
+
+}  // namespace abi
+}  // namespace ising
+
+namespace {
+
+using ising::abi::aligned256;
+using ising::abi::device_cus;
+using ising::abi::set_error;
 
 constexpr int kMaxL = 65536;
 
@@ -50,8 +68,6 @@ bool valid_shape(int32_t dim, int32_t L, int32_t layout) {
         return (L % 64) == 0;
     return false;
 }
-
-bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 
 int validate(const ising_lattice* lat) {
     if (!lat)
@@ -83,16 +99,6 @@ int validate(const ising_lattice* lat) {
 
 ising::Key key_of(const ising_lattice* lat) {
     return ising::Key{(uint32_t)(lat->seed & 0xFFFFFFFFu), (uint32_t)(lat->seed >> 32)};
-}
-
-int device_cus() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess)
-        return 0;
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    return cus;
 }
 
 unsigned char* ws_of(const ising_lattice* lat) {
@@ -143,7 +149,7 @@ extern "C" {
 
 int32_t ising_abi_version(void) { return ISING_ABI_VERSION; }
 
-const char* ising_last_error(void) { return g_last_error.c_str(); }
+const char* ising_last_error(void) { return ising::abi::last_error(); }
 
 size_t ising_spins_bytes(int32_t dim, int32_t L, int32_t layout) {
     if (!valid_shape(dim, L, layout))

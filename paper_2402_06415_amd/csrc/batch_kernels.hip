@@ -1,0 +1,386 @@
+// Batches of small INT8 lattices, each resident in LDS for a whole call.
+//
+// Every lattice of the batch runs the same checkerboard Metropolis chain
+// as a single INT8 lattice (Fig. 2a-c; SITE draws with the lattice's own
+// id), at its own beta.  One workgroup owns one lattice at a time: it
+// copies the lattice into LDS, runs all n sweeps there with one barrier
+// per half-sweep, reduces E and M after each sweep into the moments, and
+// writes the lattice back.  Workgroups take lattices from a device work
+// queue ordered largest first, so uneven sides balance over the CUs.
+//
+// Within a half-sweep a thread updates the four colour-c sites of an
+// 8-byte span of one row (L % 8 == 0): three 8-byte LDS reads (the row and
+// the rows above and below) plus one byte across the span's edge give all
+// sixteen neighbours, the anti-aligned neighbour counts of the four sites
+// are formed byte-parallel in one register, and the four sites share one
+// Philox4x32-10 block (they are q = 4g..4g+3 of their colour).
+#include "kernels.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr uint32_t T_XOR_AND = tt((kA ^ kB) & kC);  // (a ^ b) & c
+
+// Bytes 0, 2, 4, 6 and 1, 3, 5, 7 of the 8-byte value {hi:lo}.
+constexpr uint32_t kSelEven = 0x06040200u;
+constexpr uint32_t kSelOdd = 0x07050301u;
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+struct Header {
+    uint32_t magic, count;
+    uint64_t t, t_scratch;
+    uint32_t ok, pad0;
+    uint32_t queue, pad1;
+    uint32_t err;
+};
+
+__device__ __forceinline__ Header* header(unsigned char* ws) {
+    return reinterpret_cast<Header*>(ws);
+}
+
+// Update the four colour-c sites of the span x0..x0+7 of row y of the LDS
+// lattice.  g is their Philox group (compact indices 4g..4g+3), h = 2t+c.
+// Spins are bytes 0x01 (+1) and 0xFF (-1): two spins differ exactly when
+// bit 1 of their XOR is set.
+__device__ __forceinline__ void update_quad(int8_t* lat, int L, int y, int x0, int c, uint32_t g,
+                                            uint32_t h, const RoundKeys& rk, uint32_t lid,
+                                            const Accept& acc, uint32_t bit1, int& dE, int& dM,
+                                            unsigned long long& nblk) {
+    const int p = (y + c) & 1;  // colour-c sites sit at x0 + p + 2j
+    const int row = y * L;
+    const int rup = (y == 0 ? L - 1 : y - 1) * L;
+    const int rdn = (y + 1 == L ? 0 : y + 1) * L;
+    const uint2 R = *reinterpret_cast<const uint2*>(lat + row + x0);
+    const uint2 U = *reinterpret_cast<const uint2*>(lat + rup + x0);
+    const uint2 D = *reinterpret_cast<const uint2*>(lat + rdn + x0);
+    // the one neighbour outside the span: left of x0 (p = 0) or right of x0 + 7 (p = 1)
+    const int xe = p == 0 ? (x0 == 0 ? L - 1 : x0 - 1) : (x0 + 8 == L ? 0 : x0 + 8);
+    const uint32_t X = (uint8_t)lat[row + xe];
+    const uint32_t ev = perm(R.y, R.x, kSelEven), od = perm(R.y, R.x, kSelOdd);
+    const uint32_t sel = p ? kSelOdd : kSelEven;
+    const uint32_t S = p ? od : ev;                           // the four sites, byte j = site j
+    const uint32_t Lf = p ? ev : ((od << 8) | X);             // their left neighbours
+    const uint32_t Rt = p ? ((ev >> 8) | (X << 24)) : od;     // right neighbours
+    const uint32_t Up = perm(U.y, U.x, sel), Dn = perm(D.y, D.x, sel);
+    // byte j: twice the number of anti-aligned neighbours of site j (0..8)
+    const uint32_t a2 = bop3<T_XOR_AND>(S, Lf, bit1) + bop3<T_XOR_AND>(S, Rt, bit1) +
+                        bop3<T_XOR_AND>(S, Up, bit1) + bop3<T_XOR_AND>(S, Dn, bit1);
+    int na2[4];
+    bool need = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        na2[j] = (int)((a2 >> (8 * j)) & 0xFFu);
+        // u = s h = 4 - na: one anti-aligned bond gives u = 2, none u = 4
+        need |= (na2[j] == 2 && !acc.always2) || (na2[j] == 0 && !acc.always4);
+    }
+    U4 r = {0u, 0u, 0u, 0u};
+    if (need) {
+        r = philox4x32_10({g, lid, h, kTagSite}, rk);
+        ++nblk;
+    }
+    uint32_t F = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t rj = u4_get(r, j);
+        const bool flip = na2[j] >= 4 ||
+                          (na2[j] == 2 ? (acc.always2 || rj < acc.T2) : (acc.always4 || rj < acc.T4));
+        if (flip) {
+            F |= 0xFEu << (8 * j);  // 0x01 <-> 0xFF
+            dE += 8 - 2 * na2[j];   // dE = 2u = 2 (4 - na)
+            dM += ((S >> (8 * j)) & 0x80u) ? 2 : -2;  // -2 s_old
+        }
+    }
+    if (F) {
+        // spread the site bytes j = 0..3 back to span bytes p + 2j
+        const uint32_t Fx = ((F & 0xFFu) | ((F << 8) & 0xFF0000u)) << (8 * p);
+        const uint32_t Fy = (((F >> 16) & 0xFFu) | ((F >> 8) & 0xFF0000u)) << (8 * p);
+        *reinterpret_cast<uint2*>(lat + row + x0) = make_uint2(R.x ^ Fx, R.y ^ Fy);
+    }
+}
+
+// Sum of a per-thread value over the workgroup, valid in thread 0.  Must
+// be reached by every thread; `red` holds one slot per wave.
+__device__ __forceinline__ long long block_sum_to0(long long v, long long* red) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nwaves = (blockDim.x + 63) >> 6;
+    v = wave_sum_i64(v);
+    __syncthreads();
+    if (lane == 0)
+        red[wave] = v;
+    __syncthreads();
+    long long t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nwaves; ++w)
+            t += red[w];
+    return t;
+}
+
+// E and M of an L x L lattice (row-major bytes), summed into thread 0.
+__device__ __forceinline__ void count_em(const int8_t* s, int L, long long* red, long long& E,
+                                         long long& M) {
+    long long e = 0, m = 0;
+    const int N = L * L;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int y = i / L, x = i - y * L;
+        const int right = s[y * L + (x + 1 == L ? 0 : x + 1)];
+        const int down = s[(y + 1 == L ? 0 : y + 1) * L + x];
+        e -= s[i] * (right + down);
+        m += s[i];
+    }
+    E = block_sum_to0(e, red);
+    M = block_sum_to0(m, red);
+}
+
+__device__ __forceinline__ Accept accept_of(const BatchDesc& d) {
+    return Accept{d.T2, d.T4, d.always & 1u, (d.always >> 1) & 1u};
+}
+
+__global__ void k_batch_prepare(unsigned char* ws, int scratch_t, int count, uint64_t spins_bytes,
+                                int max_L, int64_t n, int mode) {
+    Header* hd = header(ws);
+    const BatchDesc* desc = reinterpret_cast<const BatchDesc*>(ws + BatchWs::desc_offset(count));
+    const int32_t* order = reinterpret_cast<const int32_t*>(ws + BatchWs::kOrder);
+    __shared__ uint32_t bad;
+    if (threadIdx.x == 0)
+        bad = (hd->magic == kBatchMagic && hd->count == (uint32_t)count) ? 0u : kBatchErrNotSetUp;
+    __syncthreads();
+    if (bad == 0) {
+        uint32_t mine = 0;
+        for (int j = threadIdx.x; j < count; j += blockDim.x) {
+            const BatchDesc d = desc[j];
+            const bool ok_L = d.L >= 8 && d.L <= max_L && (d.L & 7) == 0;
+            const bool ok_off = (d.off & 255u) == 0 &&
+                                d.off + (uint64_t)d.L * (uint64_t)d.L <= spins_bytes;
+            const bool ok_order = order[j] >= 0 && order[j] < count;
+            if (!(ok_L && ok_off && ok_order))
+                mine = kBatchErrDescriptor;
+        }
+        if (mine)
+            atomicOr(&bad, mine);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t e = bad;
+        if (e == 0 && mode == kPrepareSweep) {
+            const uint64_t t = scratch_t ? hd->t_scratch : hd->t;
+            if (t + (uint64_t)n > (1ull << 31))
+                e = kBatchErrSweepIndex;
+        }
+        if (e) {
+            hd->err |= e;
+            hd->ok = 0;
+        } else {
+            hd->ok = 1;
+            hd->queue = 0;
+            if (mode == kPrepareInit)
+                hd->t = 0;
+        }
+    }
+    if (mode == kPrepareInit && bad == 0) {
+        unsigned long long* slots = reinterpret_cast<unsigned long long*>(ws + BatchWs::kRngBlocks);
+        for (int i = threadIdx.x; i < 64; i += blockDim.x)
+            slots[i] = 0;
+    }
+}
+
+// One workgroup per lattice: random or cold start (same draws as a single
+// INT8 lattice with this lattice id).
+__global__ void k_batch_init(unsigned char* ws, int count, int8_t* spins, int start, Key key) {
+    if (header(ws)->ok == 0)
+        return;
+    const BatchDesc d =
+        reinterpret_cast<const BatchDesc*>(ws + BatchWs::desc_offset(count))[blockIdx.x];
+    uint32_t* s = reinterpret_cast<uint32_t*>(spins + d.off);
+    const int nw = d.L * d.L / 4;
+    const RoundKeys rk = round_keys(key);
+    for (int g = threadIdx.x; g < nw; g += blockDim.x) {
+        uint32_t word = 0x01010101u;
+        if (start != 0) {
+            const U4 o = philox4x32_10({(uint32_t)g, d.lid, 0u, kTagInit}, rk);
+            word = ((o.x >> 31) ? 0xFFu : 0x01u) | (((o.y >> 31) ? 0xFFu : 0x01u) << 8) |
+                   (((o.z >> 31) ? 0xFFu : 0x01u) << 16) | (((o.w >> 31) ? 0xFFu : 0x01u) << 24);
+        }
+        s[g] = word;
+    }
+}
+
+__global__ void k_batch_measure(unsigned char* ws, int count, const int8_t* spins, int64_t* E_out,
+                                int64_t* M_out) {
+    __shared__ long long red[16];
+    if (header(ws)->ok == 0)
+        return;
+    const BatchDesc d =
+        reinterpret_cast<const BatchDesc*>(ws + BatchWs::desc_offset(count))[blockIdx.x];
+    long long E, M;
+    count_em(spins + d.off, d.L, red, E, M);
+    if (threadIdx.x == 0) {
+        if (E_out)
+            E_out[blockIdx.x] = E;
+        if (M_out)
+            M_out[blockIdx.x] = M;
+    }
+}
+
+// Adds a per-lane count into slot blockIdx % 64 of `slots`.  Must be
+// reached by every thread of the workgroup.
+__device__ __forceinline__ void add_count(unsigned long long v, unsigned long long* slots,
+                                          long long* red) {
+    const long long t = block_sum_to0((long long)v, red);
+    if (threadIdx.x == 0 && t)
+        atomicAdd(slots + (blockIdx.x % 64), (unsigned long long)t);
+}
+
+// Persistent sweep: workgroups take lattices off the queue until it is
+// empty.  No workgroup waits on another, so any grid size is safe.
+__global__ void __launch_bounds__(1024) k_batch_sweep(unsigned char* ws, int scratch_t, int count,
+                                                      int8_t* spins, int64_t n, Key key,
+                                                      int64_t* moments) {
+    extern __shared__ uint2 lds2[];
+    int8_t* lat = reinterpret_cast<int8_t*>(lds2);
+    __shared__ int s_item;
+    __shared__ long long red[16];
+    __shared__ int redi[2][2][16];
+    Header* hd = header(ws);
+    if (hd->ok == 0)
+        return;  // uniform: every workgroup reads the same word
+    const BatchDesc* desc = reinterpret_cast<const BatchDesc*>(ws + BatchWs::desc_offset(count));
+    const int32_t* order = reinterpret_cast<const int32_t*>(ws + BatchWs::kOrder);
+    unsigned long long* slots =
+        reinterpret_cast<unsigned long long*>(ws + (scratch_t ? BatchWs::kRngScratch : BatchWs::kRngBlocks));
+    const uint32_t t0 = (uint32_t)(scratch_t ? hd->t_scratch : hd->t);
+    const RoundKeys rk = round_keys(key);
+    const uint32_t bit1 = 0x02020202u;
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nwaves = (bd + 63) >> 6;
+    unsigned long long nblk = 0;
+    for (;;) {
+        if (tid == 0)
+            s_item = (int)atomicAdd(&hd->queue, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= count)
+            break;
+        const int j = order[item];
+        const BatchDesc d = desc[j];
+        const Accept acc = accept_of(d);
+        const int L = d.L;
+        const int n8 = L * L / 8;
+        const uint2* src = reinterpret_cast<const uint2*>(spins + d.off);
+        for (int i = tid; i < n8; i += bd)
+            lds2[i] = src[i];
+        __syncthreads();
+        long long E, M;
+        count_em(lat, L, red, E, M);
+        long long sE = 0, sE2 = 0, sAM = 0, sM2 = 0;
+        unsigned long long m4lo = 0, m4hi = 0;
+        // this thread's first group (row y0, span k0) and the stride in rows and spans
+        const int gpr = L >> 3, ngroups = L * gpr;
+        const int y0 = tid / gpr, k0 = tid - y0 * gpr;
+        const int dy = bd / gpr, dk = bd - dy * gpr;
+        for (int64_t sw = 0; sw < n; ++sw) {
+            int dE = 0, dM = 0;
+            for (int c = 0; c < 2; ++c) {
+                const uint32_t h = 2u * (t0 + (uint32_t)sw) + (uint32_t)c;
+                int y = y0, k = k0;
+                for (int gi = tid; gi < ngroups; gi += bd) {
+                    update_quad(lat, L, y, 8 * k, c, (uint32_t)gi, h, rk, d.lid, acc, bit1, dE, dM,
+                                nblk);
+                    k += dk;
+                    y += dy;
+                    if (k >= gpr) {
+                        k -= gpr;
+                        ++y;
+                    }
+                }
+                if (c == 0)
+                    __syncthreads();
+            }
+            dE = wave_sum_i32(dE);
+            dM = wave_sum_i32(dM);
+            const int par = (int)(sw & 1);
+            if (lane == 0) {
+                redi[par][0][wave] = dE;
+                redi[par][1][wave] = dM;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                for (int w = 0; w < nwaves; ++w) {
+                    E += redi[par][0][w];
+                    M += redi[par][1][w];
+                }
+                sE += E;
+                sE2 += E * E;
+                sAM += M < 0 ? -M : M;
+                const unsigned long long m2 = (unsigned long long)(M * M);
+                sM2 += (long long)m2;
+                const unsigned long long lo = m2 * m2, hi = __umul64hi(m2, m2);
+                m4lo += lo;
+                m4hi += hi + (m4lo < lo ? 1u : 0u);
+            }
+        }
+        uint2* dst = reinterpret_cast<uint2*>(spins + d.off);
+        for (int i = tid; i < n8; i += bd)
+            dst[i] = lds2[i];
+        if (tid == 0 && moments) {
+            int64_t* mo = moments + (int64_t)j * 8;
+            mo[0] = E;
+            mo[1] = M;
+            mo[2] = sE;
+            mo[3] = sE2;
+            mo[4] = sAM;
+            mo[5] = sM2;
+            mo[6] = (int64_t)m4lo;
+            mo[7] = (int64_t)m4hi;
+        }
+    }
+    add_count(nblk, slots, red);
+}
+
+__global__ void k_batch_advance(unsigned char* ws, int64_t n) {
+    Header* hd = header(ws);
+    if (hd->ok)
+        hd->t += (uint64_t)n;
+}
+
+}  // namespace
+
+size_t batch_lds_bytes(int max_L) { return (size_t)max_L * (size_t)max_L; }
+
+hipError_t launch_batch_prepare(unsigned char* ws, bool scratch_t, int count, uint64_t spins_bytes,
+                                int max_L, int64_t n, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(256), 0, st, ws, scratch_t ? 1 : 0, count,
+                       spins_bytes, max_L, n, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_init(unsigned char* ws, int count, int8_t* spins, int start, Key key,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_init, dim3(count), dim3(256), 0, st, ws, count, spins, start, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(unsigned char* ws, bool scratch_t, int count, int8_t* spins,
+                              int max_L, int64_t n, Key key, int64_t* moments, int threads,
+                              int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_sweep, dim3(blocks), dim3(threads), batch_lds_bytes(max_L), st, ws,
+                       scratch_t ? 1 : 0, count, spins, n, key, moments);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(unsigned char* ws, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(1), 0, st, ws, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_measure(unsigned char* ws, int count, const int8_t* spins, int64_t* E,
+                                int64_t* M, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_measure, dim3(count), dim3(256), 0, st, ws, count, spins, E, M);
+    return hipGetLastError();
+}
+
+}  // namespace ising

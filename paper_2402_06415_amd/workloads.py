@@ -1,0 +1,24 @@
+"""Seeded synthetic inputs of the benchmark and test workloads.
+
+Recipes only: which lattice sides, temperatures, seeds and ids a workload
+uses.  Nothing here computes any part of the Monte Carlo method; both the
+HIP path and the CPU oracle take their inputs from these recipes.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BETA_C = 0.4406868  # critical coupling used by the single-lattice workloads
+
+
+def batched_workload(count: int = 1024, seed: int = 11):
+    """Many independent 2D lattices of uneven size on a grid of
+    temperatures: sides drawn uniformly from {32, 64, 128, 256} (numpy's
+    Philox generator keyed by `seed`), beta_k = 0.30 + 0.30 k / 63 for
+    k = 0..63 and lattice j at beta_{j mod 64}.  Random starts use the same
+    seed and lattice id j.  Returns (L, beta) as numpy arrays."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    L = rng.choice(np.array([32, 64, 128, 256], dtype=np.int32), size=count)
+    grid = 0.30 + 0.30 * np.arange(64, dtype=np.float64) / 63.0
+    beta = grid[np.arange(count) % 64]
+    return L.astype(np.int32), beta

@@ -142,3 +142,72 @@ def test_product_path_does_not_import_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "ising_oracle" not in text, f
+
+
+# ------------------------------------------------------------ batch API (host side only)
+def test_batch_struct_layout_matches_header():
+    assert ctypes.sizeof(binding.ising_batch) == 56
+    assert binding.ising_batch.spins_bytes.offset == 32
+    assert binding.ising_batch.spins.offset == 40
+
+
+def test_batch_spins_bytes_and_offsets():
+    nb, off = lib.ising_batch_spins_bytes([32, 8, 256, 24])
+    # each lattice starts on a 256-byte boundary
+    assert list(off) == [0, 1024, 1280, 1280 + 65536]
+    assert nb == 1280 + 65536 + 768
+    for bad in ([6], [12], [264], [0], [8, 30]):
+        assert lib.ising_batch_spins_bytes(bad)[0] == 0
+    assert lib.ising_batch_workspace_bytes(0) == 0
+    assert lib.ising_batch_workspace_bytes(65537) == 0
+    ws = lib.ising_batch_workspace_bytes(1024)
+    assert ws % 256 == 0 and ws >= 1280 + 4 * 1024 + 32 * 1024
+
+
+def _batch(**kw):
+    d = dict(abi_version=1, count=2, seed=1, lattice_id0=0, max_L=32, threads=0, groups_per_cu=0,
+             spins_bytes=4096, spins=0x10000, workspace=0x20000)
+    d.update(kw)
+    return binding.ising_batch(**d)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(abi_version=3), dict(count=0), dict(count=65537), dict(max_L=12), dict(max_L=264),
+    dict(threads=100), dict(threads=2048), dict(groups_per_cu=17), dict(spins=0),
+    dict(spins=0x10010), dict(workspace=0), dict(workspace=0x20004),
+    dict(lattice_id0=2 ** 32 - 1),
+])
+def test_invalid_batches_are_rejected_before_any_launch(kw):
+    b = _batch(**kw)
+    before = bytes(b)
+    for call in (lambda: lib.ising_batch_setup(b, [8, 8], [0.4, 0.4]),
+                 lambda: lib.ising_batch_init(b, 1), lambda: lib.ising_batch_sweep(b, 3),
+                 lambda: lib.ising_batch_measure(b, 0x3000, 0x3008)):
+        with pytest.raises(lib.IsingError) as e:
+            call()
+        assert e.value.code == binding.E_INVALID
+    assert bytes(b) == before
+
+
+@pytest.mark.parametrize("L,beta,msg", [([8, 40], [0.4, 0.4], "max_L"),
+                                        ([8, 12], [0.4, 0.4], "multiple of 8"),
+                                        ([8, 8], [0.4, float("nan")], "beta"),
+                                        ([8, 8], [-1.0, 0.4], "beta"),
+                                        ([32, 32], [0.4, 0.4], "spins_bytes")])
+def test_batch_setup_rejects_bad_lattices_before_copying(L, beta, msg):
+    b = _batch(spins_bytes=1024 + 512)
+    with pytest.raises(lib.IsingError) as e:
+        lib.ising_batch_setup(b, L, beta)
+    assert e.value.code == binding.E_INVALID
+    assert msg in lib.ising_last_error()
+
+
+def test_batch_sweep_argument_errors():
+    b = _batch()
+    for n in (-1, 2 ** 31 + 1):
+        with pytest.raises(lib.IsingError) as e:
+            lib.ising_batch_sweep(b, n)
+        assert e.value.code == binding.E_INVALID
+    lib.ising_batch_sweep(b, 0)  # host-only early return
+    with pytest.raises(lib.IsingError):
+        lib.ising_batch_init(b, 9)
