@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -44,19 +46,27 @@ def parse():
                     help="time the one-launch-per-half-sweep kernel instead (same chain)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    ap.add_argument("--workload", choices=("single", "batched"), default="single",
+                    help="single: one L=4096 bit-packed lattice (default); batched: 1024 INT8 "
+                         "lattices of sides 32..256 on a 64-point beta grid in one launch")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: keep the library's default launch shape")
+    ap.add_argument("--shape", default=None,
+                    help="batched: launch shape THREADS,GROUPS_PER_CU instead of autotuning")
     return ap.parse_args()
 
 
-def profiled_traffic(kernel_name: str):
-    """HBM bytes per launch of the sweep kernel from the committed rocprofv3
+def profiled_traffic(kernel_name: str, summary: str = "sweep_bit1_L4096",
+                     source: str = "bit1_kernels.hip"):
+    """HBM bytes per launch of a sweep kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or
     None when the kernel source has changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "sweep_bit1_L4096_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{summary}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()
-    for f in ("paper_2402_06415_amd/csrc/bit1_kernels.hip", "paper_2402_06415_amd/csrc/common.hpp",
+    for f in (f"paper_2402_06415_amd/csrc/{source}", "paper_2402_06415_amd/csrc/common.hpp",
               "paper_2402_06415_amd/csrc/kernels.hpp"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if rec.get("kernel") != kernel_name or rec.get("kernel_source_sha256") != h.hexdigest():
@@ -88,12 +98,144 @@ def cpu_baseline(L: int, seed: int, target_s: float):
     }
 
 
+def cpu_baseline_batched(L, beta, seed: int, target_s: float):
+    """The oracle on a bounded sample of the batched workload: the first
+    sweeps of the first lattices, each lattice's chain as in the batch."""
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    m = 64  # lattices in the sample: one full period of the beta grid
+    states = [oracle.init(int(L[j]), oracle.START_RANDOM, seed, j) for j in range(m)]
+    t0 = time.perf_counter()
+    oracle.batch_sweep(states, beta[:m], seed, 0, 0, 1, nthreads=threads)
+    one = time.perf_counter() - t0
+    n = max(1, min(1000, int(target_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.batch_sweep(states, beta[:m], seed, 0, 1, n, nthreads=threads)
+    dt = time.perf_counter() - t0
+    spins = int(sum(int(L[j]) ** 2 for j in range(m)))
+    return {
+        "value": spins * n / (dt * 1e9),
+        "unit": "spin-flip attempts/ns",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"lattices 0..{m - 1} of the batch ({spins} spins), sweeps 1..{n} ({dt:.1f} s), "
+                  "per-site draws, OpenMP over rows of one colour",
+    }
+
+
+def bench_batched(args):
+    import torch
+
+    import paper_2402_06415_amd as lib
+    from paper_2402_06415_amd.workloads import batched_workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    seed, nsw = 11, (args.sweeps if args.sweeps != 1000 else 10_000)
+    L, beta = batched_workload(seed=seed)
+    b = lib.Batch(L, beta, seed=seed, start="random", device=dev)
+    tune = None
+    if args.shape:
+        b.c.threads, b.c.groups_per_cu = (int(v) for v in args.shape.split(","))
+        tune = {"chosen": [int(b.c.threads), int(b.c.groups_per_cu)], "given": True}
+    elif not args.no_autotune:
+        times = b.autotune(probe_sweeps=200)
+        tune = {"chosen": [int(b.c.threads), int(b.c.groups_per_cu)],
+                "ms_per_200_sweeps": {f"{t}x{g}": round(ms, 3) for t, g, ms in times}}
+    stream = torch.cuda.current_stream()
+    mom = torch.zeros((b.count, 8), dtype=torch.int64, device=dev)
+
+    def step():
+        b.init("random")
+        b.sweep(nsw, out=mom)
+        return b.measure()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    b.check()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    sw_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        b.init("random")
+        sw_ev[k][0].record(stream)
+        b.sweep(nsw, out=mom)
+        sw_ev[k][1].record(stream)
+        b.measure()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev[0].elapsed_time(ev[1])
+    sweep_ms = sum(a.elapsed_time(c) for a, c in sw_ev) / args.steps
+    blocks = b.rng_blocks()
+    b.check()
+    spins = int((L.astype(np.int64) ** 2).sum())
+    attempts = spins * nsw
+    ms_per_step = total_ms / args.steps
+    achieved_tops = blocks * PHILOX_OPS_PER_BLOCK / (sweep_ms * 1e-3) / 1e12
+    alg_bytes = attempts * 2.0  # INT8: read and write each spin once per sweep
+    eff_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
+    prof = profiled_traffic("k_batch_sweep", "batch_int8_1024", "batch_kernels.hip") \
+        if nsw == 10_000 else None
+    traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None
+    rec = {
+        "metric": METRIC,
+        "value": round(attempts / (ms_per_step * 1e6), 3),
+        "unit": "spin-flip attempts/ns",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {
+            "workload": f"1024 independent 2D Ising lattices, sides uniform in {{32,64,128,256}} "
+                        f"(seed {seed}), 64-point beta grid in [0.30, 0.60], random starts, "
+                        f"{nsw} sweeps in one persistent launch + init + recount per step",
+            "lattices": int(b.count), "spins": spins, "sweeps_per_step": nsw, "seed": seed,
+            "layout": "int8", "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved_tops, 3),
+            "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "TOP/s",
+            "frac": round(achieved_tops / VALU_PEAK_TOPS, 4),
+            "traffic": round(traffic) if traffic else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "kernel": "k_batch_sweep",
+            "kernel_ms": round(sweep_ms, 4),
+            "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops per launch",
+            "valu_issue_utilisation": round(prof["valu_utilisation"], 3) if prof else None,
+        },
+        "hbm_roofline": {
+            "achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(eff_gbs / HBM_PEAK_GBS, 4),
+            "note": "algorithmic 2 B/attempt (INT8 read + write per sweep); lattices stay in LDS",
+        },
+        "autotune": tune,
+    }
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = 1 << 30
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline_batched(L, beta, seed, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "decomposition is a design, not a build.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
     import torch
 
     import paper_2402_06415_amd as lib

@@ -20,11 +20,16 @@ namespace ising {
 
 namespace {
 
-constexpr uint32_t T_XOR_AND = tt((kA ^ kB) & kC);  // (a ^ b) & c
+constexpr uint32_t T_XOR_AND = tt((kA ^ kB) & kC);    // (a ^ b) & c
+constexpr uint32_t T_OR_AND2 = tt((kA | kB) & kC);    // (a | b) & c
+constexpr uint32_t T_ANDN_AND = tt(kA & ~kB & kC);    // a & ~b & c
+constexpr uint32_t T_NOR_AND = tt(~(kA | kB) & kC);   // ~(a | b) & c
+constexpr uint32_t T_AND_OR = tt((kA & kB) | kC);     // (a & b) | c
 
 // Bytes 0, 2, 4, 6 and 1, 3, 5, 7 of the 8-byte value {hi:lo}.
 constexpr uint32_t kSelEven = 0x06040200u;
 constexpr uint32_t kSelOdd = 0x07050301u;
+constexpr uint32_t kOnes = 0x01010101u;
 
 __device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
     return __builtin_amdgcn_perm(hi, lo, sel);
@@ -42,63 +47,118 @@ __device__ __forceinline__ Header* header(unsigned char* ws) {
     return reinterpret_cast<Header*>(ws);
 }
 
+// Acceptance data of one lattice in the form the four-site update uses.
+// A site with u = 2 flips iff r < T2, with u = 4 iff r < T4, and T4 <= T2
+// (exp(-8 beta) <= exp(-4 beta)).  So with lvl = (r < T2) + (r < T4) a site
+// flips iff lvl >= need, where need = 1 for u = 2, 2 for u = 4 and 0 when
+// no draw is needed (u <= 0, or the class always flips).  When u = 2
+// always flips, T2 is replaced by 2^32 - 1: that keeps lvl = 2 exactly
+// when r < T4 and need(u = 2) is then 0.
+struct QuadAccept {
+    uint32_t T2, T4;  // thresholds as compared
+    uint32_t M2, M0;  // need of u = 2 (0 or 1) and of u = 4 (0 or 2), in every byte
+};
+
+__device__ __forceinline__ QuadAccept quad_accept(const BatchDesc& d) {
+    const bool a2 = d.always & 1u, a4 = (d.always >> 1) & 1u;
+    return QuadAccept{a2 ? 0xFFFFFFFFu : d.T2, d.T4, a2 ? 0u : kOnes, a4 ? 0u : 2u * kOnes};
+}
+
+// Per-thread counts from which a half-sweep's dE and dM follow:
+// dE = 8 nflip - 2 sum_a2 (dE = 2u = 8 - 4 na per flip, a2 = 2 na), and
+// dM = 2 (2 ndown - nflip) (-2 s_old per flip).
+struct QuadCounts {
+    uint32_t nflip = 0, ndown = 0, sum_a2 = 0;
+};
+
 // Update the four colour-c sites of the span x0..x0+7 of row y of the LDS
 // lattice.  g is their Philox group (compact indices 4g..4g+3), h = 2t+c.
 // Spins are bytes 0x01 (+1) and 0xFF (-1): two spins differ exactly when
-// bit 1 of their XOR is set.
-__device__ __forceinline__ void update_quad(int8_t* lat, int L, int y, int x0, int c, uint32_t g,
-                                            uint32_t h, const RoundKeys& rk, uint32_t lid,
-                                            const Accept& acc, uint32_t bit1, int& dE, int& dM,
+// bit 1 of their XOR is set, and a flip is an XOR with 0xFE.  All four
+// sites are handled byte-parallel in one register, without branches.
+__device__ __forceinline__ void update_quad(int8_t* lat, int L, int N, int y, int row, int x0,
+                                            int c, uint32_t g, uint32_t h, const RoundKeys& rk,
+                                            uint32_t lid, const QuadAccept& qa, QuadCounts& cnt,
                                             unsigned long long& nblk) {
     const int p = (y + c) & 1;  // colour-c sites sit at x0 + p + 2j
-    const int row = y * L;
-    const int rup = (y == 0 ? L - 1 : y - 1) * L;
-    const int rdn = (y + 1 == L ? 0 : y + 1) * L;
+    // row = y L; the rows above and below, periodic
+    const int rup = (row == 0 ? N : row) - L;
+    const int rdn = (row + L == N ? 0 : row + L);
     const uint2 R = *reinterpret_cast<const uint2*>(lat + row + x0);
     const uint2 U = *reinterpret_cast<const uint2*>(lat + rup + x0);
     const uint2 D = *reinterpret_cast<const uint2*>(lat + rdn + x0);
     // the one neighbour outside the span: left of x0 (p = 0) or right of x0 + 7 (p = 1)
-    const int xe = p == 0 ? (x0 == 0 ? L - 1 : x0 - 1) : (x0 + 8 == L ? 0 : x0 + 8);
-    const uint32_t X = (uint8_t)lat[row + xe];
+    const int xl = x0 == 0 ? L - 1 : x0 - 1;
+    const int xr = x0 + 8 == L ? 0 : x0 + 8;
+    const uint32_t X = (uint8_t)lat[row + (p ? xr : xl)];
     const uint32_t ev = perm(R.y, R.x, kSelEven), od = perm(R.y, R.x, kSelOdd);
     const uint32_t sel = p ? kSelOdd : kSelEven;
-    const uint32_t S = p ? od : ev;                           // the four sites, byte j = site j
-    const uint32_t Lf = p ? ev : ((od << 8) | X);             // their left neighbours
-    const uint32_t Rt = p ? ((ev >> 8) | (X << 24)) : od;     // right neighbours
+    const uint32_t S = p ? od : ev;                        // the four sites, byte j = site j
+    const uint32_t Lf = p ? ev : ((od << 8) | X);          // their left neighbours
+    const uint32_t Rt = p ? ((ev >> 8) | (X << 24)) : od;  // right neighbours
     const uint32_t Up = perm(U.y, U.x, sel), Dn = perm(D.y, D.x, sel);
-    // byte j: twice the number of anti-aligned neighbours of site j (0..8)
+    const uint32_t bit1 = 2u * kOnes;
+    // byte j: a2 = twice the number of anti-aligned neighbours of site j (0..8)
     const uint32_t a2 = bop3<T_XOR_AND>(S, Lf, bit1) + bop3<T_XOR_AND>(S, Rt, bit1) +
                         bop3<T_XOR_AND>(S, Up, bit1) + bop3<T_XOR_AND>(S, Dn, bit1);
-    int na2[4];
-    bool need = false;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        na2[j] = (int)((a2 >> (8 * j)) & 0xFFu);
-        // u = s h = 4 - na: one anti-aligned bond gives u = 2, none u = 4
-        need |= (na2[j] == 2 && !acc.always2) || (na2[j] == 0 && !acc.always4);
-    }
+    // classes per byte (bit 0): two or more anti-aligned (u <= 0), exactly
+    // one (u = 2), none (u = 4)
+    const uint32_t h1 = a2 >> 1;
+    const uint32_t ge2 = bop3<T_OR_AND2>(a2 >> 2, a2 >> 3, kOnes);
+    const uint32_t is2 = bop3<T_ANDN_AND>(h1, ge2, kOnes);
+    const uint32_t is0 = bop3<T_NOR_AND>(h1, ge2, kOnes);
+    const uint32_t need = bop3<T_AND_OR>(is0 << 1, qa.M0, is2 & qa.M2);
     U4 r = {0u, 0u, 0u, 0u};
     if (need) {
         r = philox4x32_10({g, lid, h, kTagSite}, rk);
         ++nblk;
     }
-    uint32_t F = 0;
+    uint32_t lvl = 4u * kOnes;  // 4 + lvl_j - need_j stays in 2..6: no borrow between bytes
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const uint32_t rj = u4_get(r, j);
-        const bool flip = na2[j] >= 4 ||
-                          (na2[j] == 2 ? (acc.always2 || rj < acc.T2) : (acc.always4 || rj < acc.T4));
-        if (flip) {
-            F |= 0xFEu << (8 * j);  // 0x01 <-> 0xFF
-            dE += 8 - 2 * na2[j];   // dE = 2u = 2 (4 - na)
-            dM += ((S >> (8 * j)) & 0x80u) ? 2 : -2;  // -2 s_old
-        }
+        lvl |= ((uint32_t)(rj < qa.T2) + (uint32_t)(rj < qa.T4)) << (8 * j);
     }
-    if (F) {
-        // spread the site bytes j = 0..3 back to span bytes p + 2j
-        const uint32_t Fx = ((F & 0xFFu) | ((F << 8) & 0xFF0000u)) << (8 * p);
-        const uint32_t Fy = (((F >> 16) & 0xFFu) | ((F >> 8) & 0xFF0000u)) << (8 * p);
-        *reinterpret_cast<uint2*>(lat + row + x0) = make_uint2(R.x ^ Fx, R.y ^ Fy);
+    const uint32_t fb = ((lvl - need) >> 2) & kOnes;  // bit 0 of byte j: site j flips
+    // 0xFE in flipped bytes: fb * 254 as a shift and a subtraction (the
+    // empty asm keeps the compiler from forming a quarter-rate multiply)
+    uint32_t fb8 = fb << 8;
+    asm volatile("" : "+v"(fb8));
+    const uint32_t F = fb8 - (fb << 1);
+    cnt.nflip += __popc(fb);
+    cnt.ndown += __popc(fb & (S >> 7));
+    cnt.sum_a2 = __builtin_amdgcn_udot4(a2, fb, cnt.sum_a2, false);  // sum of a2_j over flips
+    // spread F's bytes 0..3 to span bytes p, p + 2, p + 4, p + 6 (zeros from lo)
+    const uint32_t Fx = perm(F, 0u, p ? 0x05000400u : 0x00050004u);
+    const uint32_t Fy = perm(F, 0u, p ? 0x07000600u : 0x00070006u);
+    *reinterpret_cast<uint2*>(lat + row + x0) = make_uint2(R.x ^ Fx, R.y ^ Fy);
+}
+
+// One half-sweep (colour c) of an LDS lattice of side L (L % 8 == 0) by
+// the whole workgroup.  Group gi (Philox counter word g = gi) is the span
+// of columns 8k..8k+7 of row y, gi = y L/8 + k.
+// Thread tid takes gi = tid, tid + blockDim, ...; its row and span advance
+// incrementally, without divisions or 32-bit multiplies.
+__device__ __forceinline__ void halfsweep_lds(int8_t* lat, int L, int c, uint32_t h,
+                                              const RoundKeys& rk, uint32_t lid,
+                                              const QuadAccept& qa, QuadCounts& cnt,
+                                              unsigned long long& nblk) {
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int gpr = L >> 3, ngroups = L * gpr, N = L * L;
+    const int y0 = tid / gpr, k0 = tid - y0 * gpr;
+    const int dy = bd / gpr, dk = bd - dy * gpr;
+    const int dyL = dy * L;
+    int y = y0, k = k0, row = y0 * L;
+    for (int gi = tid; gi < ngroups; gi += bd) {
+        update_quad(lat, L, N, y, row, 8 * k, c, (uint32_t)gi, h, rk, lid, qa, cnt, nblk);
+        k += dk;
+        y += dy;
+        row += dyL;
+        if (k >= gpr) {
+            k -= gpr;
+            ++y;
+            row += L;
+        }
     }
 }
 
@@ -133,10 +193,6 @@ __device__ __forceinline__ void count_em(const int8_t* s, int L, long long* red,
     }
     E = block_sum_to0(e, red);
     M = block_sum_to0(m, red);
-}
-
-__device__ __forceinline__ Accept accept_of(const BatchDesc& d) {
-    return Accept{d.T2, d.T4, d.always & 1u, (d.always >> 1) & 1u};
 }
 
 __global__ void k_batch_prepare(unsigned char* ws, int scratch_t, int count, uint64_t spins_bytes,
@@ -253,7 +309,6 @@ __global__ void __launch_bounds__(1024) k_batch_sweep(unsigned char* ws, int scr
         reinterpret_cast<unsigned long long*>(ws + (scratch_t ? BatchWs::kRngScratch : BatchWs::kRngBlocks));
     const uint32_t t0 = (uint32_t)(scratch_t ? hd->t_scratch : hd->t);
     const RoundKeys rk = round_keys(key);
-    const uint32_t bit1 = 0x02020202u;
     const int tid = threadIdx.x, bd = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = (bd + 63) >> 6;
     unsigned long long nblk = 0;
@@ -267,7 +322,7 @@ __global__ void __launch_bounds__(1024) k_batch_sweep(unsigned char* ws, int scr
             break;
         const int j = order[item];
         const BatchDesc d = desc[j];
-        const Accept acc = accept_of(d);
+        const QuadAccept qa = quad_accept(d);
         const int L = d.L;
         const int n8 = L * L / 8;
         const uint2* src = reinterpret_cast<const uint2*>(spins + d.off);
@@ -278,30 +333,16 @@ __global__ void __launch_bounds__(1024) k_batch_sweep(unsigned char* ws, int scr
         count_em(lat, L, red, E, M);
         long long sE = 0, sE2 = 0, sAM = 0, sM2 = 0;
         unsigned long long m4lo = 0, m4hi = 0;
-        // this thread's first group (row y0, span k0) and the stride in rows and spans
-        const int gpr = L >> 3, ngroups = L * gpr;
-        const int y0 = tid / gpr, k0 = tid - y0 * gpr;
-        const int dy = bd / gpr, dk = bd - dy * gpr;
         for (int64_t sw = 0; sw < n; ++sw) {
-            int dE = 0, dM = 0;
+            QuadCounts cnt;
             for (int c = 0; c < 2; ++c) {
                 const uint32_t h = 2u * (t0 + (uint32_t)sw) + (uint32_t)c;
-                int y = y0, k = k0;
-                for (int gi = tid; gi < ngroups; gi += bd) {
-                    update_quad(lat, L, y, 8 * k, c, (uint32_t)gi, h, rk, d.lid, acc, bit1, dE, dM,
-                                nblk);
-                    k += dk;
-                    y += dy;
-                    if (k >= gpr) {
-                        k -= gpr;
-                        ++y;
-                    }
-                }
+                halfsweep_lds(lat, L, c, h, rk, d.lid, qa, cnt, nblk);
                 if (c == 0)
                     __syncthreads();
             }
-            dE = wave_sum_i32(dE);
-            dM = wave_sum_i32(dM);
+            const int dE = wave_sum_i32(8 * (int)cnt.nflip - 2 * (int)cnt.sum_a2);
+            const int dM = wave_sum_i32(2 * (2 * (int)cnt.ndown - (int)cnt.nflip));
             const int par = (int)(sw & 1);
             if (lane == 0) {
                 redi[par][0][wave] = dE;
