@@ -46,9 +46,13 @@ def parse():
                     help="time the one-launch-per-half-sweep kernel instead (same chain)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("single", "batched"), default="single",
+    ap.add_argument("--workload", choices=("single", "batched", "learned"), default="single",
                     help="single: one L=4096 bit-packed lattice (default); batched: 1024 INT8 "
-                         "lattices of sides 32..256 on a 64-point beta grid in one launch")
+                         "lattices of sides 32..256 on a 64-point beta grid in one launch; "
+                         "learned: independent samples/s of learned-proposal vs plain chains "
+                         "at L=32")
+    ap.add_argument("--beta", type=float, default=BETA, help="learned: inverse temperature")
+    ap.add_argument("--epochs", type=int, default=3, help="learned: training epochs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched: keep the library's default launch shape")
     ap.add_argument("--shape", default=None,
@@ -228,6 +232,126 @@ def bench_batched(args):
     print(json.dumps(rec), flush=True)
 
 
+# multiply-adds per site of one training step of the proposal network:
+# forward 64 + 2*1280 + 80, input gradients 80 + 2*1280, weight gradients 64 + 2*1280 + 80
+NN_MAC_PER_SITE_TRAIN = (64 + 2 * 1280 + 80) + (80 + 2 * 1280) + (64 + 2 * 1280 + 80)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def bench_learned(args):
+    """tau_int-normalised independent samples per second of the chain with
+    learned whole-lattice proposals against plain checkerboard sweeps."""
+    import torch
+
+    import paper_2402_06415_amd as lib
+    from paper_2402_06415_amd.analysis import binned_mean, tau_int
+    from paper_2402_06415_amd.learned import LearnedChains, plain_configurations, train
+    from paper_2402_06415_amd.workloads import learned_workload, nn_initial_params
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = learned_workload()
+    L, chains, k = wl["L"], wl["chains"], wl["sweeps_per_proposal"]
+    beta = args.beta
+    N = L * L
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        out = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return out, a.elapsed_time(b)
+
+    snaps = wl["train_configs"] // chains
+    data, gen_ms = timed(lambda: plain_configurations(L, beta, chains, 2000, snaps, 10, seed=101))
+    batch = 1024
+    net = lib.Net(L, max(batch, chains), params=nn_initial_params(7))
+    steps = args.epochs * (data.shape[0] // batch)
+    losses, train_ms = timed(lambda: train(net, data, args.epochs, batch, 2e-3, seed=5))
+    del data
+
+    # plain chains, equilibrated
+    T = 20000
+    plain = lib.Batch([L] * chains, [beta] * chains, seed=201, start="random", device=dev)
+    plain.sweep(2000, moments=False)
+    tr = torch.empty((T, chains, 2), dtype=torch.int64, device=dev)
+    _, plain_ms = timed(lambda: plain.sweep(T, moments=False, trace=tr))
+    trp = tr.cpu().numpy()
+    del tr
+    # learned chains
+    lc = LearnedChains(net, L, [beta] * chains, seed=301, sweeps_per_proposal=k)
+    for _ in range(100):
+        lc.cycle()
+    cycles = 1000
+    tr = torch.empty((cycles * k, chains, 2), dtype=torch.int64, device=dev)
+    lc.n_accepted.zero_()
+
+    def run_cycles():
+        for c in range(cycles):
+            lc.cycle(trace=tr[c * k:(c + 1) * k])
+
+    _, learn_ms = timed(run_cycles)
+    trl = tr.cpu().numpy()
+    rate = float(lc.n_accepted.sum().cpu()) / (cycles * chains)
+    lc.batch.check()
+
+    def stats(trace, ms, sweeps):
+        E = trace[:, :, 0] / N
+        am = np.abs(trace[:, :, 1]) / N
+        t_m, dt_m, _ = tau_int(am)
+        t_e, dt_e, _ = tau_int(E)
+        sweeps_per_s = sweeps / (ms * 1e-3)
+        return {
+            "tau_int_absm_sweeps": round(t_m, 2), "tau_int_absm_err": round(dt_m, 2),
+            "tau_int_E_sweeps": round(t_e, 2), "tau_int_E_err": round(dt_e, 2),
+            "ms_per_sweep_all_chains": round(ms / sweeps, 5),
+            "samples_per_s_absm": round(chains * sweeps_per_s / (2 * t_m), 1),
+            "samples_per_s_E": round(chains * sweeps_per_s / (2 * t_e), 1),
+            "e_mean": binned_mean(E), "absm_mean": binned_mean(am),
+        }
+
+    sp = stats(trp, plain_ms, T)
+    sl = stats(trl, learn_ms, cycles * k)
+    train_tflops = steps * batch * N * NN_MAC_PER_SITE_TRAIN * 2 / (train_ms * 1e-3) / 1e12
+    rec = {
+        "metric": METRIC,
+        "value": sl["samples_per_s_absm"],
+        "unit": "independent samples/s (|m|, tau_int-normalised)",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(learn_ms / cycles, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 weights / fp32 accumulate; u32 sweeps", "data": "synthetic",
+        "config": {
+            "workload": f"2D Ising L={L}, beta={beta}, {chains} chains; masked-conv autoregressive "
+                        f"proposal (4 layers, 16 channels, 3x3) trained on "
+                        f"{snaps * chains} plain-sampler configurations; one Z2-symmetrised "
+                        f"whole-lattice proposal per {k} sweeps",
+            "L": L, "beta": beta, "chains": chains, "train_configs": snaps * chains,
+            "train_steps": steps, "parallelism": "single GPU",
+        },
+        "learned": sl, "plain": sp,
+        "learned_over_plain": {
+            "absm": round(sl["samples_per_s_absm"] / sp["samples_per_s_absm"], 4),
+            "E": round(sl["samples_per_s_E"] / sp["samples_per_s_E"], 4),
+        },
+        "acceptance_rate": round(rate, 5),
+        "training": {"ms": round(train_ms, 1), "steps": steps, "batch": batch,
+                     "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                     "data_generation_ms": round(gen_ms, 1)},
+        "roofline": {
+            "bound": "fp32-vector",
+            "achieved": round(train_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(train_tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "training step (forward + backward + Adam kernels)",
+            "work": f"{NN_MAC_PER_SITE_TRAIN} multiply-adds per site per configuration",
+        },
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -236,6 +360,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     import torch
 
     import paper_2402_06415_amd as lib

@@ -237,6 +237,9 @@ ISING_API int ising_batch_init(const ising_batch *b, int32_t start, void *hip_st
  *   [2] sum E     [3] sum E^2         [4] sum |M|     [5] sum M^2
  *   [6], [7] sum M^4 as an unsigned 128-bit integer (low, high 64 bits)
  * (exact while n * E^2 < 2^63; n < 2^29 suffices for every L <= 256).
+ * When trace_dev is non-NULL it is device int64[n][count][2] and receives
+ * E and M of every lattice after every sweep of this call (the time series
+ * behind autocorrelation times).
  * These are the energy and magnetisation moments behind U = <H>/L^2, the
  * specific heat and the Binder cumulant.
  * Errors (host): invalid batch, n < 0 or n > 2^31 -> ISING_E_INVALID.
@@ -245,7 +248,7 @@ ISING_API int ising_batch_init(const ising_batch *b, int32_t start, void *hip_st
  * spins buffer or max_L, or t + n > 2^31; then no lattice is changed and
  * t is not advanced. */
 ISING_API int ising_batch_sweep(const ising_batch *b, int64_t n, int64_t *moments_dev,
-                                void *hip_stream);
+                                int64_t *trace_dev, void *hip_stream);
 
 /* Recount E and M of every lattice from scratch into E_dev[j], M_dev[j]
  * (device int64[count]; either may be NULL). */

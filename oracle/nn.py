@@ -145,3 +145,9 @@ def mh_log_ratio(beta: float, E_cur, E_prop, logq_cur, logq_prop):
     Boltzmann weight exp(-beta E): -beta (E' - E) + log q(s) - log q(s')."""
     return -beta * (np.asarray(E_prop, np.float64) - np.asarray(E_cur, np.float64)) + \
         np.asarray(logq_cur, np.float64) - np.asarray(logq_prop, np.float64)
+
+
+def logq_sym(params: np.ndarray, s: np.ndarray, C: int) -> np.ndarray:
+    """log of the Z2-symmetrised proposal q_sym(s) = (q(s) + q(-s)) / 2:
+    sample from q, then negate the whole configuration with probability 1/2."""
+    return np.logaddexp(logq(params, s, C), logq(params, -s, C)) - np.log(2.0)

@@ -33,7 +33,11 @@ EXPORTED = (
     "ising_batch_spins_bytes", "ising_batch_workspace_bytes", "ising_batch_setup",
     "ising_batch_init", "ising_batch_sweep", "ising_batch_measure", "ising_batch_sweep_index",
     "ising_batch_rng_blocks", "ising_batch_check_device_error", "ising_batch_autotune",
+    "ising_nn_param_count", "ising_nn_workspace_bytes", "ising_nn_round_weights", "ising_nn_logq",
+    "ising_nn_grad", "ising_nn_adam", "ising_nn_sample", "ising_batch_mh",
 )
+NN_CHANNELS = 16
+NN_MAX_L = 64
 BATCH_MAX_L = 256
 BATCH_MAX_COUNT = 65536
 MOMENT_FIELDS = ("E", "M", "sum_E", "sum_E2", "sum_absM", "sum_M2", "sum_M4_lo", "sum_M4_hi")
@@ -71,6 +75,21 @@ class ising_batch(ctypes.Structure):
         ("groups_per_cu", ctypes.c_int32),
         ("spins_bytes", ctypes.c_uint64),
         ("spins", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+    ]
+
+
+class ising_nn(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("channels", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("master", ctypes.c_void_p),
+        ("weights", ctypes.c_void_p),
+        ("grad", ctypes.c_void_p),
+        ("adam_m", ctypes.c_void_p),
+        ("adam_v", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
     ]
 
@@ -121,7 +140,7 @@ def load_library():
     lib.ising_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.ising_batch_setup.argtypes = [bat_p, i32p, f64p, vp]
     lib.ising_batch_init.argtypes = [bat_p, ctypes.c_int32, vp]
-    lib.ising_batch_sweep.argtypes = [bat_p, ctypes.c_int64, vp, vp]
+    lib.ising_batch_sweep.argtypes = [bat_p, ctypes.c_int64, vp, vp, vp]
     lib.ising_batch_measure.argtypes = [bat_p, vp, vp, vp]
     lib.ising_batch_sweep_index.argtypes = [bat_p, u64p, vp]
     lib.ising_batch_rng_blocks.argtypes = [bat_p, u64p, vp]
@@ -130,6 +149,23 @@ def load_library():
     for name in ("ising_batch_setup", "ising_batch_init", "ising_batch_sweep", "ising_batch_measure",
                  "ising_batch_sweep_index", "ising_batch_rng_blocks",
                  "ising_batch_check_device_error", "ising_batch_autotune"):
+        getattr(lib, name).restype = ctypes.c_int
+    nn_p = P(ising_nn)
+    lib.ising_nn_param_count.argtypes = [ctypes.c_int32]
+    lib.ising_nn_param_count.restype = ctypes.c_int32
+    lib.ising_nn_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.ising_nn_workspace_bytes.restype = ctypes.c_size_t
+    lib.ising_nn_round_weights.argtypes = [nn_p, vp]
+    lib.ising_nn_logq.argtypes = [nn_p, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp, vp]
+    lib.ising_nn_grad.argtypes = [nn_p, vp, ctypes.c_int64, ctypes.c_int32, vp, vp]
+    lib.ising_nn_adam.argtypes = [nn_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_int32, vp]
+    lib.ising_nn_sample.argtypes = [nn_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_uint32, ctypes.c_int32, vp, ctypes.c_int64, vp, vp]
+    lib.ising_batch_mh.argtypes = [bat_p, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, vp,
+                                   ctypes.c_uint32, vp, vp]
+    for name in ("ising_nn_round_weights", "ising_nn_logq", "ising_nn_grad", "ising_nn_adam",
+                 "ising_nn_sample", "ising_batch_mh"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.ising_abi_version() != ABI_VERSION:
         raise RuntimeError("libising.so ABI version mismatch")
@@ -235,8 +271,10 @@ def ising_batch_init(b: ising_batch, start: int, stream: int = 0):
     _check(load_library().ising_batch_init(ctypes.byref(b), start, stream))
 
 
-def ising_batch_sweep(b: ising_batch, n: int, moments_dev: int = 0, stream: int = 0):
-    _check(load_library().ising_batch_sweep(ctypes.byref(b), int(n), moments_dev or None, stream))
+def ising_batch_sweep(b: ising_batch, n: int, moments_dev: int = 0, trace_dev: int = 0,
+                      stream: int = 0):
+    _check(load_library().ising_batch_sweep(ctypes.byref(b), int(n), moments_dev or None,
+                                            trace_dev or None, stream))
 
 
 def ising_batch_measure(b: ising_batch, E_dev: int = 0, M_dev: int = 0, stream: int = 0):
@@ -269,6 +307,49 @@ def ising_batch_autotune(b: ising_batch, scratch_dev: int, probe_sweeps: int, st
         times.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 64, ctypes.byref(nt), stream))
     t = times[:3 * nt.value].reshape(-1, 3)
     return [(int(a), int(g), float(ms)) for a, g, ms in t]
+
+
+def ising_nn_param_count(channels: int = NN_CHANNELS) -> int:
+    return int(load_library().ising_nn_param_count(channels))
+
+
+def ising_nn_workspace_bytes(L: int, channels: int, max_batch: int) -> int:
+    return int(load_library().ising_nn_workspace_bytes(L, channels, max_batch))
+
+
+def ising_nn_round_weights(net: ising_nn, stream: int = 0):
+    _check(load_library().ising_nn_round_weights(ctypes.byref(net), stream))
+
+
+def ising_nn_logq(net: ising_nn, s_dev: int, stride: int, batch: int, logq_dev: int,
+                  symmetric: int = 0, stream: int = 0):
+    _check(load_library().ising_nn_logq(ctypes.byref(net), s_dev, stride, batch, symmetric,
+                                        logq_dev, stream))
+
+
+def ising_nn_grad(net: ising_nn, s_dev: int, stride: int, batch: int, loss_dev: int = 0,
+                  stream: int = 0):
+    _check(load_library().ising_nn_grad(ctypes.byref(net), s_dev, stride, batch, loss_dev or None,
+                                        stream))
+
+
+def ising_nn_adam(net: ising_nn, lr: float, b1: float, b2: float, eps: float, step: int,
+                  stream: int = 0):
+    _check(load_library().ising_nn_adam(ctypes.byref(net), lr, b1, b2, eps, step, stream))
+
+
+def ising_nn_sample(net: ising_nn, batch: int, seed: int, chain0: int, draw: int, s_out: int,
+                    stride: int, logq_out: int = 0, symmetric: int = 0, stream: int = 0):
+    _check(load_library().ising_nn_sample(ctypes.byref(net), batch, seed, chain0, draw, symmetric,
+                                          s_out, stride, logq_out or None, stream))
+
+
+def ising_batch_mh(b: ising_batch, L_prop: int, prop_dev: int, prop_stride: int, logq_cur_dev: int,
+                   logq_prop_dev: int, beta_dev: int, draw: int, accepted_dev: int = 0,
+                   stream: int = 0):
+    _check(load_library().ising_batch_mh(ctypes.byref(b), L_prop, prop_dev, prop_stride,
+                                         logq_cur_dev, logq_prop_dev, beta_dev, draw,
+                                         accepted_dev or None, stream))
 
 
 # ------------------------------------------------------------ torch-backed lattice
@@ -390,14 +471,18 @@ class Batch:
         ising_batch_init(self.c, {"cold": START_COLD_UP, "random": START_RANDOM}[start],
                          self._stream())
 
-    def sweep(self, n: int, moments: bool = True, out=None):
+    def sweep(self, n: int, moments: bool = True, out=None, trace=None):
         """n sweeps of every lattice; returns the int64 [count, 8] moments
-        (fields MOMENT_FIELDS) of this call, or None."""
+        (fields MOMENT_FIELDS) of this call, or None.  trace, if given, is
+        an int64 tensor [n, count, 2] receiving E and M after every sweep."""
         import torch
 
         if moments and out is None:
             out = torch.empty((self.count, 8), dtype=torch.int64, device=self.device)
-        ising_batch_sweep(self.c, n, out.data_ptr() if moments else 0, self._stream())
+        if trace is not None:
+            assert trace.dtype == torch.int64 and trace.is_contiguous() and trace.numel() >= 2 * n * self.count
+        ising_batch_sweep(self.c, n, out.data_ptr() if moments else 0,
+                          trace.data_ptr() if trace is not None else 0, self._stream())
         return out if moments else None
 
     def measure(self):
@@ -437,3 +522,100 @@ class Batch:
         times = ising_batch_autotune(self.c, scratch.data_ptr(), probe_sweeps, self._stream())
         del scratch_raw, scratch
         return times
+
+
+class Net:
+    """The learned proposal network on the current HIP device: float32
+    master parameters, their bfloat16 copy, gradient and Adam moments, and
+    the workspace, all torch tensors."""
+
+    def __init__(self, L: int, max_batch: int, params=None, device=None):
+        import torch
+
+        self.device = torch.device(device or "cuda")
+        self.L, self.max_batch = L, max_batch
+        self.P = ising_nn_param_count()
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.master = torch.zeros(self.P, **f32)
+        self.weights = torch.zeros(self.P, dtype=torch.int16, device=self.device)
+        self.grad = torch.zeros(self.P, **f32)
+        self.adam_m = torch.zeros(self.P, **f32)
+        self.adam_v = torch.zeros(self.P, **f32)
+        nw = ising_nn_workspace_bytes(L, NN_CHANNELS, max_batch)
+        if nw == 0:
+            raise IsingError(E_INVALID, f"L={L}, max_batch={max_batch} invalid")
+        self._ws_raw, self.workspace = _aligned_buffer(nw, self.device)
+        self.c = ising_nn(ABI_VERSION, L, NN_CHANNELS, max_batch, self.master.data_ptr(),
+                          self.weights.data_ptr(), self.grad.data_ptr(), self.adam_m.data_ptr(),
+                          self.adam_v.data_ptr(), self.workspace.data_ptr())
+        self.step = 0
+        if params is not None:
+            self.set_params(params)
+
+    _stream = staticmethod(Lattice._stream)
+
+    def set_params(self, params):
+        import torch
+
+        self.master.copy_(torch.as_tensor(np.asarray(params, dtype=np.float32)))
+        self.adam_m.zero_()
+        self.adam_v.zero_()
+        self.step = 0
+        ising_nn_round_weights(self.c, self._stream())
+
+    def bf16_params(self):
+        """The bfloat16 parameters the kernels use, as float32 (host numpy)."""
+        import torch
+
+        w = self.weights.to(torch.int32).cpu().numpy().astype(np.uint32) & 0xFFFF
+        return (w << 16).view(np.float32)
+
+    @staticmethod
+    def _cfg(s):
+        """(pointer, stride in bytes, count) of a [B, L, L] int8 tensor, or
+        of a Batch whose lattices all have side L."""
+        if isinstance(s, Batch):
+            if len(s.offsets) > 1:
+                st = int(s.offsets[1] - s.offsets[0])
+                assert all(int(s.offsets[j]) == j * st for j in range(len(s.offsets)))
+            else:
+                st = int(s.L[0]) ** 2
+            return s.spins.data_ptr(), st, s.count
+        assert s.dim() == 3 and s.stride(2) == 1 and s.stride(1) == s.shape[2]
+        return s.data_ptr(), s.stride(0), s.shape[0]
+
+    def logq(self, s, out=None, symmetric: bool = False):
+        import torch
+
+        ptr, st, B = self._cfg(s)
+        if out is None:
+            out = torch.empty(B, dtype=torch.float32, device=self.device)
+        ising_nn_logq(self.c, ptr, st, B, out.data_ptr(), int(symmetric), self._stream())
+        return out
+
+    def loss_and_grad(self, s, loss=None):
+        """Mean NLL of the batch (device tensor [1]); the gradient goes to self.grad."""
+        import torch
+
+        ptr, st, B = self._cfg(s)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        ising_nn_grad(self.c, ptr, st, B, loss.data_ptr(), self._stream())
+        return loss
+
+    def adam(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        ising_nn_adam(self.c, lr, b1, b2, eps, self.step, self._stream())
+
+    def sample(self, batch: int, seed: int, chain0: int = 0, draw: int = 0, out=None, logq=None,
+               symmetric: bool = False):
+        """Draw `batch` configurations; returns (int8 [batch, L, L], float32 [batch])."""
+        import torch
+
+        if out is None:
+            out = torch.empty((batch, self.L, self.L), dtype=torch.int8, device=self.device)
+        if logq is None:
+            logq = torch.empty(batch, dtype=torch.float32, device=self.device)
+        ising_nn_sample(self.c, batch, seed, chain0, draw, out.data_ptr(), out.stride(0),
+                        logq.data_ptr(), int(symmetric), self._stream())
+        return out, logq

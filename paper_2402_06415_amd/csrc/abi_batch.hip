@@ -183,7 +183,8 @@ int ising_batch_init(const ising_batch* b, int32_t start, void* hip_stream) {
     return ISING_OK;
 }
 
-int ising_batch_sweep(const ising_batch* b, int64_t n, int64_t* moments_dev, void* hip_stream) {
+int ising_batch_sweep(const ising_batch* b, int64_t n, int64_t* moments_dev, int64_t* trace_dev,
+                      void* hip_stream) {
     int rc = validate(b);
     if (rc)
         return rc;
@@ -197,7 +198,7 @@ int ising_batch_sweep(const ising_batch* b, int64_t n, int64_t* moments_dev, voi
                                         ising::kPrepareSweep, st),
             "batch prepare");
     HIP_TRY(ising::launch_batch_sweep(ws_of(b), false, b->count, b->spins, b->max_L, n, key_of(b),
-                                      moments_dev, s.threads, grid_of(b, s), st),
+                                      moments_dev, trace_dev, s.threads, grid_of(b, s), st),
             "batch sweep");
     HIP_TRY(ising::launch_batch_advance(ws_of(b), n, st), "batch advance");
     return ISING_OK;
@@ -318,7 +319,7 @@ int ising_batch_autotune(ising_batch* b, int8_t* scratch_spins, int64_t probe_sw
         probe.groups_per_cu = s.groups_per_cu;
         if (err == hipSuccess)
             err = ising::launch_batch_sweep(ws, true, b->count, scratch_spins, b->max_L,
-                                            probe_sweeps, key_of(b), nullptr, s.threads,
+                                            probe_sweeps, key_of(b), nullptr, nullptr, s.threads,
                                             grid_of(&probe, s), st);
         if (err == hipSuccess)
             err = hipEventRecord(e1, st);

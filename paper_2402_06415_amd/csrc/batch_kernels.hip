@@ -294,7 +294,7 @@ __device__ __forceinline__ void add_count(unsigned long long v, unsigned long lo
 // empty.  No workgroup waits on another, so any grid size is safe.
 __global__ void __launch_bounds__(1024) k_batch_sweep(unsigned char* ws, int scratch_t, int count,
                                                       int8_t* spins, int64_t n, Key key,
-                                                      int64_t* moments) {
+                                                      int64_t* moments, int64_t* trace) {
     extern __shared__ uint2 lds2[];
     int8_t* lat = reinterpret_cast<int8_t*>(lds2);
     __shared__ int s_item;
@@ -362,6 +362,11 @@ __global__ void __launch_bounds__(1024) k_batch_sweep(unsigned char* ws, int scr
                 const unsigned long long lo = m2 * m2, hi = __umul64hi(m2, m2);
                 m4lo += lo;
                 m4hi += hi + (m4lo < lo ? 1u : 0u);
+                if (trace) {
+                    int64_t* tr = trace + (sw * count + j) * 2;
+                    tr[0] = E;
+                    tr[1] = M;
+                }
             }
         }
         uint2* dst = reinterpret_cast<uint2*>(spins + d.off);
@@ -406,10 +411,10 @@ hipError_t launch_batch_init(unsigned char* ws, int count, int8_t* spins, int st
 }
 
 hipError_t launch_batch_sweep(unsigned char* ws, bool scratch_t, int count, int8_t* spins,
-                              int max_L, int64_t n, Key key, int64_t* moments, int threads,
-                              int blocks, hipStream_t st) {
+                              int max_L, int64_t n, Key key, int64_t* moments, int64_t* trace,
+                              int threads, int blocks, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_sweep, dim3(blocks), dim3(threads), batch_lds_bytes(max_L), st, ws,
-                       scratch_t ? 1 : 0, count, spins, n, key, moments);
+                       scratch_t ? 1 : 0, count, spins, n, key, moments, trace);
     return hipGetLastError();
 }
 

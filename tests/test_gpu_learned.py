@@ -1,0 +1,96 @@
+"""The learned-proposal chain end to end on the GPU: the network is trained
+by the library's own kernels on configurations from the plain sampler, and
+the combined chain (plain sweeps plus one whole-lattice proposal accepted
+by Metropolis-Hastings) must sample the Boltzmann distribution: its mean
+energy agrees with Kaufman's exact finite-lattice value and with the plain
+chain.  Statistical, so the bounds are 4 standard errors (binned)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2402_06415_amd.workloads import nn_initial_params
+
+import exact
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2402_06415_amd as lib  # noqa: E402
+from paper_2402_06415_amd.analysis import binned_mean, tau_int  # noqa: E402
+from paper_2402_06415_amd.learned import LearnedChains, plain_configurations, train  # noqa: E402
+
+BC = 0.4406868
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lib.load_library()
+    yield
+    torch.cuda.synchronize()
+
+
+def test_training_lowers_the_loss():
+    say("train L=16")
+    L = 16
+    data = plain_configurations(L, BC, chains=256, therm=400, snapshots=24, gap=5, seed=3)
+    net = lib.Net(L, 512, params=nn_initial_params(1))
+    before = float(net.loss_and_grad(data[:512]).cpu()[0])
+    losses = train(net, data, epochs=3, batch=512, lr=3e-3, seed=2)
+    after = float(net.loss_and_grad(data[:512]).cpu()[0])
+    assert np.isfinite(losses).all()
+    assert after < 0.8 * before, (before, after)
+    # a trained model must beat the uniform distribution (N log 2 nats)
+    assert after < 0.9 * L * L * np.log(2.0)
+
+
+def test_learned_chain_samples_the_boltzmann_distribution():
+    """L = 16 at beta_c: <e> of the plain chain and of the learned chain
+    against Kaufman's exact value e = -1.4530649028994416."""
+    L, chains = 16, 256
+    e_exact = exact.kaufman_energy(BC, L)
+    say("plain chain L=16")
+    plain = lib.Batch([L] * chains, [BC] * chains, seed=41, start="random")
+    plain.sweep(500, moments=False)
+    tr = torch.empty((4000, chains, 2), dtype=torch.int64, device="cuda")
+    plain.sweep(4000, moments=False, trace=tr)
+    e_plain = tr[:, :, 0].cpu().numpy() / (L * L)
+    mp, ep = binned_mean(e_plain)
+    assert abs(mp - e_exact) < 4 * ep + 1e-4, (mp, ep, e_exact)
+
+    say("train + learned chain L=16")
+    data = plain_configurations(L, BC, chains=256, therm=400, snapshots=24, gap=5, seed=5)
+    net = lib.Net(L, 512, params=nn_initial_params(2))
+    losses = train(net, data, epochs=20, batch=512, lr=3e-3, seed=4)
+    say(f"loss {losses[0]:.2f} -> {losses[-1]:.2f} nats per configuration")
+    lc = LearnedChains(net, L, [BC] * chains, seed=43, sweeps_per_proposal=10)
+    for _ in range(20):  # equilibrate
+        lc.cycle()
+    cycles = 300
+    trl = torch.empty((cycles * 10, chains, 2), dtype=torch.int64, device="cuda")
+    lc.n_accepted.zero_()
+    for c in range(cycles):
+        lc.cycle(trace=trl[c * 10:(c + 1) * 10])
+    e_learn = trl[:, :, 0].cpu().numpy() / (L * L)
+    ml, el = binned_mean(e_learn)
+    rate = float(lc.n_accepted.sum().cpu()) / (cycles * chains)
+    say(f"acceptance {rate:.3f}, <e> plain {mp:.5f}+-{ep:.5f} learned {ml:.5f}+-{el:.5f} exact {e_exact:.5f}")
+    assert rate > 0.005, rate
+    assert abs(ml - e_exact) < 4 * el + 1e-4, (ml, el, e_exact)
+    assert abs(ml - mp) < 4 * np.hypot(el, ep) + 1e-4
+    # chains that rejected the last proposal still hold the last traced state
+    E, _ = lc.batch.measure()
+    kept = lc.accepted.cpu().numpy() == 0
+    assert kept.sum() > chains // 2
+    assert (E.cpu().numpy()[kept] == trl[-1, :, 0].cpu().numpy()[kept]).all()
+    lc.batch.check()
+    tau_p = tau_int(np.abs(tr[:, :, 1].cpu().numpy()))[0]
+    tau_l = tau_int(np.abs(trl[:, :, 1].cpu().numpy()))[0]
+    say(f"tau_int |m|: plain {tau_p:.1f} sweeps, learned {tau_l:.1f} sweeps")
+    assert tau_l > 0 and tau_p > 0

@@ -60,6 +60,18 @@ def test_model_is_normalised_and_autoregressive():
         assert np.allclose(z1.reshape(-1)[:i + 1], z0.reshape(-1)[:i + 1], rtol=0, atol=1e-14)
 
 
+def test_symmetrised_model_is_normalised_and_even():
+    C, L = 4, 3
+    p = _params(C, 6, 0.8)
+    S = _all_states(L)
+    lq = nn.logq_sym(p, S, C)
+    assert abs(np.exp(lq).sum() - 1.0) < 1e-12
+    assert np.allclose(lq, nn.logq_sym(p, -S, C), rtol=0, atol=1e-13)
+    # (q(s) + q(-s)) / 2 from the plain model, term by term
+    q = np.exp(nn.logq(p, S, C))
+    assert np.allclose(np.exp(lq), 0.5 * (q + np.exp(nn.logq(p, -S, C))), rtol=1e-12)
+
+
 def test_sampler_frequencies_match_q():
     C, L, B = 3, 2, 20000
     p = _params(C, 7, 0.7)
