@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ising_oracle.c")
+_SRC_EA = os.path.join(_HERE, "ea_oracle.c")
 _LIB = os.path.join(_HERE, "libising_oracle.so")
 
 MODE_SITE = 0
@@ -34,7 +35,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-               "-o", tmp, _SRC, "-lm"]
+               "-o", tmp, _SRC, _SRC_EA, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
@@ -44,7 +45,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                  os.path.getmtime(_SRC_EA)):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -77,6 +79,32 @@ def _load():
     lib.oracle_sweep.restype = ctypes.c_int
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = ctypes.c_int
+    f64p = ctypes.POINTER(ctypes.c_double)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.oracle_ea_energy.argtypes = [i8p, i8p, ctypes.c_int]
+    lib.oracle_ea_energy.restype = ctypes.c_int64
+    lib.oracle_ea_local_u.argtypes = [i8p, i8p, ctypes.c_int, ctypes.c_int64]
+    lib.oracle_ea_local_u.restype = ctypes.c_int
+    lib.oracle_ea_thresholds.argtypes = [ctypes.c_double, u32p, u8p]
+    lib.oracle_ea_thresholds.restype = ctypes.c_int
+    lib.oracle_ea_swap_threshold.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                             u32p, u8p]
+    lib.oracle_ea_swap_threshold.restype = None
+    lib.oracle_ea_init.argtypes = [i8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                   ctypes.c_uint32]
+    lib.oracle_ea_init.restype = None
+    lib.oracle_ea_halfsweep.argtypes = [i8p, i8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, i64p,
+                                        ctypes.c_int]
+    lib.oracle_ea_halfsweep.restype = ctypes.c_int
+    lib.oracle_ea_exchange.argtypes = [i64p, i32p, ctypes.c_int, f64p, ctypes.c_uint64,
+                                       ctypes.c_uint64, u64p]
+    lib.oracle_ea_exchange.restype = None
+    lib.oracle_ea_run.argtypes = [i8p, i8p, ctypes.c_int, ctypes.c_int, f64p, ctypes.c_uint64,
+                                  ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, i32p, i64p, u64p,
+                                  i64p, ctypes.c_int]
+    lib.oracle_ea_run.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -207,3 +235,73 @@ def batch_sweep(states, betas, seed: int, lattice_id0: int, t0: int, n: int, nth
         E, M = sweep(s, MODE_SITE, seed, lattice_id0 + j, t0, n, betas[j], nthreads=nthreads)
         out.append(moments(E, M))
     return out
+
+
+# ------------------------------------------------------------ 3D spin glass
+def ea_energy(s: np.ndarray, J: np.ndarray) -> int:
+    """H = -sum_n sum_d J_d(n) s_n s_{n+e_d} of s [L, L, L] (index [z, y, x])
+    with couplings J [3, L, L, L] (d = 0: x, 1: y, 2: z)."""
+    s, J = np.ascontiguousarray(s, np.int8), np.ascontiguousarray(J, np.int8)
+    return int(_load().oracle_ea_energy(_ptr(s, ctypes.c_int8), _ptr(J, ctypes.c_int8), s.shape[0]))
+
+
+def ea_local_u(s: np.ndarray, J: np.ndarray, n: int) -> int:
+    s, J = np.ascontiguousarray(s, np.int8), np.ascontiguousarray(J, np.int8)
+    return int(_load().oracle_ea_local_u(_ptr(s, ctypes.c_int8), _ptr(J, ctypes.c_int8),
+                                         s.shape[0], n))
+
+
+def ea_thresholds(beta: float):
+    T = np.zeros(3, np.uint32)
+    a = np.zeros(3, np.uint8)
+    if _load().oracle_ea_thresholds(float(beta), _ptr(T, ctypes.c_uint32), _ptr(a, ctypes.c_uint8)):
+        raise ValueError("invalid beta")
+    return T, a
+
+
+def ea_swap_threshold(beta_lo: float, beta_hi: float, D: int):
+    T = np.zeros(1, np.uint32)
+    a = np.zeros(1, np.uint8)
+    _load().oracle_ea_swap_threshold(float(beta_lo), float(beta_hi), int(D),
+                                     _ptr(T, ctypes.c_uint32), _ptr(a, ctypes.c_uint8))
+    return int(T[0]), bool(a[0])
+
+
+def ea_init(L: int, start: int, seed: int, replica_id: int) -> np.ndarray:
+    s = np.zeros((L, L, L), np.int8)
+    _load().oracle_ea_init(_ptr(s, ctypes.c_int8), L, start, seed, replica_id)
+    return s
+
+
+def ea_halfsweep(s: np.ndarray, J: np.ndarray, c: int, seed: int, replica_id: int, t: int,
+                 beta: float, nthreads: int = 1) -> int:
+    dE = ctypes.c_int64(0)
+    J = np.ascontiguousarray(J, np.int8)
+    if _load().oracle_ea_halfsweep(_ptr(s, ctypes.c_int8), _ptr(J, ctypes.c_int8), s.shape[0], c,
+                                   seed, replica_id, t, float(beta), ctypes.byref(dE), nthreads):
+        raise ValueError("oracle_ea_halfsweep rejected its arguments")
+    return dE.value
+
+
+def ea_run(spins: np.ndarray, J: np.ndarray, beta, seed: int, t0: int, n: int, every: int,
+           perm: np.ndarray, E: np.ndarray, accepts: np.ndarray = None, trace: bool = True,
+           nthreads: int = 1):
+    """n sweeps of the replicas spins [R, L, L, L] in place (replica id r),
+    temperatures beta [R] increasing, exchange after every `every`-th
+    sweep; perm (int32 [R], temperature -> replica), E (int64 [R], current
+    energies) and accepts (uint64 [R-1]) are updated.  Returns the energy
+    trace [n, R] (or None)."""
+    R, L = spins.shape[0], spins.shape[1]
+    beta = np.ascontiguousarray(beta, np.float64)
+    J = np.ascontiguousarray(J, np.int8)
+    if accepts is None:
+        accepts = np.zeros(max(R - 1, 1), np.uint64)
+    tr = np.zeros((max(n, 1), R), np.int64) if trace else None
+    rc = _load().oracle_ea_run(_ptr(spins, ctypes.c_int8), _ptr(J, ctypes.c_int8), L, R,
+                               _ptr(beta, ctypes.c_double), seed, t0, n, every,
+                               _ptr(perm, ctypes.c_int32), _ptr(E, ctypes.c_int64),
+                               _ptr(accepts, ctypes.c_uint64),
+                               _ptr(tr, ctypes.c_int64) if trace else None, nthreads)
+    if rc:
+        raise ValueError("oracle_ea_run rejected its arguments")
+    return tr[:n] if trace else None

@@ -46,3 +46,19 @@ def learned_workload():
     the plain sampler; one whole-lattice proposal per 10 sweeps."""
     return {"L": 32, "betas": (0.40, 0.4406868, 0.48), "chains": 1024, "train_configs": 100_000,
             "sweeps_per_proposal": 10}
+
+
+def ea_bonds(L: int, seed: int = 3) -> np.ndarray:
+    """Couplings of the 3D Edwards-Anderson +-J glass: int8 [3, L, L, L]
+    (axis d = x, y, z; index [d, z, y, x]), i.i.d. +1 / -1 with p = 1/2 from
+    numpy's Philox generator keyed by `seed`."""
+    rng = np.random.Generator(np.random.Philox(seed))
+    return (2 * rng.integers(0, 2, size=(3, L, L, L), dtype=np.int8) - 1).astype(np.int8)
+
+
+def ea_workload(replicas: int = 64, L: int = 128):
+    """The spin-glass study: cubic L = 128, bonds from seed 3, 64 replicas
+    at beta_k = 0.5 + 0.7 k / 63 (uniform in [0.5, 1.2]), replica exchange
+    every 10 sweeps, 10^4 sweeps, random starts (seed 3, replica id r)."""
+    beta = 0.5 + 0.7 * np.arange(replicas, dtype=np.float64) / max(replicas - 1, 1)
+    return {"L": L, "beta": beta, "bond_seed": 3, "seed": 3, "every": 10, "sweeps": 10_000}

@@ -1,0 +1,155 @@
+"""Pins of the 3D spin-glass oracle (oracle/ea_oracle.c): thresholds
+against 80-digit arithmetic and printed closed-form values, the energy
+against an independent numpy formula, E(flip) - E = 2u, exact gauge
+invariance of the whole chain, exact detailed balance of each half-sweep
+on the 2^8 states of a 2x2x2 lattice, and replica exchange sampling each
+temperature's exact distribution."""
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_06415_amd.workloads import ea_bonds
+
+
+def _energy_numpy(s, J):
+    s = s.astype(np.int64)
+    E = 0
+    for d, ax in enumerate((2, 1, 0)):  # x, y, z are array axes 2, 1, 0
+        E -= int((J[d].astype(np.int64) * s * np.roll(s, -1, axis=ax)).sum())
+    return E
+
+
+def test_thresholds_printed_values():
+    assert oracle.ea_thresholds(0.5)[0].tolist() == [581260616, 78665071, 10646160]
+    assert oracle.ea_thresholds(1.2)[0].tolist() == [35346495, 290893, 2394]
+
+
+@pytest.mark.parametrize("beta", [0.0, 1e-12, 0.5, 0.7, 0.9, 1.2])
+def test_thresholds_bracket_exp(beta):
+    T, a = oracle.ea_thresholds(beta)
+    with mp.workdps(80):
+        for i, u in enumerate((2, 4, 6)):
+            P = mp.e ** (-mp.mpf(beta) * 2 * u)
+            if a[i]:
+                assert mp.ldexp(P, 32) > 2 ** 32 - 1
+                continue
+            assert mp.mpf(int(T[i]) - 1) / 2 ** 32 < P <= mp.mpf(int(T[i])) / 2 ** 32
+
+
+@pytest.mark.parametrize("blo,bhi,D", [(0.5, 0.5 + 0.7 / 63, 4), (0.5, 0.5 + 0.7 / 63, 400),
+                                       (1.0, 1.2, 12), (0.5, 0.6, 2000), (0.5, 0.9, 100000)])
+def test_swap_threshold_brackets_exp(blo, bhi, D):
+    T, a = oracle.ea_swap_threshold(blo, bhi, D)
+    with mp.workdps(80):
+        P = mp.e ** (-(mp.mpf(bhi) - mp.mpf(blo)) * D)
+        assert not a
+        if T == 0:
+            assert P < mp.mpf(2) ** -1070  # exp underflows in double
+        else:
+            assert mp.mpf(T - 1) / 2 ** 32 < P <= mp.mpf(T) / 2 ** 32
+    assert oracle.ea_swap_threshold(blo, bhi, 0) == (0, True)
+    assert oracle.ea_swap_threshold(blo, bhi, -8) == (0, True)
+
+
+def test_energy_and_local_field():
+    L = 6
+    J = ea_bonds(L, 7)
+    s = oracle.ea_init(L, 1, 9, 0)
+    assert oracle.ea_energy(s, J) == _energy_numpy(s, J)
+    assert oracle.ea_energy(np.ones((L, L, L), np.int8), np.ones((3, L, L, L), np.int8)) == -3 * L ** 3
+    E0 = oracle.ea_energy(s, J)
+    for n in range(L ** 3):
+        t = s.copy()
+        t.reshape(-1)[n] *= -1
+        assert oracle.ea_energy(t, J) - E0 == 2 * oracle.ea_local_u(s, J, n)
+
+
+def test_chain_is_gauge_invariant():
+    """With tau_n = +-1, J'_d(n) = tau_n J_d(n) tau_{n+e_d} and s' = tau s have
+    the same energies and local fields, so the same draws give the chain
+    tau * chain, exchanges included, bit for bit."""
+    L, R = 4, 3
+    J = ea_bonds(L, 11)
+    tau = oracle.ea_init(L, 1, 12, 5)
+    Jg = np.empty_like(J)
+    for d, ax in enumerate((2, 1, 0)):
+        Jg[d] = tau * J[d] * np.roll(tau, -1, axis=ax)
+    beta = np.array([0.5, 0.8, 1.1])
+    a = np.stack([oracle.ea_init(L, 1, 3, r) for r in range(R)])
+    b = a * tau[None]
+    Ea = np.array([oracle.ea_energy(x, J) for x in a])
+    Eb = np.array([oracle.ea_energy(x, Jg) for x in b])
+    assert (Ea == Eb).all()
+    pa, pb = np.arange(R, dtype=np.int32), np.arange(R, dtype=np.int32)
+    ta = oracle.ea_run(a, J, beta, 3, 0, 60, 2, pa, Ea)
+    tb = oracle.ea_run(b, Jg, beta, 3, 0, 60, 2, pb, Eb)
+    assert (ta == tb).all() and (pa == pb).all()
+    assert (b == a * tau[None]).all()
+    assert sorted(pa.tolist()) == list(range(R))
+
+
+def _all_states_3d():
+    idx = np.arange(256)
+    return (1 - 2 * ((idx[:, None] >> np.arange(8)) & 1)).astype(np.int8).reshape(256, 2, 2, 2)
+
+
+@pytest.mark.parametrize("beta", [0.3, 0.9])
+def test_halfsweep_detailed_balance_2x2x2(beta):
+    """K_c flips each colour-c site independently with probability
+    T(u)/2^32 (1 for u <= 0): pi K_c is reversible up to the 2^-32
+    quantisation, for random couplings on the 2x2x2 torus."""
+    J = ea_bonds(2, 21)
+    S = _all_states_3d()
+    E = np.array([oracle.ea_energy(x, J) for x in S], np.float64)
+    pi = np.exp(-beta * (E - E.min()))
+    pi /= pi.sum()
+    T, a = oracle.ea_thresholds(beta)
+    code = {x.tobytes(): k for k, x in enumerate(S)}
+    for c in (0, 1):
+        sites = [n for n in range(8) if ((n & 1) + ((n >> 1) & 1) + (n >> 2)) % 2 == c]
+        K = np.zeros((256, 256))
+        for k, x in enumerate(S):
+            p = []
+            for n in sites:
+                u = oracle.ea_local_u(x, J, n)
+                p.append(1.0 if u <= 0 or a[u // 2 - 1] else float(T[u // 2 - 1]) / 2 ** 32)
+            for F in range(1 << len(sites)):
+                y = x.copy().reshape(-1)
+                w = 1.0
+                for b, n in enumerate(sites):
+                    if (F >> b) & 1:
+                        y[n] *= -1
+                        w *= p[b]
+                    else:
+                        w *= 1 - p[b]
+                K[k, code[y.reshape(2, 2, 2).tobytes()]] += w
+        flow = pi[:, None] * K
+        assert np.allclose(flow, flow.T, rtol=4 * 2.0 ** -32 / float(T[2]) * 2 ** 32, atol=1e-17)
+        assert np.allclose(pi @ K, pi, atol=1e-12)
+
+
+def test_replica_exchange_samples_each_temperature():
+    """Three replicas on the 2x2x2 glass, exchange after every sweep: the
+    energy seen at each temperature averages to the exact Boltzmann mean."""
+    J = ea_bonds(2, 23)
+    beta = np.array([0.3, 0.6, 0.9])
+    S = _all_states_3d()
+    E_all = np.array([oracle.ea_energy(x, J) for x in S], np.float64)
+    exact = [float((E_all * np.exp(-b * E_all)).sum() / np.exp(-b * E_all).sum()) for b in beta]
+    R = 3
+    spins = np.stack([oracle.ea_init(2, 1, 31, r) for r in range(R)])
+    E = np.array([oracle.ea_energy(x, J) for x in spins])
+    perm = np.arange(R, dtype=np.int32)
+    acc = np.zeros(R - 1, np.uint64)
+    n = 30000
+    hist = np.zeros((n, R))
+    for t in range(n):
+        oracle.ea_run(spins, J, beta, 31, t, 1, 1, perm, E, acc, trace=False)
+        hist[t] = E[perm]
+    assert (acc > 0).all()
+    for k in range(R):
+        x = hist[1000:, k]
+        blocks = x[: len(x) // 50 * 50].reshape(50, -1).mean(axis=1)
+        err = blocks.std(ddof=1) / np.sqrt(50)
+        assert abs(blocks.mean() - exact[k]) < 4 * err + 1e-9, (k, blocks.mean(), exact[k], err)
