@@ -35,6 +35,8 @@ EXPORTED = (
     "ising_batch_rng_blocks", "ising_batch_check_device_error", "ising_batch_autotune",
     "ising_nn_param_count", "ising_nn_workspace_bytes", "ising_nn_round_weights", "ising_nn_logq",
     "ising_nn_grad", "ising_nn_adam", "ising_nn_sample", "ising_batch_mh",
+    "ising_ea_spins_bytes", "ising_ea_workspace_bytes", "ising_ea_setup", "ising_ea_init",
+    "ising_ea_sweep", "ising_ea_measure", "ising_ea_state", "ising_ea_check_device_error",
 )
 NN_CHANNELS = 16
 NN_MAX_L = 64
@@ -90,6 +92,19 @@ class ising_nn(ctypes.Structure):
         ("grad", ctypes.c_void_p),
         ("adam_m", ctypes.c_void_p),
         ("adam_v", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+    ]
+
+
+class ising_ea(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("replicas", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("spins", ctypes.c_void_p),
+        ("bonds", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
     ]
 
@@ -166,6 +181,20 @@ def load_library():
                                    ctypes.c_uint32, vp, vp]
     for name in ("ising_nn_round_weights", "ising_nn_logq", "ising_nn_grad", "ising_nn_adam",
                  "ising_nn_sample", "ising_batch_mh"):
+        getattr(lib, name).restype = ctypes.c_int
+    ea_p = P(ising_ea)
+    lib.ising_ea_spins_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.ising_ea_spins_bytes.restype = ctypes.c_size_t
+    lib.ising_ea_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.ising_ea_workspace_bytes.restype = ctypes.c_size_t
+    lib.ising_ea_setup.argtypes = [ea_p, f64p, vp]
+    lib.ising_ea_init.argtypes = [ea_p, ctypes.c_int32, vp]
+    lib.ising_ea_sweep.argtypes = [ea_p, ctypes.c_int64, ctypes.c_int32, vp, vp]
+    lib.ising_ea_measure.argtypes = [ea_p, vp, vp]
+    lib.ising_ea_state.argtypes = [ea_p, u64p, i32p, P(ctypes.c_int64), u64p, vp]
+    lib.ising_ea_check_device_error.argtypes = [ea_p, vp]
+    for name in ("ising_ea_setup", "ising_ea_init", "ising_ea_sweep", "ising_ea_measure",
+                 "ising_ea_state", "ising_ea_check_device_error"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.ising_abi_version() != ABI_VERSION:
         raise RuntimeError("libising.so ABI version mismatch")
@@ -350,6 +379,52 @@ def ising_batch_mh(b: ising_batch, L_prop: int, prop_dev: int, prop_stride: int,
     _check(load_library().ising_batch_mh(ctypes.byref(b), L_prop, prop_dev, prop_stride,
                                          logq_cur_dev, logq_prop_dev, beta_dev, draw,
                                          accepted_dev or None, stream))
+
+
+def ising_ea_spins_bytes(L: int, replicas: int) -> int:
+    return int(load_library().ising_ea_spins_bytes(L, replicas))
+
+
+def ising_ea_workspace_bytes(L: int, replicas: int) -> int:
+    return int(load_library().ising_ea_workspace_bytes(L, replicas))
+
+
+def ising_ea_setup(ea: ising_ea, beta_host, stream: int = 0):
+    b, bp = _f64(beta_host)
+    if len(b) != ea.replicas:
+        raise IsingError(E_INVALID, "one beta per replica")
+    _check(load_library().ising_ea_setup(ctypes.byref(ea), bp, stream))
+
+
+def ising_ea_init(ea: ising_ea, start: int, stream: int = 0):
+    _check(load_library().ising_ea_init(ctypes.byref(ea), start, stream))
+
+
+def ising_ea_sweep(ea: ising_ea, n: int, every: int, trace_dev: int = 0, stream: int = 0):
+    _check(load_library().ising_ea_sweep(ctypes.byref(ea), int(n), int(every), trace_dev or None,
+                                         stream))
+
+
+def ising_ea_measure(ea: ising_ea, E_dev: int, stream: int = 0):
+    _check(load_library().ising_ea_measure(ctypes.byref(ea), E_dev, stream))
+
+
+def ising_ea_state(ea: ising_ea, stream: int = 0):
+    """(t, perm [R], E [R], accepts [R-1]) read back from the device."""
+    R = ea.replicas
+    t = ctypes.c_uint64(0)
+    perm = np.zeros(R, np.int32)
+    E = np.zeros(R, np.int64)
+    acc = np.zeros(max(R - 1, 1), np.uint64)
+    _check(load_library().ising_ea_state(
+        ctypes.byref(ea), ctypes.byref(t), perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        E.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        acc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), stream))
+    return int(t.value), perm, E, acc[:max(R - 1, 0)]
+
+
+def ising_ea_check_device_error(ea: ising_ea, stream: int = 0):
+    _check(load_library().ising_ea_check_device_error(ctypes.byref(ea), stream))
 
 
 # ------------------------------------------------------------ torch-backed lattice
@@ -619,3 +694,62 @@ class Net:
         ising_nn_sample(self.c, batch, seed, chain0, draw, out.data_ptr(), out.stride(0),
                         logq.data_ptr(), int(symmetric), self._stream())
         return out, logq
+
+
+class SpinGlass:
+    """R replicas of the 3D +-J glass (couplings `bonds`, int8 [3, L, L, L])
+    on a beta ladder, with replica exchange; torch-backed buffers."""
+
+    def __init__(self, bonds, betas, seed: int = 3, start: str = "random", device=None,
+                 init: bool = True):
+        import torch
+
+        self.device = torch.device(device or "cuda")
+        bonds = np.ascontiguousarray(bonds, np.int8)
+        self.L = int(bonds.shape[1])
+        self.R = len(betas)
+        nb = ising_ea_spins_bytes(self.L, self.R)
+        nw = ising_ea_workspace_bytes(self.L, self.R)
+        if nb == 0:
+            raise IsingError(E_INVALID, f"L={self.L}, R={self.R} invalid")
+        self._spins_raw, self.spins = _aligned_buffer(nb, self.device)
+        self._bonds_raw, self.bonds = _aligned_buffer(bonds.nbytes, self.device)
+        self.bonds.copy_(torch.from_numpy(bonds.reshape(-1).view(np.uint8)))
+        self._ws_raw, self.workspace = _aligned_buffer(nw, self.device)
+        self.c = ising_ea(ABI_VERSION, self.L, self.R, 0, seed, self.spins.data_ptr(),
+                          self.bonds.data_ptr(), self.workspace.data_ptr())
+        self.beta = np.ascontiguousarray(betas, np.float64)
+        ising_ea_setup(self.c, self.beta, self._stream())
+        if init:
+            self.init(start)
+
+    _stream = staticmethod(Lattice._stream)
+
+    def init(self, start: str = "random"):
+        ising_ea_init(self.c, {"cold": START_COLD_UP, "random": START_RANDOM}[start], self._stream())
+
+    def sweep(self, n: int, every: int = 10, trace=None):
+        """n sweeps; trace (int64 [n, R], optional) receives every replica's energy after each sweep."""
+        if trace is not None:
+            assert trace.is_contiguous() and trace.numel() >= n * self.R
+        ising_ea_sweep(self.c, n, every, trace.data_ptr() if trace is not None else 0,
+                       self._stream())
+
+    def replica(self, r: int):
+        import torch
+
+        N = self.L ** 3
+        return self.spins[r * N:(r + 1) * N].view(torch.int8).view(self.L, self.L, self.L)
+
+    def measure(self):
+        import torch
+
+        E = torch.empty(self.R, dtype=torch.int64, device=self.device)
+        ising_ea_measure(self.c, E.data_ptr(), self._stream())
+        return E
+
+    def state(self):
+        return ising_ea_state(self.c, self._stream())
+
+    def check(self):
+        ising_ea_check_device_error(self.c, self._stream())

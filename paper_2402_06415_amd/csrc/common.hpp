@@ -20,6 +20,7 @@ constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 constexpr uint32_t kTagSite = 0u;   // one uint32 per site (INT8 layout)
 constexpr uint32_t kTagPlane = 1u;  // bit planes, block index in bits 8.. (BIT1)
 constexpr uint32_t kTagInit = 2u;   // random start
+constexpr uint32_t kTagSwap = 5u;      // replica-exchange draws
 constexpr uint32_t kTagNNSample = 6u;  // site draws of the learned proposal
 constexpr uint32_t kTagMH = 7u;        // acceptance draws of whole-lattice moves
 

@@ -1,0 +1,379 @@
+// 3D Edwards-Anderson +-J spin glass with replica exchange.
+//
+// All replicas are swept together: one launch per half-sweep covers every
+// replica, one thread per 8-byte span of a row (the four colour-c sites of
+// the span share one Philox4x32-10 block, SITE draws).  The six neighbours
+// of the four sites come from the span's row (plus one byte across its
+// edge), the rows above and below and the planes in front and behind; the
+// couplings from the same places of the three bond arrays.  A bond is
+// unsatisfied when J s_i s_j = -1: for +-1 bytes (0x01 / 0xFF) that is bit 1
+// of s_i ^ s_j ^ J, so the unsatisfied counts of the four sites are summed
+// byte-parallel.  With n_u unsatisfied bonds, u = 6 - 2 n_u: n_u >= 3 flips
+// without a draw, n_u = 2, 1, 0 need r < T2, T4, T6 (T6 <= T4 <= T2), i.e.
+// lvl = (r < T2) + (r < T4) + (r < T6) >= 1, 2, 3.
+//
+// Per-block energy changes go to a partials array; a per-sweep kernel sums
+// them in a fixed order, then the exchange kernel (a no-op between
+// exchanges) swaps temperatures and advances the device sweep index.
+#include "kernels.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr uint32_t T_AND_OR = tt((kA & kB) | kC);       // (a & b) | c
+constexpr uint32_t T_OR_AND = tt((kA | kB) & kC);       // (a | b) & c
+constexpr uint32_t T_NOR_AND = tt(~(kA | kB) & kC);     // ~(a | b) & c
+constexpr uint32_t T_ANDN_AND = tt(kA & ~kB & kC);      // a & ~b & c
+constexpr uint32_t T_AND2 = tt(kA & kB);                // a & b
+constexpr uint32_t kOnes = 0x01010101u;
+constexpr uint32_t kSelEven = 0x06040200u;  // bytes 0, 2, 4, 6 of {hi:lo}
+constexpr uint32_t kSelOdd = 0x07050301u;   // bytes 1, 3, 5, 7
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+struct EaHeader {
+    uint32_t magic, R;
+    uint64_t t, t0;
+    uint32_t ok, err;
+};
+
+__device__ __forceinline__ EaHeader* ea_header(unsigned char* ws) {
+    return reinterpret_cast<EaHeader*>(ws);
+}
+
+// Thresholds of one temperature as the update compares them (written by
+// ising_ea_setup).
+struct EaAccept {
+    uint32_t T2, T4, T6;   // 0xFFFFFFFF where the class always flips
+    uint32_t M2, M4, M6;   // need of u = 2, 4, 6 in every byte (0 when always)
+};
+
+// The four sites' bytes of a span (p: parity of their x) and the byte
+// across the span's edge.
+struct Span {
+    uint32_t S, Lf, Rt;
+};
+__device__ __forceinline__ Span split_row(uint2 R, uint32_t X, int p) {
+    const uint32_t ev = perm(R.y, R.x, kSelEven), od = perm(R.y, R.x, kSelOdd);
+    Span s;
+    s.S = p ? od : ev;
+    s.Lf = p ? ev : ((od << 8) | X);
+    s.Rt = p ? ((ev >> 8) | (X << 24)) : od;
+    return s;
+}
+
+// bit 1 of each byte set where J s_i s_j = -1
+__device__ __forceinline__ uint32_t unsat(uint32_t a, uint32_t b, uint32_t j) {
+    return xor3(a, b, j) & 0x02020202u;
+}
+
+__global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* spins,
+                               const int8_t* bonds, int L, int R, int c, Key key) {
+    EaHeader* hd = ea_header(ws);
+    if (hd->ok == 0)
+        return;
+    const int64_t N = (int64_t)L * L * L;
+    const int gpr = L >> 3;
+    const int64_t spans = N >> 3;                   // spans of one colour per replica
+    const int bpr = (int)((spans + 255) >> 8);      // blocks per replica
+    const int r = blockIdx.x / bpr, bi = blockIdx.x - r * bpr;
+    const int64_t gi = (int64_t)bi * 256 + threadIdx.x;
+    int dE = 0;
+    if (gi < spans) {
+        const int k = (int)(gi % gpr);
+        const int64_t rowi = gi / gpr;              // z L + y
+        const int y = (int)(rowi % L), z = (int)(rowi / L);
+        const int p = (y + z + c) & 1;
+        const int x0 = 8 * k;
+        const int64_t LL = (int64_t)L * L;
+        const int64_t row = rowi * L;
+        const int64_t rup = (y == 0 ? row + LL - L : row - L);      // y - 1
+        const int64_t rdn = (y + 1 == L ? row - LL + L : row + L);  // y + 1
+        const int64_t rbk = (z == 0 ? row + N - LL : row - LL);     // z - 1
+        const int64_t rft = (z + 1 == L ? row - N + LL : row + LL); // z + 1
+        const int xe = p ? (x0 + 8 == L ? 0 : x0 + 8) : (x0 == 0 ? L - 1 : x0 - 1);
+        const int8_t* sr = spins + (int64_t)r * N;
+        const int8_t* Jx = bonds;
+        const int8_t* Jy = bonds + N;
+        const int8_t* Jz = bonds + 2 * N;
+        const uint2 Rw = *reinterpret_cast<const uint2*>(sr + row + x0);
+        const Span sp = split_row(Rw, (uint8_t)sr[row + xe], p);
+        const uint32_t sel = p ? kSelOdd : kSelEven;
+        auto at = [&](const int8_t* base, int64_t rb) {
+            const uint2 w = *reinterpret_cast<const uint2*>(base + rb + x0);
+            return perm(w.y, w.x, sel);
+        };
+        // couplings: right bond J_x(n) at the sites; left bond J_x(n - e_x)
+        const uint2 Jxw = *reinterpret_cast<const uint2*>(Jx + row + x0);
+        const uint32_t jev = perm(Jxw.y, Jxw.x, kSelEven), jod = perm(Jxw.y, Jxw.x, kSelOdd);
+        const uint32_t JR = p ? jod : jev;
+        const uint32_t JL = p ? jev : ((jod << 8) | (uint8_t)Jx[row + (x0 == 0 ? L - 1 : x0 - 1)]);
+        const uint32_t a2 = unsat(sp.S, sp.Lf, JL) + unsat(sp.S, sp.Rt, JR) +
+                            unsat(sp.S, at(sr, rup), at(Jy, rup)) +
+                            unsat(sp.S, at(sr, rdn), at(Jy, row)) +
+                            unsat(sp.S, at(sr, rbk), at(Jz, rbk)) +
+                            unsat(sp.S, at(sr, rft), at(Jz, row));
+        // a2 = 2 n_u per byte (0..12); classes on n_u = 0, 1, 2 (bits 0..2 of n_u)
+        // (multi-input logic through bop3 with explicit tables, as elsewhere)
+        const uint32_t nu = (a2 >> 1) & 0x07070707u;
+        const uint32_t b1s = nu >> 1, b2s = nu >> 2;              // bits 1, 2 at bit 0
+        const uint32_t hi = bop3<T_OR_AND>(b1s, b2s, kOnes);      // n_u >= 2
+        const uint32_t is0 = bop3<T_NOR_AND>(nu, hi, kOnes);      // n_u == 0: u = 6
+        const uint32_t is1 = bop3<T_ANDN_AND>(nu, hi, kOnes);     // n_u == 1: u = 4
+        const uint32_t lo2 = bop3<T_NOR_AND>(nu, b2s, kOnes);     // bits 0 and 2 clear
+        const uint32_t is2 = bop3<T_AND2>(b1s, lo2, lo2);         // n_u == 2: u = 2
+        const EaAccept a = reinterpret_cast<const EaAccept*>(ws + lay.thr)[
+            reinterpret_cast<const int32_t*>(ws + lay.tidx)[r]];
+        const uint32_t n6 = bop3<T_OR_AND>(is0, is0 << 1, a.M6);  // 3 where u = 6
+        const uint32_t need = n6 | bop3<T_AND_OR>(is1 << 1, a.M4, is2 & a.M2);
+        U4 rr = {0u, 0u, 0u, 0u};
+        if (need)
+            rr = philox4x32_10({(uint32_t)((row + x0) >> 3), (uint32_t)r,
+                                2u * (uint32_t)hd->t + (uint32_t)c, kTagSite},
+                               key);
+        uint32_t lvl = 4u * kOnes;  // 4 + lvl_j - need_j stays in 1..7
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t rj = u4_get(rr, j);
+            lvl |= ((uint32_t)(rj < a.T2) + (uint32_t)(rj < a.T4) + (uint32_t)(rj < a.T6))
+                   << (8 * j);
+        }
+        const uint32_t fb = ((lvl - need) >> 2) & kOnes;
+        uint32_t fb8 = fb << 8;
+        asm volatile("" : "+v"(fb8));
+        const uint32_t F = fb8 - (fb << 1);  // 0xFE in flipped bytes
+        // dE = 2u = 12 - 4 n_u = 12 - 2 a2 per flip
+        dE = 12 * (int)__popc(fb) - 2 * (int)__builtin_amdgcn_udot4(a2, fb, 0u, false);
+        const uint32_t Fx = perm(F, 0u, p ? 0x05000400u : 0x00050004u);
+        const uint32_t Fy = perm(F, 0u, p ? 0x07000600u : 0x00070006u);
+        *reinterpret_cast<uint2*>(const_cast<int8_t*>(sr) + row + x0) =
+            make_uint2(Rw.x ^ Fx, Rw.y ^ Fy);
+    }
+    // block sum of dE -> partials[c][r][bi]
+    __shared__ int red[4];
+    dE = wave_sum_i32(dE);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = dE;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        reinterpret_cast<int32_t*>(ws + lay.partial)[((int64_t)c * R + r) * bpr + bi] =
+            red[0] + red[1] + red[2] + red[3];
+}
+
+// Per replica: E += sum of both half-sweeps' partials (fixed order); trace.
+__global__ void k_ea_reduce(unsigned char* ws, const EaLayout lay, int R, int bpr, int64_t* trace) {
+    EaHeader* hd = ea_header(ws);
+    if (hd->ok == 0)
+        return;
+    const int r = blockIdx.x;
+    const int32_t* part = reinterpret_cast<const int32_t*>(ws + lay.partial);
+    long long v = 0;
+    for (int i = threadIdx.x; i < bpr; i += blockDim.x)
+        v += (long long)part[(int64_t)r * bpr + i] + part[((int64_t)R + r) * bpr + i];
+    __shared__ long long red[4];
+    v = wave_sum_i64(v);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long* E = reinterpret_cast<long long*>(ws + lay.E);
+        E[r] += red[0] + red[1] + red[2] + red[3];
+        if (trace)
+            trace[(int64_t)(hd->t - hd->t0) * R + r] = E[r];
+    }
+}
+
+// Exchange step after sweep t if due, then t += 1.  One thread per pair.
+__global__ void k_ea_exchange(unsigned char* ws, const EaLayout lay, int R, int every, Key key) {
+    EaHeader* hd = ea_header(ws);
+    if (hd->ok == 0)
+        return;
+    const uint64_t t = hd->t;
+    if (every > 0 && (t + 1) % (uint64_t)every == 0) {
+        const uint64_t m = (t + 1) / (uint64_t)every - 1;
+        const int k = (int)(m & 1) + 2 * (int)threadIdx.x;
+        if (k + 1 < R) {
+            int32_t* perm_ = reinterpret_cast<int32_t*>(ws + lay.perm);
+            int32_t* tidx = reinterpret_cast<int32_t*>(ws + lay.tidx);
+            const long long* E = reinterpret_cast<const long long*>(ws + lay.E);
+            const int32_t a = perm_[k], b = perm_[k + 1];
+            const long long D = E[a] - E[b];
+            bool swap = D <= 0;
+            if (!swap) {
+                if (D & 3) {
+                    atomicOr(&hd->err, kEaErrEnergy);
+                } else {
+                    const EaSwapMeta meta = reinterpret_cast<const EaSwapMeta*>(ws + lay.swap_meta)[k];
+                    const uint64_t q = (uint64_t)(D >> 2);
+                    uint32_t T;
+                    if (q < meta.len)
+                        T = reinterpret_cast<const uint32_t*>(ws + lay.swap_tab)[(int64_t)k * kEaSwapTable + q];
+                    else
+                        T = q < meta.zero_from ? 1u : 0u;
+                    const U4 o = philox4x32_10({(uint32_t)k, (uint32_t)m, 0u, kTagSwap}, key);
+                    swap = o.x < T;
+                }
+            }
+            if (swap) {
+                perm_[k] = b;
+                perm_[k + 1] = a;
+                tidx[b] = k;
+                tidx[a] = k + 1;
+                reinterpret_cast<unsigned long long*>(ws + lay.accepts)[k] += 1;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        hd->t = t + 1;
+}
+
+__global__ void k_ea_prepare(unsigned char* ws, const EaLayout lay, int R, int64_t n, int mode) {
+    EaHeader* hd = ea_header(ws);
+    __shared__ uint32_t bad;
+    if (threadIdx.x == 0) {
+        uint32_t e = (hd->magic == kEaMagic && hd->R == (uint32_t)R) ? 0u : kEaErrNotSetUp;
+        if (e == 0 && mode == kEaPrepareSweep && hd->t + (uint64_t)n > (1ull << 31))
+            e = kEaErrSweepIndex;
+        bad = e;
+        if (e) {
+            hd->err |= e;
+            hd->ok = 0;
+        } else {
+            hd->ok = 1;
+            if (mode == kEaPrepareSweep)
+                hd->t0 = hd->t;
+            if (mode == kEaPrepareInit)
+                hd->t = 0;
+        }
+    }
+    __syncthreads();
+    if (bad == 0 && mode == kEaPrepareInit)
+        for (int i = threadIdx.x; i < R; i += blockDim.x) {
+            reinterpret_cast<int32_t*>(ws + lay.perm)[i] = i;
+            reinterpret_cast<int32_t*>(ws + lay.tidx)[i] = i;
+            reinterpret_cast<long long*>(ws + lay.E)[i] = 0;
+            reinterpret_cast<unsigned long long*>(ws + lay.accepts)[i] = 0;
+        }
+}
+
+__global__ void k_ea_init(unsigned char* ws, int8_t* spins, int L, int R, int start, Key key) {
+    if (ea_header(ws)->ok == 0)
+        return;
+    const int64_t N = (int64_t)L * L * L, words = N >> 2;
+    const int64_t bpr = (words + 255) >> 8;
+    const int r = (int)(blockIdx.x / bpr);
+    const int64_t g = (int64_t)(blockIdx.x - r * bpr) * 256 + threadIdx.x;
+    if (g >= words)
+        return;
+    uint32_t word = 0x01010101u;
+    if (start != 0) {
+        const U4 o = philox4x32_10({(uint32_t)g, (uint32_t)r, 0u, kTagInit}, key);
+        word = ((o.x >> 31) ? 0xFFu : 0x01u) | (((o.y >> 31) ? 0xFFu : 0x01u) << 8) |
+               (((o.z >> 31) ? 0xFFu : 0x01u) << 16) | (((o.w >> 31) ? 0xFFu : 0x01u) << 24);
+    }
+    reinterpret_cast<uint32_t*>(spins + (int64_t)r * N)[g] = word;
+}
+
+// E of every replica (atomic sums of block totals into out[r], zeroed first).
+__global__ void k_ea_energy(unsigned char* ws, const int8_t* spins, const int8_t* bonds, int L,
+                            int R, long long* out) {
+    if (ea_header(ws)->ok == 0)
+        return;
+    const int64_t N = (int64_t)L * L * L;
+    const int64_t bpr = (N + 255) >> 8;
+    const int r = (int)(blockIdx.x / bpr);
+    const int64_t n = (int64_t)(blockIdx.x - r * bpr) * 256 + threadIdx.x;
+    long long e = 0;
+    if (n < N) {
+        const int8_t* s = spins + (int64_t)r * N;
+        const int x = (int)(n % L), y = (int)((n / L) % L), z = (int)(n / ((int64_t)L * L));
+        const int64_t nx = n - x + (x + 1 == L ? 0 : x + 1);
+        const int64_t ny = n + (y + 1 == L ? -(int64_t)(L - 1) * L : L);
+        const int64_t nz = n + (z + 1 == L ? -(int64_t)(L - 1) * L * L : (int64_t)L * L);
+        e = -(long long)s[n] * (bonds[n] * s[nx] + bonds[N + n] * s[ny] + bonds[2 * N + n] * s[nz]);
+    }
+    __shared__ long long red[4];
+    e = wave_sum_i64(e);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = red[0] + red[1] + red[2] + red[3];
+        if (t)
+            atomicAdd(reinterpret_cast<unsigned long long*>(out + r), (unsigned long long)t);
+    }
+}
+
+__global__ void k_ea_fill(long long* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+}  // namespace
+
+EaLayout ea_ws_layout(int L, int R) {
+    EaLayout l;
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t o = 256;
+    l.perm = o;
+    o += up((size_t)R * 4);
+    l.tidx = o;
+    o += up((size_t)R * 4);
+    l.E = o;
+    o += up((size_t)R * 8);
+    l.accepts = o;
+    o += up((size_t)R * 8);
+    l.thr = o;
+    o += up((size_t)R * sizeof(uint32_t) * 6);
+    l.swap_meta = o;
+    o += up((size_t)R * sizeof(EaSwapMeta));
+    l.swap_tab = o;
+    o += up((size_t)R * kEaSwapTable * 4);
+    const int64_t N = (int64_t)L * L * L;
+    l.bpr = (int)(((N >> 3) + 255) >> 8);
+    l.partial = o;
+    o += up((size_t)2 * R * l.bpr * 4);
+    l.bytes = o;
+    return l;
+}
+
+hipError_t launch_ea_prepare(unsigned char* ws, const EaLayout& lay, int R, int64_t n, int mode,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_ea_prepare, dim3(1), dim3(256), 0, st, ws, lay, R, n, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_ea_init(unsigned char* ws, int8_t* spins, int L, int R, int start, Key key,
+                          hipStream_t st) {
+    const int64_t words = (int64_t)L * L * L / 4;
+    hipLaunchKernelGGL(k_ea_init, dim3((unsigned)(R * ((words + 255) / 256))), dim3(256), 0, st, ws,
+                       spins, L, R, start, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_ea_energy(unsigned char* ws, const int8_t* spins, const int8_t* bonds, int L,
+                            int R, long long* out, hipStream_t st) {
+    const int64_t N = (int64_t)L * L * L;
+    hipLaunchKernelGGL(k_ea_fill, dim3((R + 255) / 256), dim3(256), 0, st, out, R);
+    hipLaunchKernelGGL(k_ea_energy, dim3((unsigned)(R * ((N + 255) / 256))), dim3(256), 0, st, ws,
+                       spins, bonds, L, R, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ea_sweep(unsigned char* ws, const EaLayout& lay, int8_t* spins,
+                           const int8_t* bonds, int L, int R, int every, Key key, int64_t* trace,
+                           hipStream_t st) {
+    for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_ea_halfsweep, dim3((unsigned)(R * lay.bpr)), dim3(256), 0, st, ws, lay,
+                           spins, bonds, L, R, c, key);
+    hipLaunchKernelGGL(k_ea_reduce, dim3(R), dim3(256), 0, st, ws, lay, R, lay.bpr, trace);
+    hipLaunchKernelGGL(k_ea_exchange, dim3(1), dim3(512), 0, st, ws, lay, R, every, key);
+    return hipGetLastError();
+}
+
+}  // namespace ising

@@ -163,6 +163,38 @@ hipError_t launch_batch_mh(unsigned char* ws, int count, int8_t* spins, int L_pr
                            const float* lq_prop, const double* beta, Key key, uint32_t draw,
                            int32_t* accepted, hipStream_t st);
 
+// 3D Edwards-Anderson spin glass with replica exchange --------------------
+constexpr uint32_t kEaMagic = 0x31414549u;  // "IEA1"
+constexpr int kEaSwapTable = 4096;          // swap thresholds tabulated per pair
+constexpr uint32_t kEaErrNotSetUp = 1u;
+constexpr uint32_t kEaErrSweepIndex = 4u;
+constexpr uint32_t kEaErrEnergy = 16u;      // an energy difference not a multiple of 4
+enum EaPrepareMode { kEaPrepareSweep = 0, kEaPrepareInit = 1, kEaPrepareMeasure = 2 };
+// Swap thresholds of one pair: T(q) for D = 4q, q < len, from the table;
+// 1 for len <= q < zero_from; 0 beyond (exp underflows).
+struct EaSwapMeta {
+    uint64_t len;
+    uint64_t zero_from;
+};
+// Workspace of a spin-glass run (byte offsets); the header (magic, R,
+// sweep index, ok and error words) is at 0.
+struct EaLayout {
+    size_t perm = 0, tidx = 0, E = 0, accepts = 0, thr = 0, swap_meta = 0, swap_tab = 0;
+    size_t partial = 0, bytes = 0;
+    int bpr = 0;  // blocks per replica of a half-sweep
+};
+EaLayout ea_ws_layout(int L, int R);
+hipError_t launch_ea_prepare(unsigned char* ws, const EaLayout& lay, int R, int64_t n, int mode,
+                             hipStream_t st);
+hipError_t launch_ea_init(unsigned char* ws, int8_t* spins, int L, int R, int start, Key key,
+                          hipStream_t st);
+hipError_t launch_ea_energy(unsigned char* ws, const int8_t* spins, const int8_t* bonds, int L,
+                            int R, long long* out, hipStream_t st);
+// One sweep of all replicas, the energy update and the exchange step.
+hipError_t launch_ea_sweep(unsigned char* ws, const EaLayout& lay, int8_t* spins,
+                           const int8_t* bonds, int L, int R, int every, Key key, int64_t* trace,
+                           hipStream_t st);
+
 // Shared small kernels ------------------------------------------------------
 hipError_t launch_fill_i64(long long* p, int64_t n, long long v, hipStream_t st);
 // out[j] = base + sum_{i<=j} d[i] in place (d == out allowed); base read
