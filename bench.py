@@ -46,11 +46,11 @@ def parse():
                     help="time the one-launch-per-half-sweep kernel instead (same chain)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("single", "batched", "learned"), default="single",
+    ap.add_argument("--workload", choices=("single", "batched", "learned", "ea"), default="single",
                     help="single: one L=4096 bit-packed lattice (default); batched: 1024 INT8 "
                          "lattices of sides 32..256 on a 64-point beta grid in one launch; "
                          "learned: independent samples/s of learned-proposal vs plain chains "
-                         "at L=32")
+                         "at L=32; ea: 3D +-J spin glass L=128, 64 replicas, replica exchange")
     ap.add_argument("--beta", type=float, default=BETA, help="learned: inverse temperature")
     ap.add_argument("--epochs", type=int, default=3, help="learned: training epochs")
     ap.add_argument("--no-autotune", action="store_true",
@@ -352,6 +352,130 @@ def bench_learned(args):
     print(json.dumps(rec), flush=True)
 
 
+def cpu_baseline_ea(J, betas, seed: int, every: int, target_s: float):
+    """The oracle on a bounded sample of the spin-glass workload: all
+    replicas from the same random starts, the first sweeps."""
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    R, L = len(betas), J.shape[1]
+    spins = np.stack([oracle.ea_init(L, oracle.START_RANDOM, seed, r) for r in range(R)])
+    E = np.array([oracle.ea_energy(x, J) for x in spins])
+    perm = np.arange(R, dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.ea_run(spins, J, betas, seed, 0, 1, every, perm, E, trace=False, nthreads=threads)
+    one = time.perf_counter() - t0
+    n = max(1, min(50, int(target_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.ea_run(spins, J, betas, seed, 1, n, every, perm, E, trace=False, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": R * L ** 3 * n / (dt * 1e9), "unit": "spin-flip attempts/ns", "cores": threads,
+            "kind": "oracle",
+            "sample": f"all {R} replicas, sweeps 1..{n} ({dt:.1f} s), exchange every {every}"}
+
+
+def bench_ea(args):
+    import torch
+
+    import paper_2402_06415_amd as lib
+    from paper_2402_06415_amd.workloads import ea_bonds, ea_workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = ea_workload()
+    L, betas, every = wl["L"], wl["beta"], wl["every"]
+    R = len(betas)
+    nsw = args.sweeps if args.sweeps != 1000 else wl["sweeps"]
+    J = ea_bonds(L, wl["bond_seed"])
+    g = lib.SpinGlass(J, betas, seed=wl["seed"], device=dev)
+    # one block of `every` sweeps (4 launches per sweep) captured once and replayed
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        g.sweep(every, every)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g.sweep(every, every)
+    stream = torch.cuda.current_stream()
+    reps = nsw // every
+
+    def step():
+        g.init("random")
+        for _ in range(reps):
+            graph.replay()
+        return g.measure()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g.check()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    sw = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        g.init("random")
+        if k == args.steps - 1:
+            sw[0].record(stream)
+        for _ in range(reps):
+            graph.replay()
+        if k == args.steps - 1:
+            sw[1].record(stream)
+        g.measure()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev[0].elapsed_time(ev[1])
+    sweep_ms = sw[0].elapsed_time(sw[1])
+    blocks = g.rng_blocks()
+    t, perm, E, acc = g.state()
+    g.check()
+    attempts = R * L ** 3 * nsw
+    ms_per_step = total_ms / args.steps
+    achieved_tops = blocks * PHILOX_OPS_PER_BLOCK / (sweep_ms * 1e-3) / 1e12
+    eff_gbs = attempts * 2.0 / (sweep_ms * 1e-3) / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": round(attempts / (ms_per_step * 1e6), 3),
+        "unit": "spin-flip attempts/ns",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {
+            "workload": f"3D Edwards-Anderson +-J glass L={L} (bonds seed {wl['bond_seed']}), {R} "
+                        f"replicas at beta in [0.5, 1.2], exchange every {every} sweeps, {nsw} "
+                        "sweeps per step (HIP-graph replay of one exchange period) + init + recount",
+            "L": L, "replicas": R, "sweeps_per_step": nsw, "every": every,
+            "layout": "int8", "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "TOP/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": None,
+            "kernel": "k_ea_halfsweep (+ reduce and exchange kernels)",
+            "kernel_ms": round(sweep_ms, 3),
+            "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops in the last step",
+        },
+        "hbm_roofline": {"achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(eff_gbs / HBM_PEAK_GBS, 4),
+                         "note": "algorithmic 2 B/attempt (INT8 spins read + written per sweep); "
+                                 "128 MiB of spins + 6 MiB of bonds"},
+        "swap_acceptance": [round(float(a) / (nsw // every / 2), 4) for a in acc],
+        "sweep_index": t,
+    }
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        c = torch.empty_like(a)
+        c.copy_(a)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = 1 << 30
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline_ea(J, betas, wl["seed"], every, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -362,6 +486,8 @@ def main():
         return bench_batched(args)
     if args.workload == "learned":
         return bench_learned(args)
+    if args.workload == "ea":
+        return bench_ea(args)
     import torch
 
     import paper_2402_06415_amd as lib

@@ -47,7 +47,7 @@ extern "C" {
 
 typedef struct ising_ea {
     int32_t abi_version;  /* must equal ISING_ABI_VERSION                     */
-    int32_t L;            /* L % 8 == 0, 8..ISING_EA_MAX_L                      */
+    int32_t L;            /* a power of two, 8..ISING_EA_MAX_L                  */
     int32_t replicas;     /* R, 1..ISING_EA_MAX_REPLICAS                        */
     int32_t reserved;     /* 0                                                  */
     uint64_t seed;        /* Philox key of starts, sweeps and exchanges        */
@@ -95,6 +95,11 @@ ISING_API int ising_ea_measure(const ising_ea *ea, int64_t *E_dev, void *hip_str
  * (accepts_host uint64[R-1]); any output may be NULL. */
 ISING_API int ising_ea_state(const ising_ea *ea, uint64_t *t_host, int32_t *perm_host,
                              int64_t *E_host, uint64_t *accepts_host, void *hip_stream);
+
+/* Read back (synchronising the stream) the Philox blocks the sweeps have
+ * drawn since ising_ea_init (four sites share a block; blocks whose four
+ * sites all flip without a draw are skipped).  Diagnostic only. */
+ISING_API int ising_ea_rng_blocks(const ising_ea *ea, uint64_t *blocks_host, void *hip_stream);
 
 /* Read back and clear the device error word (see ising_check_device_error). */
 ISING_API int ising_ea_check_device_error(const ising_ea *ea, void *hip_stream);

@@ -37,6 +37,7 @@ EXPORTED = (
     "ising_nn_grad", "ising_nn_adam", "ising_nn_sample", "ising_batch_mh",
     "ising_ea_spins_bytes", "ising_ea_workspace_bytes", "ising_ea_setup", "ising_ea_init",
     "ising_ea_sweep", "ising_ea_measure", "ising_ea_state", "ising_ea_check_device_error",
+    "ising_ea_rng_blocks",
 )
 NN_CHANNELS = 16
 NN_MAX_L = 64
@@ -193,6 +194,8 @@ def load_library():
     lib.ising_ea_measure.argtypes = [ea_p, vp, vp]
     lib.ising_ea_state.argtypes = [ea_p, u64p, i32p, P(ctypes.c_int64), u64p, vp]
     lib.ising_ea_check_device_error.argtypes = [ea_p, vp]
+    lib.ising_ea_rng_blocks.argtypes = [ea_p, u64p, vp]
+    lib.ising_ea_rng_blocks.restype = ctypes.c_int
     for name in ("ising_ea_setup", "ising_ea_init", "ising_ea_sweep", "ising_ea_measure",
                  "ising_ea_state", "ising_ea_check_device_error"):
         getattr(lib, name).restype = ctypes.c_int
@@ -421,6 +424,12 @@ def ising_ea_state(ea: ising_ea, stream: int = 0):
         E.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
         acc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), stream))
     return int(t.value), perm, E, acc[:max(R - 1, 0)]
+
+
+def ising_ea_rng_blocks(ea: ising_ea, stream: int = 0) -> int:
+    v = ctypes.c_uint64(0)
+    _check(load_library().ising_ea_rng_blocks(ctypes.byref(ea), ctypes.byref(v), stream))
+    return int(v.value)
 
 
 def ising_ea_check_device_error(ea: ising_ea, stream: int = 0):
@@ -753,3 +762,6 @@ class SpinGlass:
 
     def check(self):
         ising_ea_check_device_error(self.c, self._stream())
+
+    def rng_blocks(self) -> int:
+        return ising_ea_rng_blocks(self.c, self._stream())

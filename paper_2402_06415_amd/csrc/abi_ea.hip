@@ -22,8 +22,8 @@ int validate(const ising_ea* ea) {
     if (ea->abi_version != ISING_ABI_VERSION)
         return set_error(ISING_E_INVALID, "abi_version %d, library has %d", ea->abi_version,
                          ISING_ABI_VERSION);
-    if (ea->L < 8 || ea->L > ISING_EA_MAX_L || (ea->L % 8))
-        return set_error(ISING_E_INVALID, "L = %d: a multiple of 8 in 8..%d", ea->L,
+    if (ea->L < 8 || ea->L > ISING_EA_MAX_L || (ea->L & (ea->L - 1)))
+        return set_error(ISING_E_INVALID, "L = %d: a power of two in 8..%d", ea->L,
                          ISING_EA_MAX_L);
     if (ea->replicas < 1 || ea->replicas > ISING_EA_MAX_REPLICAS)
         return set_error(ISING_E_INVALID, "replicas = %d outside 1..%d", ea->replicas,
@@ -58,7 +58,8 @@ bool threshold(double x, uint32_t* T) {
 extern "C" {
 
 size_t ising_ea_spins_bytes(int32_t L, int32_t replicas) {
-    if (L < 8 || L > ISING_EA_MAX_L || (L % 8) || replicas < 1 || replicas > ISING_EA_MAX_REPLICAS)
+    if (L < 8 || L > ISING_EA_MAX_L || (L & (L - 1)) || replicas < 1 ||
+        replicas > ISING_EA_MAX_REPLICAS)
         return 0;
     return (size_t)replicas * (size_t)L * L * L;
 }
@@ -234,6 +235,20 @@ int ising_ea_state(const ising_ea* ea, uint64_t* t_host, int32_t* perm_host, int
         HIP_TRY(hipMemcpyAsync(accepts_host, ws + lay.accepts, (size_t)(R - 1) * 8,
                                hipMemcpyDeviceToHost, st),
                 "read swap counts");
+    HIP_TRY(hipStreamSynchronize(st), "synchronise");
+    return ISING_OK;
+}
+
+int ising_ea_rng_blocks(const ising_ea* ea, uint64_t* blocks_host, void* hip_stream) {
+    int rc = validate(ea);
+    if (rc)
+        return rc;
+    if (!blocks_host)
+        return set_error(ISING_E_INVALID, "blocks_host is NULL");
+    const EaLayout lay = ising::ea_ws_layout(ea->L, ea->replicas);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    HIP_TRY(hipMemcpyAsync(blocks_host, ws_of(ea) + lay.rng_blocks, 8, hipMemcpyDeviceToHost, st),
+            "read block counter");
     HIP_TRY(hipStreamSynchronize(st), "synchronise");
     return ISING_OK;
 }

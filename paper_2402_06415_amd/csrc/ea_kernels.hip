@@ -71,38 +71,37 @@ __device__ __forceinline__ uint32_t unsat(uint32_t a, uint32_t b, uint32_t j) {
 }
 
 __global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* spins,
-                               const int8_t* bonds, int L, int R, int c, Key key) {
+                               const int8_t* bonds, int lgL, int R, int c, Key key) {
     EaHeader* hd = ea_header(ws);
     if (hd->ok == 0)
         return;
-    const int64_t N = (int64_t)L * L * L;
-    const int gpr = L >> 3;
-    const int64_t spans = N >> 3;                   // spans of one colour per replica
-    const int bpr = (int)((spans + 255) >> 8);      // blocks per replica
-    const int r = blockIdx.x / bpr, bi = blockIdx.x - r * bpr;
-    const int64_t gi = (int64_t)bi * 256 + threadIdx.x;
-    int dE = 0;
-    if (gi < spans) {
-        const int k = (int)(gi % gpr);
-        const int64_t rowi = gi / gpr;              // z L + y
-        const int y = (int)(rowi % L), z = (int)(rowi / L);
+    // grid (spans of a plane / 256, z, replica); L = 2^lgL, 32-bit index math
+    const int L = 1 << lgL, lgG = lgL - 3;          // spans per row: 2^lgG
+    const uint32_t N = 1u << (3 * lgL);
+    const uint32_t LL = 1u << (2 * lgL);
+    const int r = blockIdx.z, z = blockIdx.y;
+    const uint32_t gp = blockIdx.x * 256u + threadIdx.x;  // span within the plane
+    const int bpr = (int)(gridDim.x * gridDim.y);
+    const int bi = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    int dE = 0, nblk = 0;
+    if (gp < (LL >> 3)) {
+        const int y = (int)(gp >> lgG), k = (int)(gp & ((1u << lgG) - 1));
         const int p = (y + z + c) & 1;
         const int x0 = 8 * k;
-        const int64_t LL = (int64_t)L * L;
-        const int64_t row = rowi * L;
-        const int64_t rup = (y == 0 ? row + LL - L : row - L);      // y - 1
-        const int64_t rdn = (y + 1 == L ? row - LL + L : row + L);  // y + 1
-        const int64_t rbk = (z == 0 ? row + N - LL : row - LL);     // z - 1
-        const int64_t rft = (z + 1 == L ? row - N + LL : row + LL); // z + 1
+        const uint32_t row = ((uint32_t)z << (2 * lgL)) | ((uint32_t)y << lgL);
+        const uint32_t rup = (y == 0 ? row + LL - L : row - L);      // y - 1
+        const uint32_t rdn = (y + 1 == L ? row - LL + L : row + L);  // y + 1
+        const uint32_t rbk = (z == 0 ? row + N - LL : row - LL);     // z - 1
+        const uint32_t rft = (z + 1 == L ? row - N + LL : row + LL); // z + 1
         const int xe = p ? (x0 + 8 == L ? 0 : x0 + 8) : (x0 == 0 ? L - 1 : x0 - 1);
-        const int8_t* sr = spins + (int64_t)r * N;
+        const int8_t* sr = spins + (size_t)r * N;
         const int8_t* Jx = bonds;
         const int8_t* Jy = bonds + N;
         const int8_t* Jz = bonds + 2 * N;
         const uint2 Rw = *reinterpret_cast<const uint2*>(sr + row + x0);
         const Span sp = split_row(Rw, (uint8_t)sr[row + xe], p);
         const uint32_t sel = p ? kSelOdd : kSelEven;
-        auto at = [&](const int8_t* base, int64_t rb) {
+        auto at = [&](const int8_t* base, uint32_t rb) {
             const uint2 w = *reinterpret_cast<const uint2*>(base + rb + x0);
             return perm(w.y, w.x, sel);
         };
@@ -130,10 +129,12 @@ __global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* sp
         const uint32_t n6 = bop3<T_OR_AND>(is0, is0 << 1, a.M6);  // 3 where u = 6
         const uint32_t need = n6 | bop3<T_AND_OR>(is1 << 1, a.M4, is2 & a.M2);
         U4 rr = {0u, 0u, 0u, 0u};
-        if (need)
-            rr = philox4x32_10({(uint32_t)((row + x0) >> 3), (uint32_t)r,
+        if (need) {
+            rr = philox4x32_10({(row + (uint32_t)x0) >> 3, (uint32_t)r,
                                 2u * (uint32_t)hd->t + (uint32_t)c, kTagSite},
                                key);
+            nblk = 1;
+        }
         uint32_t lvl = 4u * kOnes;  // 4 + lvl_j - need_j stays in 1..7
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -152,15 +153,21 @@ __global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* sp
         *reinterpret_cast<uint2*>(const_cast<int8_t*>(sr) + row + x0) =
             make_uint2(Rw.x ^ Fx, Rw.y ^ Fy);
     }
-    // block sum of dE -> partials[c][r][bi]
-    __shared__ int red[4];
+    // block sums of dE and of the Philox blocks drawn -> partials[c][r][bi]
+    __shared__ int red[2][4];
     dE = wave_sum_i32(dE);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = dE;
+    nblk = wave_sum_i32(nblk);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = dE;
+        red[1][threadIdx.x >> 6] = nblk;
+    }
     __syncthreads();
-    if (threadIdx.x == 0)
-        reinterpret_cast<int32_t*>(ws + lay.partial)[((int64_t)c * R + r) * bpr + bi] =
-            red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) {
+        const int64_t at = ((int64_t)c * R + r) * bpr + bi;
+        reinterpret_cast<int32_t*>(ws + lay.partial)[at] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        reinterpret_cast<int32_t*>(ws + lay.partial_blk)[at] =
+            red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
 }
 
 // Per replica: E += sum of both half-sweeps' partials (fixed order); trace.
@@ -170,17 +177,25 @@ __global__ void k_ea_reduce(unsigned char* ws, const EaLayout lay, int R, int bp
         return;
     const int r = blockIdx.x;
     const int32_t* part = reinterpret_cast<const int32_t*>(ws + lay.partial);
-    long long v = 0;
-    for (int i = threadIdx.x; i < bpr; i += blockDim.x)
+    const int32_t* pblk = reinterpret_cast<const int32_t*>(ws + lay.partial_blk);
+    long long v = 0, nb = 0;
+    for (int i = threadIdx.x; i < bpr; i += blockDim.x) {
         v += (long long)part[(int64_t)r * bpr + i] + part[((int64_t)R + r) * bpr + i];
-    __shared__ long long red[4];
+        nb += (long long)pblk[(int64_t)r * bpr + i] + pblk[((int64_t)R + r) * bpr + i];
+    }
+    __shared__ long long red[2][4];
     v = wave_sum_i64(v);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = v;
+    nb = wave_sum_i64(nb);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = v;
+        red[1][threadIdx.x >> 6] = nb;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         long long* E = reinterpret_cast<long long*>(ws + lay.E);
-        E[r] += red[0] + red[1] + red[2] + red[3];
+        E[r] += red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        atomicAdd(reinterpret_cast<unsigned long long*>(ws + lay.rng_blocks),
+                  (unsigned long long)(red[1][0] + red[1][1] + red[1][2] + red[1][3]));
         if (trace)
             trace[(int64_t)(hd->t - hd->t0) * R + r] = E[r];
     }
@@ -258,6 +273,8 @@ __global__ void k_ea_prepare(unsigned char* ws, const EaLayout lay, int R, int64
             reinterpret_cast<long long*>(ws + lay.E)[i] = 0;
             reinterpret_cast<unsigned long long*>(ws + lay.accepts)[i] = 0;
         }
+    if (bad == 0 && mode == kEaPrepareInit && threadIdx.x == 0)
+        *reinterpret_cast<unsigned long long*>(ws + lay.rng_blocks) = 0;
 }
 
 __global__ void k_ea_init(unsigned char* ws, int8_t* spins, int L, int R, int start, Key key) {
@@ -319,6 +336,7 @@ __global__ void k_ea_fill(long long* p, int n) {
 EaLayout ea_ws_layout(int L, int R) {
     EaLayout l;
     auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    l.plane_blocks = (int)((((size_t)L * L / 8) + 255) / 256);
     size_t o = 256;
     l.perm = o;
     o += up((size_t)R * 4);
@@ -334,10 +352,13 @@ EaLayout ea_ws_layout(int L, int R) {
     o += up((size_t)R * sizeof(EaSwapMeta));
     l.swap_tab = o;
     o += up((size_t)R * kEaSwapTable * 4);
-    const int64_t N = (int64_t)L * L * L;
-    l.bpr = (int)(((N >> 3) + 255) >> 8);
+    l.bpr = l.plane_blocks * L;
     l.partial = o;
     o += up((size_t)2 * R * l.bpr * 4);
+    l.partial_blk = o;
+    o += up((size_t)2 * R * l.bpr * 4);
+    l.rng_blocks = o;
+    o += 256;
     l.bytes = o;
     return l;
 }
@@ -368,9 +389,12 @@ hipError_t launch_ea_energy(unsigned char* ws, const int8_t* spins, const int8_t
 hipError_t launch_ea_sweep(unsigned char* ws, const EaLayout& lay, int8_t* spins,
                            const int8_t* bonds, int L, int R, int every, Key key, int64_t* trace,
                            hipStream_t st) {
+    int lgL = 0;
+    while ((1 << lgL) < L)
+        ++lgL;
     for (int c = 0; c < 2; ++c)
-        hipLaunchKernelGGL(k_ea_halfsweep, dim3((unsigned)(R * lay.bpr)), dim3(256), 0, st, ws, lay,
-                           spins, bonds, L, R, c, key);
+        hipLaunchKernelGGL(k_ea_halfsweep, dim3((unsigned)lay.plane_blocks, (unsigned)L, (unsigned)R),
+                           dim3(256), 0, st, ws, lay, spins, bonds, lgL, R, c, key);
     hipLaunchKernelGGL(k_ea_reduce, dim3(R), dim3(256), 0, st, ws, lay, R, lay.bpr, trace);
     hipLaunchKernelGGL(k_ea_exchange, dim3(1), dim3(512), 0, st, ws, lay, R, every, key);
     return hipGetLastError();

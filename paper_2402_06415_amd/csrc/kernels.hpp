@@ -180,8 +180,9 @@ struct EaSwapMeta {
 // sweep index, ok and error words) is at 0.
 struct EaLayout {
     size_t perm = 0, tidx = 0, E = 0, accepts = 0, thr = 0, swap_meta = 0, swap_tab = 0;
-    size_t partial = 0, bytes = 0;
-    int bpr = 0;  // blocks per replica of a half-sweep
+    size_t partial = 0, partial_blk = 0, rng_blocks = 0, bytes = 0;
+    int bpr = 0;           // blocks per replica of a half-sweep
+    int plane_blocks = 0;  // blocks per z-plane of a replica
 };
 EaLayout ea_ws_layout(int L, int R);
 hipError_t launch_ea_prepare(unsigned char* ws, const EaLayout& lay, int R, int64_t n, int mode,
