@@ -19,6 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ising_oracle.c")
 _SRC_EA = os.path.join(_HERE, "ea_oracle.c")
+_SRC_XY = os.path.join(_HERE, "xy_oracle.c")
 _LIB = os.path.join(_HERE, "libising_oracle.so")
 
 MODE_SITE = 0
@@ -35,7 +36,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-               "-o", tmp, _SRC, _SRC_EA, "-lm"]
+               "-o", tmp, _SRC, _SRC_EA, _SRC_XY, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
@@ -45,8 +46,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
-                                                                  os.path.getmtime(_SRC_EA)):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+            os.path.getmtime(f) for f in (_SRC, _SRC_EA, _SRC_XY)):
         build(force=True)
     lib = ctypes.CDLL(_LIB)
     u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -105,6 +106,17 @@ def _load():
                                   ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, i32p, i64p, u64p,
                                   i64p, ctypes.c_int]
     lib.oracle_ea_run.restype = ctypes.c_int
+    lib.oracle_xy_init.argtypes = [f64p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                   ctypes.c_uint32]
+    lib.oracle_xy_init.restype = None
+    lib.oracle_xy_energy.argtypes = [f64p, ctypes.c_int]
+    lib.oracle_xy_energy.restype = ctypes.c_double
+    lib.oracle_xy_halfsweep.argtypes = [f64p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double]
+    lib.oracle_xy_halfsweep.restype = ctypes.c_int64
+    lib.oracle_xy_sweep.argtypes = [f64p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_uint64, ctypes.c_int64, ctypes.c_double, f64p, i64p]
+    lib.oracle_xy_sweep.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -305,3 +317,30 @@ def ea_run(spins: np.ndarray, J: np.ndarray, beta, seed: int, t0: int, n: int, e
     if rc:
         raise ValueError("oracle_ea_run rejected its arguments")
     return tr[:n] if trace else None
+
+
+# ------------------------------------------------------------ 2D XY model
+def xy_init(L: int, start: int, seed: int, lattice_id: int = 0) -> np.ndarray:
+    th = np.zeros((L, L), np.float64)
+    _load().oracle_xy_init(_ptr(th, ctypes.c_double), L, start, seed, lattice_id)
+    return th
+
+
+def xy_energy(theta: np.ndarray) -> float:
+    theta = np.ascontiguousarray(theta, np.float64)
+    return float(_load().oracle_xy_energy(_ptr(theta, ctypes.c_double), theta.shape[0]))
+
+
+def xy_halfsweep(theta: np.ndarray, c: int, seed: int, lattice_id: int, t: int, beta: float) -> int:
+    return int(_load().oracle_xy_halfsweep(_ptr(theta, ctypes.c_double), theta.shape[0], c, seed,
+                                           lattice_id, t, float(beta)))
+
+
+def xy_sweep(theta: np.ndarray, seed: int, lattice_id: int, t0: int, n: int, beta: float):
+    """n sweeps in place; returns (energy after each sweep [n], accepted rotations)."""
+    E = np.zeros(max(n, 1), np.float64)
+    acc = ctypes.c_int64(0)
+    if _load().oracle_xy_sweep(_ptr(theta, ctypes.c_double), theta.shape[0], seed, lattice_id, t0,
+                               n, float(beta), _ptr(E, ctypes.c_double), ctypes.byref(acc)):
+        raise ValueError("oracle_xy_sweep rejected its arguments")
+    return E[:n], acc.value
