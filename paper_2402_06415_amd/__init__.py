@@ -12,7 +12,9 @@ from .binding import (  # noqa: F401
     ising_nn_workspace_bytes, ising_nn_round_weights, ising_nn_logq, ising_nn_grad, ising_nn_adam,
     ising_nn_sample, ising_batch_mh, SpinGlass, ising_ea, ising_ea_spins_bytes,
     ising_ea_workspace_bytes, ising_ea_setup, ising_ea_init, ising_ea_sweep, ising_ea_measure,
-    ising_ea_state, ising_ea_check_device_error, ising_ea_rng_blocks,
+    ising_ea_state, ising_ea_check_device_error, ising_ea_rng_blocks, XYLattices, ising_xy,
+    ising_xy_workspace_bytes, ising_xy_init, ising_xy_sweep, ising_xy_energy, ising_xy_state,
+    ising_xy_check_device_error,
     ABI_VERSION, FLAG_GLOBAL_HALFSWEEP, LAYOUT_BIT1, LAYOUT_INT8, START_COLD_UP, START_RANDOM, IsingError, Lattice,
     ising_abi_version, ising_check_device_error, ising_from_int8, ising_init, ising_lattice,
     ising_last_error, ising_measure, ising_rng_blocks, ising_spins_bytes, ising_sweep, ising_thresholds,

@@ -37,7 +37,8 @@ EXPORTED = (
     "ising_nn_grad", "ising_nn_adam", "ising_nn_sample", "ising_batch_mh",
     "ising_ea_spins_bytes", "ising_ea_workspace_bytes", "ising_ea_setup", "ising_ea_init",
     "ising_ea_sweep", "ising_ea_measure", "ising_ea_state", "ising_ea_check_device_error",
-    "ising_ea_rng_blocks",
+    "ising_ea_rng_blocks", "ising_xy_workspace_bytes", "ising_xy_init", "ising_xy_sweep",
+    "ising_xy_energy", "ising_xy_state", "ising_xy_check_device_error",
 )
 NN_CHANNELS = 16
 NN_MAX_L = 64
@@ -93,6 +94,18 @@ class ising_nn(ctypes.Structure):
         ("grad", ctypes.c_void_p),
         ("adam_m", ctypes.c_void_p),
         ("adam_v", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+    ]
+
+
+class ising_xy(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("count", ctypes.c_int32),
+        ("lattice_id0", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+        ("theta", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
     ]
 
@@ -198,6 +211,17 @@ def load_library():
     lib.ising_ea_rng_blocks.restype = ctypes.c_int
     for name in ("ising_ea_setup", "ising_ea_init", "ising_ea_sweep", "ising_ea_measure",
                  "ising_ea_state", "ising_ea_check_device_error"):
+        getattr(lib, name).restype = ctypes.c_int
+    xy_p = P(ising_xy)
+    lib.ising_xy_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.ising_xy_workspace_bytes.restype = ctypes.c_size_t
+    lib.ising_xy_init.argtypes = [xy_p, ctypes.c_int32, vp]
+    lib.ising_xy_sweep.argtypes = [xy_p, ctypes.c_double, ctypes.c_int64, vp, vp]
+    lib.ising_xy_energy.argtypes = [xy_p, vp, vp]
+    lib.ising_xy_state.argtypes = [xy_p, u64p, u64p, vp]
+    lib.ising_xy_check_device_error.argtypes = [xy_p, vp]
+    for name in ("ising_xy_init", "ising_xy_sweep", "ising_xy_energy", "ising_xy_state",
+                 "ising_xy_check_device_error"):
         getattr(lib, name).restype = ctypes.c_int
     if lib.ising_abi_version() != ABI_VERSION:
         raise RuntimeError("libising.so ABI version mismatch")
@@ -434,6 +458,36 @@ def ising_ea_rng_blocks(ea: ising_ea, stream: int = 0) -> int:
 
 def ising_ea_check_device_error(ea: ising_ea, stream: int = 0):
     _check(load_library().ising_ea_check_device_error(ctypes.byref(ea), stream))
+
+
+def ising_xy_workspace_bytes(count: int) -> int:
+    return int(load_library().ising_xy_workspace_bytes(count))
+
+
+def ising_xy_init(xy: ising_xy, start: int, stream: int = 0):
+    _check(load_library().ising_xy_init(ctypes.byref(xy), start, stream))
+
+
+def ising_xy_sweep(xy: ising_xy, beta: float, n: int, E_trace_dev: int = 0, stream: int = 0):
+    _check(load_library().ising_xy_sweep(ctypes.byref(xy), float(beta), int(n),
+                                         E_trace_dev or None, stream))
+
+
+def ising_xy_energy(xy: ising_xy, E_dev: int, stream: int = 0):
+    _check(load_library().ising_xy_energy(ctypes.byref(xy), E_dev, stream))
+
+
+def ising_xy_state(xy: ising_xy, stream: int = 0):
+    t = ctypes.c_uint64(0)
+    acc = np.zeros(xy.count, np.uint64)
+    _check(load_library().ising_xy_state(ctypes.byref(xy), ctypes.byref(t),
+                                         acc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                         stream))
+    return int(t.value), acc
+
+
+def ising_xy_check_device_error(xy: ising_xy, stream: int = 0):
+    _check(load_library().ising_xy_check_device_error(ctypes.byref(xy), stream))
 
 
 # ------------------------------------------------------------ torch-backed lattice
@@ -765,3 +819,51 @@ class SpinGlass:
 
     def rng_blocks(self) -> int:
         return ising_ea_rng_blocks(self.c, self._stream())
+
+
+class XYLattices:
+    """`count` independent L x L XY lattices (double angles) on the GPU."""
+
+    def __init__(self, L: int, count: int = 1, seed: int = 1, lattice_id0: int = 0,
+                 start: str = "random", device=None, init: bool = True):
+        import torch
+
+        self.device = torch.device(device or "cuda")
+        self.L, self.count = L, count
+        nw = ising_xy_workspace_bytes(count)
+        if nw == 0 or L < 2 or L % 2 or L > 128:
+            raise IsingError(E_INVALID, f"L={L}, count={count} invalid")
+        self._th_raw, th = _aligned_buffer(count * L * L * 8, self.device)
+        self.theta = th.view(torch.float64).view(count, L, L)
+        self._ws_raw, self.workspace = _aligned_buffer(nw, self.device)
+        self.c = ising_xy(ABI_VERSION, L, count, lattice_id0, seed, self.theta.data_ptr(),
+                          self.workspace.data_ptr())
+        if init:
+            self.init(start)
+
+    _stream = staticmethod(Lattice._stream)
+
+    def init(self, start: str = "random"):
+        ising_xy_init(self.c, {"cold": START_COLD_UP, "random": START_RANDOM}[start], self._stream())
+
+    def sweep(self, beta: float, n: int, trace: bool = True):
+        """n sweeps; returns H after each sweep, double [n, count] (or None)."""
+        import torch
+
+        E = torch.empty((max(n, 1), self.count), dtype=torch.float64, device=self.device) \
+            if trace else None
+        ising_xy_sweep(self.c, beta, n, E.data_ptr() if trace else 0, self._stream())
+        return E[:n] if trace else None
+
+    def energy(self):
+        import torch
+
+        E = torch.empty(self.count, dtype=torch.float64, device=self.device)
+        ising_xy_energy(self.c, E.data_ptr(), self._stream())
+        return E
+
+    def state(self):
+        return ising_xy_state(self.c, self._stream())
+
+    def check(self):
+        ising_xy_check_device_error(self.c, self._stream())

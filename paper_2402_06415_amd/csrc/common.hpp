@@ -23,6 +23,8 @@ constexpr uint32_t kTagInit = 2u;   // random start
 constexpr uint32_t kTagSwap = 5u;      // replica-exchange draws
 constexpr uint32_t kTagNNSample = 6u;  // site draws of the learned proposal
 constexpr uint32_t kTagMH = 7u;        // acceptance draws of whole-lattice moves
+constexpr uint32_t kTagXy = 8u;        // XY trials: new angle and decision
+constexpr uint32_t kTagXyInit = 9u;    // XY random start
 
 struct Key {
     uint32_t k0, k1;

@@ -1,0 +1,208 @@
+// Metropolis Monte Carlo of the 2D classical XY model in double precision.
+//
+// One workgroup owns one lattice: its L*L angles sit in LDS for all n
+// sweeps of a call (L <= 128: 128 KiB).  Within a half-sweep the threads
+// take the sites of one colour in turn; a site's trial reads its four
+// neighbours (the other colour) from LDS and writes its own angle, so the
+// update is in place and race-free.  After each sweep the workgroup sums H
+// for the energy trace.  Every floating-point operation is rounded on its
+// own (no fused multiply-add), as the trial is defined operation by
+// operation.
+#include "kernels.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586;  // nearest double to 2 pi
+
+struct XyHeader {
+    uint32_t magic, count;
+    uint64_t t, t0;
+    uint32_t ok, err;
+};
+
+__device__ __forceinline__ XyHeader* xy_header(unsigned char* ws) {
+    return reinterpret_cast<XyHeader*>(ws);
+}
+
+__device__ __forceinline__ double unit53(uint32_t hi, uint32_t lo) {
+    return (double)((((uint64_t)hi << 32) | lo) >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// H of an L x L lattice (angles `th`, LDS or global), summed into thread 0.
+__device__ __forceinline__ double energy_to0(const double* th, int L, double* red) {
+#pragma clang fp contract(off)
+    double e = 0.0;
+    const int N = L * L;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const int y = n / L, x = n - y * L;
+        const double t = th[n];
+        e -= cos(t - th[y * L + (x + 1 == L ? 0 : x + 1)]) +
+             cos(t - th[(y + 1 == L ? 0 : y + 1) * L + x]);
+    }
+    e = wave_sum_f64(e);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = e;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+            s += red[w];
+    return s;
+}
+
+__global__ void k_xy_init(unsigned char* ws, double* theta, int L, int count, int start, Key key,
+                          uint32_t lid0) {
+    const int j = blockIdx.y;
+    const int N = L * L;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        reinterpret_cast<unsigned long long*>(ws + kXyAccepted)[j] = 0;
+        if (j == 0) {
+            XyHeader* hd = xy_header(ws);
+            hd->magic = kXyMagic;
+            hd->count = (uint32_t)count;
+            hd->t = 0;
+            hd->ok = 0;
+        }
+    }
+    if (n >= N)
+        return;
+    double v = 0.0;
+    if (start != 0) {
+        const U4 o = philox4x32_10({(uint32_t)n, lid0 + (uint32_t)j, 0u, kTagXyInit}, key);
+        v = unit53(o.x, o.y) * kTwoPi;
+    }
+    theta[(int64_t)j * N + n] = v;
+}
+
+__global__ void k_xy_prepare(unsigned char* ws, int count, int64_t n) {
+    XyHeader* hd = xy_header(ws);
+    uint32_t e = (hd->magic == kXyMagic && hd->count == (uint32_t)count) ? 0u : kXyErrNotInit;
+    if (e == 0 && hd->t + (uint64_t)n > (1ull << 31))
+        e = kXyErrSweepIndex;
+    if (e) {
+        hd->err |= e;
+        hd->ok = 0;
+    } else {
+        hd->ok = 1;
+        hd->t0 = hd->t;
+    }
+}
+
+__global__ void k_xy_advance(unsigned char* ws, int64_t n) {
+    XyHeader* hd = xy_header(ws);
+    if (hd->ok)
+        hd->t += (uint64_t)n;
+}
+
+__global__ void __launch_bounds__(256) k_xy_sweep(unsigned char* ws, double* theta, int L,
+                                                  int count, int64_t n, double beta, Key key,
+                                                  uint32_t lid0, double* E_trace) {
+#pragma clang fp contract(off)
+    extern __shared__ double th[];
+    __shared__ double red[4];
+    XyHeader* hd = xy_header(ws);
+    if (hd->ok == 0)
+        return;
+    const int j = blockIdx.x;
+    const uint32_t lid = lid0 + (uint32_t)j;
+    const int N = L * L, half = L >> 1;
+    const uint32_t t0 = (uint32_t)hd->t;
+    double* g = theta + (int64_t)j * N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        th[i] = g[i];
+    __syncthreads();
+    const RoundKeys rk = round_keys(key);
+    unsigned long long acc = 0;
+    for (int64_t sw = 0; sw < n; ++sw) {
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t h = 2u * (t0 + (uint32_t)sw) + (uint32_t)c;
+            for (int q = threadIdx.x; q < (N >> 1); q += blockDim.x) {
+                const int y = q / half, x = 2 * (q - y * half) + ((y + c) & 1);
+                const int row = y * L;
+                const U4 o = philox4x32_10({(uint32_t)q, lid, h, kTagXy}, rk);
+                const double th_new = unit53(o.x, o.y) * kTwoPi;
+                const double p = unit53(o.z, o.w);
+                const double t = th[row + x];
+                const double nb[4] = {th[row + (x + 1 == L ? 0 : x + 1)],
+                                      th[row + (x == 0 ? L - 1 : x - 1)],
+                                      th[(y + 1 == L ? 0 : y + 1) * L + x],
+                                      th[(y == 0 ? L - 1 : y - 1) * L + x]};
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    d += cos(th_new - nb[k]) - cos(t - nb[k]);
+                const double dE = -d;
+                const double P = exp(-beta * dE);
+                if (p < P) {
+                    th[row + x] = th_new;
+                    ++acc;
+                }
+            }
+            __syncthreads();
+        }
+        const double E = energy_to0(th, L, red);
+        if (threadIdx.x == 0 && E_trace)
+            E_trace[sw * count + j] = E;
+    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        g[i] = th[i];
+    // accepted rotations of this lattice
+    __shared__ unsigned long long racc[4];
+    unsigned long long a = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        a += __shfl_xor(a, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        racc[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        reinterpret_cast<unsigned long long*>(ws + kXyAccepted)[j] +=
+            racc[0] + racc[1] + racc[2] + racc[3];
+}
+
+__global__ void k_xy_energy(const double* theta, int L, double* E_out) {
+    __shared__ double red[4];
+    const double E = energy_to0(theta + (int64_t)blockIdx.x * L * L, L, red);
+    if (threadIdx.x == 0)
+        E_out[blockIdx.x] = E;
+}
+
+}  // namespace
+
+size_t xy_workspace_bytes(int count) { return kXyAccepted + (((size_t)count * 8 + 255) & ~(size_t)255); }
+
+hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, int start, Key key,
+                          uint32_t lid0, hipStream_t st) {
+    const int N = L * L;
+    hipLaunchKernelGGL(k_xy_init, dim3((N + 255) / 256, count), dim3(256), 0, st, ws, theta, L,
+                       count, start, key, lid0);
+    return hipGetLastError();
+}
+
+hipError_t launch_xy_sweep(unsigned char* ws, double* theta, int L, int count, int64_t n,
+                           double beta, Key key, uint32_t lid0, double* E_trace, hipStream_t st) {
+    hipLaunchKernelGGL(k_xy_prepare, dim3(1), dim3(1), 0, st, ws, count, n);
+    hipLaunchKernelGGL(k_xy_sweep, dim3(count), dim3(256), (size_t)L * L * sizeof(double), st, ws,
+                       theta, L, count, n, beta, key, lid0, E_trace);
+    hipLaunchKernelGGL(k_xy_advance, dim3(1), dim3(1), 0, st, ws, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_xy_energy(const double* theta, int L, int count, double* E_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_xy_energy, dim3(count), dim3(256), 0, st, theta, L, E_out);
+    return hipGetLastError();
+}
+
+}  // namespace ising

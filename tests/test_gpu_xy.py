@@ -1,0 +1,107 @@
+"""GPU parity of the XY model against the float64 oracle (oracle/xy_oracle.c).
+
+Both sides draw the same Philox trials and evaluate the trial operation by
+operation in double precision without fused multiply-adds, so the angles
+must agree bit for bit: a decision could only differ where p lies within
+the last-place difference of the two libraries' cos/exp of the threshold
+(probability ~1e-16 per trial).  Energies are sums of L^2 cosines in
+different orders: within 1e-12 relative of 2 L^2."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+from test_oracle_xy import _ring_mean_energy
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2402_06415_amd as lib  # noqa: E402
+
+BETA_XY = 1.0 / 0.85
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    lib.load_library()
+    yield
+    torch.cuda.synchronize()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _compare(L, count, beta, seed, chunks, lid0=0, start="random"):
+    say(f"xy L={L} count={count} beta={beta} chunks={chunks}")
+    g = lib.XYLattices(L, count, seed=seed, lattice_id0=lid0, start=start)
+    st = oracle.START_RANDOM if start == "random" else oracle.START_COLD_UP
+    th = [oracle.xy_init(L, st, seed, lid0 + j) for j in range(count)]
+    assert (_host(g.theta) == np.stack(th)).all()
+    t = 0
+    accs = np.zeros(count, np.int64)
+    for n in chunks:
+        E = _host(g.sweep(beta, n))
+        for j in range(count):
+            Eo, a = oracle.xy_sweep(th[j], seed, lid0 + j, t, n, beta)
+            accs[j] += a
+            assert np.allclose(E[:, j], Eo, rtol=0, atol=1e-12 * 2 * L * L), (j, E[:, j], Eo)
+        t += n
+        got = _host(g.theta)
+        for j in range(count):
+            if not (got[j] == th[j]).all():
+                raise AssertionError(f"lattice {j}: {(got[j] != th[j]).sum()} angles differ "
+                                     f"after sweep {t}")
+    gt, gacc = g.state()
+    assert gt == t and (gacc == accs).all()
+    assert np.allclose(_host(g.energy()), [oracle.xy_energy(x) for x in th], rtol=0,
+                       atol=1e-12 * 2 * L * L)
+    g.check()
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 16, 32])
+def test_xy_bit_exact_at_the_papers_temperature(L):
+    _compare(L, 3, BETA_XY, 11, (5, 4), lid0=2)
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.3, 20.0])
+def test_xy_beta_cases(beta):
+    _compare(8, 2, beta, 5, (6,), start="cold" if beta == 20.0 else "random")
+
+
+def test_xy_papers_largest_size():
+    """L = 128 (the paper's largest), ten seeds as in its energy study."""
+    _compare(128, 10, BETA_XY, 21, (10,))
+
+
+def test_xy_sweep_before_init_is_a_device_error():
+    say("xy no init")
+    raw_t, th = lib.binding._aligned_buffer(4 * 4 * 8, "cuda")
+    raw_w, ws = lib.binding._aligned_buffer(lib.ising_xy_workspace_bytes(1), "cuda")
+    th.fill_(0)
+    c = lib.ising_xy(1, 4, 1, 0, 1, th.data_ptr(), ws.data_ptr())
+    lib.ising_xy_sweep(c, 1.0, 3)
+    with pytest.raises(lib.IsingError):
+        lib.ising_xy_check_device_error(c)
+    assert (_host(th) == 0).all()
+
+
+def test_xy_two_by_two_torus_on_the_gpu():
+    """256 GPU chains on the 2x2 torus: <E> against the Bessel closed form."""
+    say("xy 2x2 torus")
+    g = lib.XYLattices(2, 256, seed=17)
+    g.sweep(BETA_XY, 200, trace=False)
+    E = _host(g.sweep(BETA_XY, 4000))
+    blocks = E.reshape(40, -1).mean(axis=1)
+    err = blocks.std(ddof=1) / np.sqrt(40)
+    exact = _ring_mean_energy(BETA_XY)
+    assert abs(blocks.mean() - exact) < 4 * err, (blocks.mean(), exact, err)
