@@ -46,11 +46,13 @@ def parse():
                     help="time the one-launch-per-half-sweep kernel instead (same chain)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("single", "batched", "learned", "ea"), default="single",
+    ap.add_argument("--workload", choices=("single", "batched", "learned", "ea", "xy"),
+                    default="single",
                     help="single: one L=4096 bit-packed lattice (default); batched: 1024 INT8 "
                          "lattices of sides 32..256 on a 64-point beta grid in one launch; "
                          "learned: independent samples/s of learned-proposal vs plain chains "
-                         "at L=32; ea: 3D +-J spin glass L=128, 64 replicas, replica exchange")
+                         "at L=32; ea: 3D +-J spin glass L=128, 64 replicas, replica exchange; "
+                         "xy: the paper's XY model at T=0.85, L=8..128, ten seeds")
     ap.add_argument("--beta", type=float, default=BETA, help="learned: inverse temperature")
     ap.add_argument("--epochs", type=int, default=3, help="learned: training epochs")
     ap.add_argument("--no-autotune", action="store_true",
@@ -476,6 +478,70 @@ def bench_ea(args):
     print(json.dumps(rec), flush=True)
 
 
+# the paper's own XY timing: 42.36 us per MC step at L = 32 (float64, FPGA)
+PAPER_XY_L32_US = 42.36
+
+
+def bench_xy(args):
+    """Time per Monte Carlo step and internal energy U = <H>/L^2 of the XY
+    model at T = 0.85 for L = 8..128, ten independent lattices per size."""
+    import torch
+
+    import paper_2402_06415_amd as lib
+    from paper_2402_06415_amd.analysis import binned_mean
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    beta, seeds, steps = 1.0 / 0.85, 10, (args.sweeps if args.sweeps != 1000 else 10_000)
+    stream = torch.cuda.current_stream()
+    sizes = {}
+    for L in (8, 16, 32, 64, 128):
+        g = lib.XYLattices(L, seeds, seed=1 + L, start="random", device=dev)
+        g.sweep(beta, max(steps // 5, 1), trace=False)  # equilibration
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        E = g.sweep(beta, steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        g.check()
+        U, dU = binned_mean(E.cpu().numpy() / (L * L))
+        _, acc = g.state()
+        sizes[str(L)] = {"us_per_step": round(ms * 1e3 / steps, 3),
+                         "attempts_per_ns_10_lattices": round(seeds * L * L * steps / (ms * 1e6), 4),
+                         "U": round(U, 6), "U_err": round(dU, 6),
+                         "acceptance": round(float(acc.sum()) / (seeds * L * L * (steps + steps // 5)), 4)}
+    l32 = sizes["32"]
+    value = 1024 / (l32["us_per_step"] * 1e3)  # attempts/ns of one L = 32 lattice
+    rec = {
+        "metric": METRIC, "value": round(value, 4), "unit": "spin-flip attempts/ns",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(l32["us_per_step"] / 1e3, 6),
+        "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": round(PAPER_XY_L32_US / l32["us_per_step"], 3),
+        "vs_baseline_note": "paper's FPGA: 42.36 us per MC step at L=32, float64 (its own hardware)",
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"2D XY model, T=0.85, random starts, {steps} MC steps per size, "
+                               f"{seeds} independent lattices per size (value: one L=32 lattice)",
+                   "sizes": [8, 16, 32, 64, 128], "parallelism": "single GPU"},
+        "sizes": sizes,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        th = oracle.xy_init(32, oracle.START_RANDOM, 33, 0)
+        n = 200
+        t0 = time.perf_counter()
+        oracle.xy_sweep(th, 33, 0, 0, n, beta)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": 1024 * n / (dt * 1e9), "unit": "spin-flip attempts/ns",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"one L=32 lattice, {n} MC steps ({dt:.2f} s), "
+                                         f"{dt / n * 1e6:.1f} us per step"}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -488,6 +554,8 @@ def main():
         return bench_learned(args)
     if args.workload == "ea":
         return bench_ea(args)
+    if args.workload == "xy":
+        return bench_xy(args)
     import torch
 
     import paper_2402_06415_amd as lib
