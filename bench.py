@@ -437,6 +437,8 @@ def bench_ea(args):
     attempts = R * L ** 3 * nsw
     ms_per_step = total_ms / args.steps
     achieved_tops = blocks * PHILOX_OPS_PER_BLOCK / (sweep_ms * 1e-3) / 1e12
+    prof = profiled_traffic("k_ea_halfsweep", "ea_L128_R64", "ea_kernels.hip") \
+        if (L == 128 and R == 64) else None
     eff_gbs = attempts * 2.0 / (sweep_ms * 1e-3) / 1e9
     rec = {
         "metric": METRIC,
@@ -455,7 +457,10 @@ def bench_ea(args):
         },
         "roofline": {
             "bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "TOP/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": None,
+            "unit": "TOP/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4),
+            "traffic": round(prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"])
+            if prof else None,
+            "traffic_unit": "bytes per k_ea_halfsweep launch (rocprofv3, copy-scaled)",
             "kernel": "k_ea_halfsweep (+ reduce and exchange kernels)",
             "kernel_ms": round(sweep_ms, 3),
             "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops in the last step",
@@ -609,7 +614,11 @@ def main():
     # effective HBM roofline: 2 bits per attempt (read + write once per sweep)
     alg_bytes = attempts * 0.25
     eff_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    kernel_name = "k_halfsweep_bit1" if args.global_halfsweep else "k_sweep_bit1_tiles"
+    # the library's tile plan (one LDS-resident tile of rows per workgroup,
+    # at most 64 KiB each, one workgroup per CU) covers L <= 8192 on 256 CUs;
+    # larger lattices run one launch per half-sweep from global memory
+    tiles = not args.global_halfsweep and L <= 8192
+    kernel_name = "k_sweep_bit1_tiles" if tiles else "k_halfsweep_bit1"
     prof = profiled_traffic(kernel_name) if (L == 4096 and nsw == 1000) else None
     traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None
     rec = {
@@ -647,7 +656,8 @@ def main():
         "hbm_roofline": {
             "achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(eff_gbs / HBM_PEAK_GBS, 4),
-            "note": "algorithmic 0.25 B/attempt; the 2 MiB lattice stays on chip",
+            "note": "algorithmic 0.25 B/attempt" + ("; the lattice stays in LDS during a call"
+                                                     if tiles else "; lattice in HBM"),
         },
         "E_final": E, "M_final": M,
     }
