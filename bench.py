@@ -62,20 +62,33 @@ def parse():
     return ap.parse_args()
 
 
+# Sources whose text determines each profiled sweep kernel's code.
+KERNEL_SOURCES = {
+    "bit1_kernels.hip": ("bit1_kernels.hip", "common.hpp", "kernels.hpp"),
+    "batch_kernels.hip": ("batch_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp"),
+    "ea_kernels.hip": ("ea_kernels.hip", "common.hpp", "kernels.hpp", "ea.hpp"),
+}
+
+
+def kernel_source_hash(source: str) -> str:
+    """sha256 over the sources that determine the kernels of `source`."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[source]:
+        h.update(open(os.path.join(ROOT, "paper_2402_06415_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def profiled_traffic(kernel_name: str, summary: str = "sweep_bit1_L4096",
                      source: str = "bit1_kernels.hip"):
     """HBM bytes per launch of a sweep kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or
-    None when the kernel source has changed since the counters were taken."""
+    None when the kernel sources have changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{summary}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in (f"paper_2402_06415_amd/csrc/{source}", "paper_2402_06415_amd/csrc/common.hpp",
-              "paper_2402_06415_amd/csrc/kernels.hpp"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if rec.get("kernel") != kernel_name or rec.get("kernel_source_sha256") != h.hexdigest():
+    if rec.get("kernel") != kernel_name or \
+            rec.get("kernel_source_sha256") != kernel_source_hash(source):
         return None
     return rec
 

@@ -10,7 +10,7 @@
 
 #include "abi_common.hpp"
 #include "ising.h"
-#include "kernels.hpp"
+#include "batch.hpp"
 
 namespace {
 

@@ -7,7 +7,7 @@
 
 #include "abi_common.hpp"
 #include "ising_ea.h"
-#include "kernels.hpp"
+#include "ea.hpp"
 
 namespace {
 

@@ -4,7 +4,7 @@
 
 #include "abi_common.hpp"
 #include "ising_nn.h"
-#include "kernels.hpp"
+#include "nn.hpp"
 
 namespace {
 

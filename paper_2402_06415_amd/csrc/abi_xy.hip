@@ -4,7 +4,7 @@
 
 #include "abi_common.hpp"
 #include "ising_xy.h"
-#include "kernels.hpp"
+#include "xy.hpp"
 
 namespace {
 

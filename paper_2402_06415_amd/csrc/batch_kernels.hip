@@ -14,7 +14,7 @@
 // sixteen neighbours, the anti-aligned neighbour counts of the four sites
 // are formed byte-parallel in one register, and the four sites share one
 // Philox4x32-10 block (they are q = 4g..4g+3 of their colour).
-#include "kernels.hpp"
+#include "batch.hpp"
 
 namespace ising {
 

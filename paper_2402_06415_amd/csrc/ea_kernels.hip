@@ -15,7 +15,7 @@
 // Per-block energy changes go to a partials array; a per-sweep kernel sums
 // them in a fixed order, then the exchange kernel (a no-op between
 // exchanges) swaps temperatures and advances the device sweep index.
-#include "kernels.hpp"
+#include "ea.hpp"
 
 namespace ising {
 

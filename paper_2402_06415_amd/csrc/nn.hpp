@@ -1,0 +1,51 @@
+// Host-side launchers of the learned proposal network and of whole-lattice
+// Metropolis-Hastings moves (internal to libising.so).
+#pragma once
+
+#include "batch.hpp"
+
+namespace ising {
+
+constexpr int kNNChannels = 16;
+constexpr int kNNWgradPerBlock = 4096;  // (b, p) pairs per weight-gradient block
+// Byte offsets of the network workspace of max_batch configurations.
+struct NNWs {
+    size_t wexp = 0;          // float[P]: the bfloat16 weights as float
+    size_t h[3] = {0, 0, 0};  // float[B][C][N]: post-ReLU outputs of layers 1-3
+    size_t g[2] = {0, 0};     // float[B][C][N]: gradients, ping-pong
+    size_t dz = 0;            // float[B][N]: gradient of the loss at the logits
+    size_t logq = 0;          // float[B]
+    size_t logq2 = 0;         // float[B]: log q of the negated configurations
+    size_t partial = 0;       // float[chunks][C][C*5+1]: weight-gradient partial sums
+    int chunks = 0;
+    size_t bytes = 0;
+};
+NNWs nn_ws_layout(int L, int max_batch);
+int nn_param_count();
+int nn_wgrad_chunks(int L, int B);
+hipError_t launch_nn_round(const float* master, uint16_t* w, float* wexp, hipStream_t st);
+// Forward pass of B configurations; logq[b] = log q(s_b); with_dz also
+// writes the loss gradient at the logits (for launch_nn_backward).
+hipError_t launch_nn_forward(const int8_t* s, int64_t stride, int B, int L, const NNWs& lay,
+                             unsigned char* ws, float* logq, bool with_dz, float sign,
+                             hipStream_t st);
+// log q_sym(s) = log((q(s) + q(-s)) / 2): two forward passes and a combine.
+hipError_t launch_nn_logq_sym(const int8_t* s, int64_t stride, int B, int L, const NNWs& lay,
+                              unsigned char* ws, float* logq, hipStream_t st);
+// Backward pass after launch_nn_forward(with_dz, logq = ws + lay.logq):
+// writes the gradient into grad and the mean NLL into loss (may be NULL).
+hipError_t launch_nn_backward(const int8_t* s, int64_t stride, int B, int L, const NNWs& lay,
+                              unsigned char* ws, float* grad, float* loss, hipStream_t st);
+hipError_t launch_nn_adam(float* master, float* m, float* v, const float* g, uint16_t* w,
+                          float* wexp, float lr, float b1, float b2, float eps, float c1, float c2,
+                          hipStream_t st);
+size_t nn_sample_lds_bytes(int L);
+hipError_t launch_nn_sample(const float* wexp, int L, int B, Key key, uint32_t chain0,
+                            uint32_t draw, int symmetric, int8_t* s_out, int64_t stride,
+                            float* logq, hipStream_t st);
+hipError_t launch_batch_mh(unsigned char* ws, int count, int8_t* spins, int L_prop,
+                           const int8_t* prop, int64_t pstride, const float* lq_cur,
+                           const float* lq_prop, const double* beta, Key key, uint32_t draw,
+                           int32_t* accepted, hipStream_t st);
+
+}  // namespace ising

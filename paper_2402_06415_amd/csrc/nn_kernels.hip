@@ -7,7 +7,7 @@
 // the kernels read the float32 expansion of those bfloat16 values (`wexp`,
 // exactly the same numbers), because uniform float loads become scalar
 // operands of the FMAs, and accumulate in float32.
-#include "kernels.hpp"
+#include "nn.hpp"
 
 namespace ising {
 

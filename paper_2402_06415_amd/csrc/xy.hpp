@@ -1,0 +1,20 @@
+// Host-side launchers of the 2D XY model (internal to libising.so).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace ising {
+
+constexpr uint32_t kXyMagic = 0x31595849u;   // "IXY1"
+constexpr uint32_t kXyErrNotInit = 1u;
+constexpr uint32_t kXyErrSweepIndex = 4u;
+constexpr size_t kXyAccepted = 256;          // uint64[count]: accepted rotations
+size_t xy_workspace_bytes(int count);
+hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, int start, Key key,
+                          uint32_t lid0, hipStream_t st);
+// prepare (validate, note t), the persistent sweep kernel, advance t
+hipError_t launch_xy_sweep(unsigned char* ws, double* theta, int L, int count, int64_t n,
+                           double beta, Key key, uint32_t lid0, double* E_trace, hipStream_t st);
+hipError_t launch_xy_energy(const double* theta, int L, int count, double* E_out, hipStream_t st);
+
+}  // namespace ising

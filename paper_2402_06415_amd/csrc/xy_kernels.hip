@@ -8,7 +8,7 @@
 // for the energy trace.  Every floating-point operation is rounded on its
 // own (no fused multiply-add), as the trial is defined operation by
 // operation.
-#include "kernels.hpp"
+#include "xy.hpp"
 
 namespace ising {
 
