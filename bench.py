@@ -249,8 +249,10 @@ def bench_batched(args):
 
 # multiply-adds per site of one training step of the proposal network:
 # forward 64 + 2*1280 + 80, input gradients 80 + 2*1280, weight gradients 64 + 2*1280 + 80
-NN_MAC_PER_SITE_TRAIN = (64 + 2 * 1280 + 80) + (80 + 2 * 1280) + (64 + 2 * 1280 + 80)
+NN_MAC_PER_SITE = 64 + 2 * 1280 + 80  # layers 1-4 of the masked network, one site
+NN_MAC_PER_SITE_TRAIN = NN_MAC_PER_SITE + (80 + 2 * 1280) + NN_MAC_PER_SITE
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_MATRIX_PEAK_TFLOPS = 157.3
 
 
 def bench_learned(args):
@@ -310,6 +312,14 @@ def bench_learned(args):
 
     _, learn_ms = timed(run_cycles)
     trl = tr.cpu().numpy()
+    # the dominant kernel of a cycle: the wavefront evaluation (here log q_sym
+    # of the current states, the same kernel as the sampler), timed alone
+    reps = 20
+    lq = torch.empty(chains, dtype=torch.float32, device=dev)
+    net.logq(lc.batch, out=lq, symmetric=True)
+    _, wave_ms = timed(lambda: [net.logq(lc.batch, out=lq, symmetric=True) for _ in range(reps)])
+    wave_ms /= reps
+    wave_tflops = chains * 2 * N * NN_MAC_PER_SITE * 2 / (wave_ms * 1e-3) / 1e12
     rate = float(lc.n_accepted.sum().cpu()) / (cycles * chains)
     lc.batch.check()
 
@@ -357,9 +367,18 @@ def bench_learned(args):
                      "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                      "data_generation_ms": round(gen_ms, 1)},
         "roofline": {
+            "bound": "mfma",
+            "achieved": round(wave_tflops, 3), "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(wave_tflops / FP32_MATRIX_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "k_nn_wave (log q_sym of the current states: 2 waves per configuration)",
+            "kernel_ms": round(wave_ms, 4),
+            "work": f"{chains} configurations x 2 signs x {N} sites x {NN_MAC_PER_SITE} "
+                    "float32 multiply-adds",
+        },
+        "training_roofline": {
             "bound": "fp32-vector",
             "achieved": round(train_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(train_tflops / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+            "frac": round(train_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
             "kernel": "training step (forward + backward + Adam kernels)",
             "work": f"{NN_MAC_PER_SITE_TRAIN} multiply-adds per site per configuration",
         },

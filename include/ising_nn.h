@@ -70,10 +70,13 @@ ISING_API size_t ising_nn_workspace_bytes(int32_t L, int32_t channels, int32_t m
 ISING_API int ising_nn_round_weights(const ising_nn *net, void *hip_stream);
 
 /* log q(s) of `batch` configurations: configuration b is the int8 L x L
- * row-major +1/-1 array at s_dev + b * stride (bytes, >= L*L).  All sites
- * are evaluated in parallel (teacher forcing).  With symmetric = 1 the
- * result is log q_sym(s) = log((q(s) + q(-s)) / 2), the Z2-symmetrised
- * proposal (sample from q, negate the whole lattice with probability 1/2).
+ * row-major +1/-1 array at s_dev + b * stride (bytes, >= L*L).  The sites
+ * are evaluated by the sampler's own code with the given spins in place of
+ * draws (teacher forcing), so that for a configuration written by
+ * ising_nn_sample with the same `symmetric` the result is bitwise the
+ * logq_out the sampler returned.  With symmetric = 1 the result is
+ * log q_sym(s) = log((q(s) + q(-s)) / 2), the Z2-symmetrised proposal
+ * (sample from q, negate the whole lattice with probability 1/2).
  * logq_dev: device float32[batch].  Errors: batch outside 1..max_batch,
  * stride < L*L, symmetric not 0 or 1, NULL pointers, invalid net ->
  * ISING_E_INVALID. */
@@ -95,15 +98,17 @@ ISING_API int ising_nn_grad(const ising_nn *net, const int8_t *s_dev, int64_t st
 ISING_API int ising_nn_adam(const ising_nn *net, float lr, float b1, float b2, float eps,
                             int32_t step, void *hip_stream);
 
-/* Draw `batch` configurations from q, site by site in raster order (the
- * network is evaluated incrementally: each step computes the four layers
- * at the new site only, from row caches of the earlier ones).
+/* Draw `batch` configurations from q, site by site: the sites of one
+ * anti-diagonal x + 2y = t are drawn together for t = 0, 1, ..., 3L - 3,
+ * which respects every dependency of the raster-order factorisation (the
+ * masks reach the row above up to x + 1 and the left neighbour), so the
+ * configuration is the one raster-order sampling gives for the same draws.
  * Configuration b goes to s_out + b * stride and uses chain id chain0 + b
- * in the Philox counter, draw index `draw`; logq_out (float32[batch], may
- * be NULL) receives log q of the drawn configuration as accumulated during
- * sampling.  With symmetric = 1 each configuration is then negated when
- * the top bit of out[0] of counter (2^32 - 1, chain, draw, 6) is set
- * (logq_out still refers to the configuration before the negation). */
+ * in the Philox counter, draw index `draw`.  With symmetric = 1 each
+ * configuration is written negated when the top bit of out[0] of counter
+ * (2^32 - 1, chain, draw, 6) is set.  logq_out (float32[batch], may be
+ * NULL) receives log q of the configuration written (log q_sym with
+ * symmetric = 1), bitwise equal to ising_nn_logq of it. */
 ISING_API int ising_nn_sample(const ising_nn *net, int32_t batch, uint64_t seed, uint32_t chain0,
                               uint32_t draw, int32_t symmetric, int8_t *s_out, int64_t stride,
                               float *logq_out, void *hip_stream);

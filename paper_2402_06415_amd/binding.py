@@ -747,7 +747,9 @@ class Net:
 
     def sample(self, batch: int, seed: int, chain0: int = 0, draw: int = 0, out=None, logq=None,
                symmetric: bool = False):
-        """Draw `batch` configurations; returns (int8 [batch, L, L], float32 [batch])."""
+        """Draw `batch` configurations; returns (int8 [batch, L, L], float32 [batch]):
+        the configurations written and their log q (log q_sym with symmetric),
+        bitwise equal to logq() of the same configurations."""
         import torch
 
         if out is None:

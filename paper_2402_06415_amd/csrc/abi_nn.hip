@@ -88,15 +88,10 @@ int ising_nn_logq(const ising_nn* net, const int8_t* s_dev, int64_t stride, int3
     if (symmetric != 0 && symmetric != 1)
         return set_error(ISING_E_INVALID, "symmetric must be 0 or 1");
     const ising::NNWs lay = ising::nn_ws_layout(net->L, net->max_batch);
-    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    if (symmetric)
-        HIP_TRY(ising::launch_nn_logq_sym(s_dev, stride, batch, net->L, lay, ws_of(net), logq_dev,
-                                          st),
-                "nn forward");
-    else
-        HIP_TRY(ising::launch_nn_forward(s_dev, stride, batch, net->L, lay, ws_of(net), logq_dev,
-                                         false, 1.f, st),
-                "nn forward");
+    HIP_TRY(ising::launch_nn_wave(reinterpret_cast<const float*>(ws_of(net) + lay.wexp), net->L,
+                                  batch, 0, symmetric, s_dev, stride, ising::Key{0u, 0u}, 0u, 0u,
+                                  nullptr, 0, logq_dev, reinterpret_cast<hipStream_t>(hip_stream)),
+            "nn logq");
     return ISING_OK;
 }
 
@@ -153,10 +148,10 @@ int ising_nn_sample(const ising_nn* net, int32_t batch, uint64_t seed, uint32_t 
     if (symmetric != 0 && symmetric != 1)
         return set_error(ISING_E_INVALID, "symmetric must be 0 or 1");
     const ising::NNWs lay = ising::nn_ws_layout(net->L, net->max_batch);
-    HIP_TRY(ising::launch_nn_sample(reinterpret_cast<const float*>(ws_of(net) + lay.wexp), net->L,
-                                    batch, key_of(seed), chain0, draw, symmetric, s_out, stride,
-                                    logq_out,
-                                    reinterpret_cast<hipStream_t>(hip_stream)),
+    HIP_TRY(ising::launch_nn_wave(reinterpret_cast<const float*>(ws_of(net) + lay.wexp), net->L,
+                                  batch, 1, symmetric, nullptr, 0, key_of(seed), chain0, draw,
+                                  s_out, stride, logq_out,
+                                  reinterpret_cast<hipStream_t>(hip_stream)),
             "nn sample");
     return ISING_OK;
 }

@@ -15,7 +15,6 @@ struct NNWs {
     size_t g[2] = {0, 0};     // float[B][C][N]: gradients, ping-pong
     size_t dz = 0;            // float[B][N]: gradient of the loss at the logits
     size_t logq = 0;          // float[B]
-    size_t logq2 = 0;         // float[B]: log q of the negated configurations
     size_t partial = 0;       // float[chunks][C][C*5+1]: weight-gradient partial sums
     int chunks = 0;
     size_t bytes = 0;
@@ -29,9 +28,6 @@ hipError_t launch_nn_round(const float* master, uint16_t* w, float* wexp, hipStr
 hipError_t launch_nn_forward(const int8_t* s, int64_t stride, int B, int L, const NNWs& lay,
                              unsigned char* ws, float* logq, bool with_dz, float sign,
                              hipStream_t st);
-// log q_sym(s) = log((q(s) + q(-s)) / 2): two forward passes and a combine.
-hipError_t launch_nn_logq_sym(const int8_t* s, int64_t stride, int B, int L, const NNWs& lay,
-                              unsigned char* ws, float* logq, hipStream_t st);
 // Backward pass after launch_nn_forward(with_dz, logq = ws + lay.logq):
 // writes the gradient into grad and the mean NLL into loss (may be NULL).
 hipError_t launch_nn_backward(const int8_t* s, int64_t stride, int B, int L, const NNWs& lay,
@@ -39,10 +35,16 @@ hipError_t launch_nn_backward(const int8_t* s, int64_t stride, int B, int L, con
 hipError_t launch_nn_adam(float* master, float* m, float* v, const float* g, uint16_t* w,
                           float* wexp, float lr, float b1, float b2, float eps, float c1, float c2,
                           hipStream_t st);
-size_t nn_sample_lds_bytes(int L);
-hipError_t launch_nn_sample(const float* wexp, int L, int B, Key key, uint32_t chain0,
-                            uint32_t draw, int symmetric, int8_t* s_out, int64_t stride,
-                            float* logq, hipStream_t st);
+// Wavefront evaluation (sites of one anti-diagonal x + 2y at a time, on the
+// matrix cores): with sample = 1 draws B configurations into s_out, else
+// evaluates the B configurations at s_in (teacher forcing); logq (may be
+// NULL in sampling) receives log q, or log q_sym with symmetric = 1.  The
+// two modes give the same bits for the same configuration.  L <= 64.
+size_t nn_wave_lds_bytes(int L, int symmetric);
+hipError_t launch_nn_wave(const float* wexp, int L, int B, int sample, int symmetric,
+                          const int8_t* s_in, int64_t in_stride, Key key, uint32_t chain0,
+                          uint32_t draw, int8_t* s_out, int64_t out_stride, float* logq,
+                          hipStream_t st);
 hipError_t launch_batch_mh(unsigned char* ws, int count, int8_t* spins, int L_prop,
                            const int8_t* prop, int64_t pstride, const float* lq_cur,
                            const float* lq_prop, const double* beta, Key key, uint32_t draw,

@@ -158,15 +158,6 @@ __global__ void k_nn_out(const float* h3, const int8_t* s, int64_t stride, int B
     }
 }
 
-// log q_sym = log((q(s) + q(-s)) / 2) from a = log q(s), b = log q(-s).
-__global__ void k_nn_logsym(const float* a, const float* b, float* out, int B) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < B) {
-        const float x = a[i], y = b[i];
-        out[i] = fmaxf(x, y) + log1pf(expf(-fabsf(x - y))) - 0.69314718055994531f;
-    }
-}
-
 // Mean negative log-likelihood from logq[0..B-1] in a fixed order.
 __global__ void k_nn_loss(const float* logq, int B, float* loss) {
     __shared__ float red[4];
@@ -334,127 +325,269 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
     wexp[i] = bf16_to_f32(h);
 }
 
-// Incremental autoregressive sampling: one wave per configuration.  Each
-// step computes the four layers at the new site only; the earlier sites'
-// activations come from two-row ring buffers in LDS (the masks reach one
-// row up at most), with a zero column on each side for the padding.
-// Lane l holds, for the whole run, the weights it multiplies: layers 2 and
-// 3 split as (co = l / 4, ci in 4 (l % 4) .. +3), layers 1 and 4 use lanes
-// 0..15 (one output channel or one input channel each).
-__global__ void __launch_bounds__(64) k_nn_sample(const float* __restrict__ wexp, int L, Key key,
-                                                  uint32_t chain0, uint32_t draw, int symmetric,
-                                                  int8_t* s_out, int64_t stride, float* logq_out) {
-    extern __shared__ float sh[];
-    const int W2 = L + 2;               // padded row
-    float* sb = sh;                     // [2][W2] spins as +-1.0
-    float* hb[3] = {sb + 2 * W2, sb + 2 * W2 + C * 2 * W2, sb + 2 * W2 + 2 * C * 2 * W2};
-    const int lane = threadIdx.x;
-    const int total = 2 * W2 + 3 * C * 2 * W2;
-    for (int i = lane; i < total; i += 64)
-        sh[i] = 0.f;
-    // per-lane weights
-    const int co = lane >> 2, part = lane & 3;
-    float w1[4] = {0.f, 0.f, 0.f, 0.f}, b1 = 0.f, w4[NTB] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    if (lane < C) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            w1[t] = wexp[NNOff::W1 + lane * 4 + t];
-        b1 = wexp[NNOff::B1 + lane];
-#pragma unroll
-        for (int t = 0; t < NTB; ++t)
-            w4[t] = wexp[NNOff::W4 + lane * NTB + t];
+// Wavefront evaluation of the network, for sampling and for log q.
+//
+// The factorisation is over sites in raster order, and the logits of site
+// (y, x) depend on the sites whose activations its taps read: (y-1, x-1),
+// (y-1, x), (y-1, x+1), (y, x-1) and, above layer 1, (y, x) itself.  All
+// of these lie on earlier anti-diagonals t = x + 2y, so the sites of one
+// anti-diagonal (at most ceil(L/2), one per row) are evaluated together,
+// 3L - 2 steps instead of L^2, and the draws and results are those of the
+// site-by-site order.
+//
+// One wave per configuration and sign.  Lane l = m + 16 kk serves row slot
+// m of each 16-slot tile; each step runs, per tile, the 16 sites as the 16
+// rows of float32 matrix products on the matrix cores
+// (v_mfma_f32_16x16x4_f32): layer 1 is one product over the four mask-A
+// taps, layers 2 and 3 are 20 products over K = 5 taps x 16 channels: the
+// product (tap, q) takes channel 4q + kk in lane kk, and the four chains
+// q = 0..3 (five taps each) accumulate separately and are summed at the
+// end.  Layer 4 (one output) is a per-lane partial over that lane's
+// channels, summed across the four kk lanes.  Activations live in LDS for
+// only four columns (x mod 4): a row reads the row above at x-1..x+1
+// while that row writes x+2.  Channel c is stored at position
+// 4 (c mod 4) + c / 4 so that one 16-byte read gives lane kk its four
+// channels of a tap.  Rows share R = floor((L+1)/2) + 1 ring entries:
+// row y + R starts after row y + 1 has read the last columns of row y.
+//
+// With `symmetric`, a second wave evaluates the negated configuration in
+// step with the first, and the result is log q_sym = log((q(s) + q(-s)) / 2).
+// Each wave adds its log-likelihood terms after the per-step barrier, in
+// the same order in every mode, so that sampling and teacher-forced
+// evaluation of the same configuration give the same bits.
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+struct WaveSlot {
+    int y, x;
+    bool on;
+};
+
+// Row slot s (0 <= s < S, S a power of two >= ceil(L/2)) at step t: the
+// active row congruent to s mod S, if any.
+__device__ __forceinline__ WaveSlot wave_slot(int s, int t, int L, int S) {
+    int ylo = (t - L + 2) >> 1;  // ceil((t - L + 1) / 2)
+    ylo = ylo < 0 ? 0 : ylo;
+    const int yhi = (t >> 1) < L - 1 ? (t >> 1) : L - 1;
+    WaveSlot r;
+    r.y = ylo + ((s - ylo) & (S - 1));
+    r.x = t - 2 * r.y;
+    r.on = r.y <= yhi;
+    return r;
+}
+
+__device__ __forceinline__ int act_at(int layer, int R, int y, int x) {
+    const int ry = y < R ? y : y - R;  // y mod R, as y < L < 2R
+    return ((layer * R + ry) * 4 + (x & 3)) * 16;
+}
+
+__device__ __forceinline__ int chan_pos(int c) { return (c & 3) * 4 + (c >> 2); }
+
+// log sigmoid(v) = -(max(-v, 0) + log1p(e^-|v|)), with log1p(e) taken as
+// log(u) - ((u - 1) - e) / u for u = 1 + e (the rounding of u corrected
+// to first order) on the hardware exp and log.
+__device__ __forceinline__ float log_sigmoid_hw(float v) {
+    const float e = __expf(-fabsf(v));
+    const float u = 1.f + e;
+    return -(fmaxf(-v, 0.f) + (__logf(u) - __fdividef((u - 1.f) - e, u)));
+}
+
+template <int T>
+__global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp, int L, int sample,
+                                                 int symmetric, const int8_t* s_in,
+                                                 int64_t in_stride, Key key, uint32_t chain0,
+                                                 uint32_t draw, int8_t* s_out, int64_t out_stride,
+                                                 float* logq_out) {
+    extern __shared__ __align__(16) float sh[];  // 16-byte reads of four channels
+    __shared__ float red[2];
+    constexpr int S = 16 * T;
+    const int W2 = L + 2, R = (L + 1) / 2 + 1;
+    const int sb_floats = (L * W2 + 3) & ~3;
+    const int layer_floats = R * 4 * C;
+    float* sb = sh;  // [L][L + 2] spins as +-1.0 (unsigned), zero columns 0 and L + 1
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 15, kk = lane >> 4;
+    // per wave: activations [3][R][4][C], then 16 floats kept zero (read for
+    // taps outside the lattice) and 16 floats that absorb writes of idle rows
+    float* act = sh + sb_floats + w * (3 * layer_floats + 2 * C);
+    const int zero_off = 3 * layer_floats, junk_off = zero_off + C;
+    const float sigma = w == 0 ? 1.f : -1.f;
+    const int b = blockIdx.x;
+    for (int i = threadIdx.x; i < sb_floats; i += blockDim.x) {
+        float v = 0.f;
+        const int y = i / W2, xc = i - y * W2;
+        if (!sample && y < L && xc >= 1 && xc <= L)
+            v = (float)s_in[(int64_t)b * in_stride + y * L + xc - 1];
+        sb[i] = v;
     }
-    float wm[2][4][NTB], bm[2];
+    if (lane < C)
+        act[zero_off + lane] = 0.f;
+    // matrix-core operands: B[k = kk][j = m] of every product
+    const float wb1 = wexp[NNOff::W1 + m * 4 + kk];
+    float wb2[20], wb3[20], w4[20];
 #pragma unroll
-    for (int l = 0; l < 2; ++l) {
-        const int wo = l == 0 ? NNOff::W2 : NNOff::W3;
-        bm[l] = wexp[(l == 0 ? NNOff::B2 : NNOff::B3) + co];
+    for (int tap = 0; tap < NTB; ++tap)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int t = 0; t < NTB; ++t)
-                wm[l][j][t] = wexp[wo + (co * C + part * 4 + j) * NTB + t];
-    }
-    const float b4 = wexp[NNOff::B4];
+        for (int q = 0; q < 4; ++q) {
+            const int ci = 4 * q + kk;
+            wb2[tap * 4 + q] = wexp[NNOff::W2 + (m * C + ci) * NTB + tap];
+            wb3[tap * 4 + q] = wexp[NNOff::W3 + (m * C + ci) * NTB + tap];
+            w4[tap * 4 + q] = wexp[NNOff::W4 + ci * NTB + tap];
+        }
+    const float bias1 = wexp[NNOff::B1 + m], bias2 = wexp[NNOff::B2 + m];
+    const float bias3 = wexp[NNOff::B3 + m], bias4 = wexp[NNOff::B4];
     const RoundKeys rk = round_keys(key);
-    const uint32_t chain = chain0 + blockIdx.x;
-    int8_t* out = s_out + (int64_t)blockIdx.x * stride;
-    // symmetric: the configuration is written negated with probability 1/2
-    // (the network still conditions on the drawn, unnegated spins)
+    const uint32_t chain = chain0 + (uint32_t)b;
+    // symmetric sampling writes the configuration negated with probability 1/2
     float out_sign = 1.f;
-    if (symmetric) {
+    if (sample && symmetric) {
         const U4 o = philox4x32_10({0xFFFFFFFFu, chain, draw, kTagNNSample}, rk);
         out_sign = (o.x >> 31) ? -1.f : 1.f;
     }
     __syncthreads();
-    float lq = 0.f;
-    U4 rr = {0u, 0u, 0u, 0u};
-    int y = 0, x = 0;
-    const int N = L * L;
-    for (int i = 0; i < N; ++i) {
-        const int cur = y & 1, prv = cur ^ 1, col = x + 1;
-        // offsets of the five taps inside one channel's [2][W2] buffer
-        const int o0 = prv * W2 + col - 1, o1 = prv * W2 + col, o2 = prv * W2 + col + 1;
-        const int o3 = cur * W2 + col - 1, o4 = cur * W2 + col;
-        if (lane < C) {
-            float a = b1;
-            a = fmaf(w1[0], sb[o0], a);
-            a = fmaf(w1[1], sb[o1], a);
-            a = fmaf(w1[2], sb[o2], a);
-            a = fmaf(w1[3], sb[o3], a);
-            hb[0][lane * 2 * W2 + o4] = fmaxf(a, 0.f);
-        }
-        __syncthreads();
+    float lq[T];
 #pragma unroll
-        for (int l = 0; l < 2; ++l) {
-            const float* hin = hb[l];
-            float a = 0.f;
+    for (int u = 0; u < T; ++u)
+        lq[u] = 0.f;
+    const int steps = 3 * L - 2;
+    for (int t = 0; t < steps; ++t) {
+        // Geometry of the step, shared by the layers: for this lane's site of
+        // each tile the LDS offsets of its five taps (the zero block when the
+        // tap is outside the lattice or the slot idle) and of its spin; for
+        // the four product rows this lane receives, where their results go.
+        WaveSlot g[T];
+        int toff[T][NTB], doff[T][4], spin_in[T], spin_at[T];
+        bool dok[T][4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float* c0 = hin + (part * 4 + j) * 2 * W2;
-                a = fmaf(wm[l][j][0], c0[o0], a);
-                a = fmaf(wm[l][j][1], c0[o1], a);
-                a = fmaf(wm[l][j][2], c0[o2], a);
-                a = fmaf(wm[l][j][3], c0[o3], a);
-                a = fmaf(wm[l][j][4], c0[o4], a);
+        for (int u = 0; u < T; ++u) {
+            g[u] = wave_slot(16 * u + m, t, L, S);
+#pragma unroll
+            for (int tap = 0; tap < NTB; ++tap) {
+                const int yy = g[u].y + tap_dy(tap), xx = g[u].x + tap_dx(tap);
+                const bool ok = g[u].on && yy >= 0 && (unsigned)xx < (unsigned)L;
+                toff[u][tap] = ok ? act_at(0, R, yy, xx) + kk * 4 : zero_off;
             }
-            a += __shfl_xor(a, 1, 64);
-            a += __shfl_xor(a, 2, 64);
-            if (part == 0)
-                hb[l + 1][co * 2 * W2 + o4] = fmaxf(a + bm[l], 0.f);
-            __syncthreads();
-        }
-        float zp = 0.f;
-        if (lane < C) {
-            const float* c0 = hb[2] + lane * 2 * W2;
-            zp = fmaf(w4[0], c0[o0], zp);
-            zp = fmaf(w4[1], c0[o1], zp);
-            zp = fmaf(w4[2], c0[o2], zp);
-            zp = fmaf(w4[3], c0[o3], zp);
-            zp = fmaf(w4[4], c0[o4], zp);
-        }
+            {
+                // layer-1 input of this lane: tap kk (mask A) of its site;
+                // index 0 is the zero column of row 0
+                const int dy = kk < 3 ? -1 : 0, dx = kk < 3 ? kk - 1 : -1;
+                const bool ok = g[u].on && g[u].y + dy >= 0;
+                spin_in[u] = ok ? (g[u].y + dy) * W2 + g[u].x + dx + 1 : 0;
+                spin_at[u] = g[u].on ? g[u].y * W2 + g[u].x + 1 : 0;
+            }
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1)
-            zp += __shfl_xor(zp, off, 64);
-        const float z = __shfl(zp, 0, 64) + b4;
-        if ((i & 3) == 0)
-            rr = philox4x32_10({(uint32_t)(i >> 2), chain, draw, kTagNNSample}, rk);
-        const uint32_t r = u4_get(rr, i & 3);
-        const float pplus = 1.f / (1.f + expf(-z));
-        const float sp = ((double)r < (double)pplus * 4294967296.0) ? 1.f : -1.f;
-        lq += log_sigmoid(sp * z);
-        if (lane == 0) {
-            sb[o4] = sp;
-            out[i] = (int8_t)(out_sign * sp);
+            for (int v = 0; v < 4; ++v) {
+                const WaveSlot d = wave_slot(16 * u + 4 * kk + v, t, L, S);
+                dok[u][v] = d.on;
+                doff[u][v] = d.on ? act_at(0, R, d.y, d.x) + chan_pos(m) : junk_off;
+            }
+        }
+        // layer 1 (mask A): A[i = m][k = kk] is tap kk of site m
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const float a = sigma * sb[spin_in[u]];
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wb1, acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                act[doff[u][v]] = fmaxf(acc[v] + bias1, 0.f);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // layers 2 and 3 (mask B)
+#pragma unroll
+        for (int layer = 1; layer < 3; ++layer) {
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                f4 in[NTB];
+#pragma unroll
+                for (int tap = 0; tap < NTB; ++tap) {
+                    const int o = toff[u][tap] == zero_off
+                                      ? zero_off
+                                      : toff[u][tap] + (layer - 1) * layer_floats;
+                    in[tap] = *reinterpret_cast<const f4*>(act + o);
+                }
+                // four independent accumulation chains (one per q), summed at the end
+                f4 part[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    part[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int tap = 0; tap < NTB; ++tap)
+                        part[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            in[tap][q], layer == 1 ? wb2[tap * 4 + q] : wb3[tap * 4 + q], part[q],
+                            0, 0, 0);
+                }
+                const f4 acc = (part[0] + part[1]) + (part[2] + part[3]);
+                const float bias = layer == 1 ? bias2 : bias3;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    act[dok[u][v] ? doff[u][v] + layer * layer_floats : junk_off] =
+                        fmaxf(acc[v] + bias, 0.f);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // layer 4: partial over this lane's channels, then across the kk lanes
+        float z[T];
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            float part = 0.f;
+#pragma unroll
+            for (int tap = 0; tap < NTB; ++tap) {
+                const int o =
+                    toff[u][tap] == zero_off ? zero_off : toff[u][tap] + 2 * layer_floats;
+                const f4 in = *reinterpret_cast<const f4*>(act + o);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    part = fmaf(w4[tap * 4 + q], in[q], part);
+            }
+            part += __shfl_xor(part, 16, 64);
+            part += __shfl_xor(part, 32, 64);
+            z[u] = part + bias4;
+        }
+        if (sample && w == 0) {
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                if (g[u].on) {
+                    const int i = g[u].y * L + g[u].x;
+                    const U4 o = philox4x32_10({(uint32_t)(i >> 2), chain, draw, kTagNNSample}, rk);
+                    const uint32_t r = u4_get(o, i & 3);
+                    const float pplus = 1.f / (1.f + expf(-z[u]));
+                    const float sp = ((double)r < (double)pplus * 4294967296.0) ? 1.f : -1.f;
+                    if (kk == 0) {
+                        sb[spin_at[u]] = sp;
+                        s_out[(int64_t)b * out_stride + i] = (int8_t)(out_sign * sp);
+                    }
+                }
+            }
         }
         __syncthreads();
-        if (++x == L) {
-            x = 0;
-            ++y;
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const float term = log_sigmoid_hw(sigma * sb[spin_at[u]] * z[u]);
+            lq[u] += g[u].on ? term : 0.f;
         }
     }
-    if (lane == 0 && logq_out)
-        logq_out[blockIdx.x] = lq;
+    float tot = lq[0];
+#pragma unroll
+    for (int u = 1; u < T; ++u)
+        tot += lq[u];
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1)
+        tot += __shfl_xor(tot, off, 64);
+    if (lane == 0)
+        red[w] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0 && logq_out) {
+        float r = red[0];
+        if (symmetric) {
+            const float x = red[0], y = red[1];
+            r = fmaxf(x, y) + log1pf(expf(-fabsf(x - y))) - 0.69314718055994531f;
+        }
+        logq_out[b] = r;
+    }
 }
 
 // E of an L x L int8 lattice (periodic right and down bonds), summed by
@@ -544,8 +677,6 @@ NNWs nn_ws_layout(int L, int max_batch) {
     o += up((size_t)max_batch * N * 4);
     w.logq = o;
     o += up((size_t)max_batch * 4);
-    w.logq2 = o;
-    o += up((size_t)max_batch * 4);
     w.chunks = nn_wgrad_chunks(L, max_batch);
     w.partial = o;
     o += up((size_t)w.chunks * C * (C * NTB + 1) * 4);
@@ -581,19 +712,6 @@ hipError_t launch_nn_forward(const int8_t* s, int64_t stride, int B, int L, cons
                        NNOff::B3, h[2]);
     hipLaunchKernelGGL(k_nn_out, dim3(B), dim3(256), 0, st, h[2], s, stride, B, L, sign, wexp, logq,
                        with_dz ? reinterpret_cast<float*>(ws + lay.dz) : nullptr);
-    return hipGetLastError();
-}
-
-hipError_t launch_nn_logq_sym(const int8_t* s, int64_t stride, int B, int L, const NNWs& lay,
-                              unsigned char* ws, float* logq, hipStream_t st) {
-    float* a = reinterpret_cast<float*>(ws + lay.logq);
-    float* b = reinterpret_cast<float*>(ws + lay.logq2);
-    hipError_t e = launch_nn_forward(s, stride, B, L, lay, ws, a, false, 1.f, st);
-    if (e == hipSuccess)
-        e = launch_nn_forward(s, stride, B, L, lay, ws, b, false, -1.f, st);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_nn_logsym, dim3((B + 255) / 256), dim3(256), 0, st, a, b, logq, B);
     return hipGetLastError();
 }
 
@@ -650,13 +768,27 @@ hipError_t launch_nn_adam(float* master, float* m, float* v, const float* g, uin
     return hipGetLastError();
 }
 
-size_t nn_sample_lds_bytes(int L) { return (size_t)(2 * (L + 2) + 3 * C * 2 * (L + 2)) * 4; }
+size_t nn_wave_lds_bytes(int L, int symmetric) {
+    const size_t sb = ((size_t)L * (L + 2) + 3) & ~(size_t)3;
+    const size_t R = (size_t)(L + 1) / 2 + 1;
+    return (sb + (size_t)(symmetric ? 2 : 1) * (3 * R * 4 * C + 2 * C)) * sizeof(float);
+}
 
-hipError_t launch_nn_sample(const float* wexp, int L, int B, Key key, uint32_t chain0,
-                            uint32_t draw, int symmetric, int8_t* s_out, int64_t stride,
-                            float* logq, hipStream_t st) {
-    hipLaunchKernelGGL(k_nn_sample, dim3(B), dim3(64), nn_sample_lds_bytes(L), st, wexp, L, key,
-                       chain0, draw, symmetric, s_out, stride, logq);
+hipError_t launch_nn_wave(const float* wexp, int L, int B, int sample, int symmetric,
+                          const int8_t* s_in, int64_t in_stride, Key key, uint32_t chain0,
+                          uint32_t draw, int8_t* s_out, int64_t out_stride, float* logq,
+                          hipStream_t st) {
+    const int rows = (L + 1) / 2;  // sites of one anti-diagonal, at most
+    const dim3 block(symmetric ? 128 : 64);
+    const size_t lds = nn_wave_lds_bytes(L, symmetric);
+    if (rows <= 16)
+        hipLaunchKernelGGL(k_nn_wave<1>, dim3(B), block, lds, st, wexp, L, sample, symmetric, s_in,
+                           in_stride, key, chain0, draw, s_out, out_stride, logq);
+    else if (rows <= 32)
+        hipLaunchKernelGGL(k_nn_wave<2>, dim3(B), block, lds, st, wexp, L, sample, symmetric, s_in,
+                           in_stride, key, chain0, draw, s_out, out_stride, logq);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

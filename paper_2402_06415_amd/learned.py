@@ -72,7 +72,6 @@ class LearnedChains:
         self.prop = torch.empty((self.count, L, L), dtype=torch.int8, device=dev)
         self.lq_cur = torch.empty(self.count, dtype=torch.float32, device=dev)
         self.lq_prop = torch.empty(self.count, dtype=torch.float32, device=dev)
-        self.lq_sampled = torch.empty(self.count, dtype=torch.float32, device=dev)
         self.accepted = torch.zeros(self.count, dtype=torch.int32, device=dev)
         self.n_accepted = torch.zeros(self.count, dtype=torch.int64, device=dev)
         self.draw = 0
@@ -83,9 +82,9 @@ class LearnedChains:
 
         self.batch.sweep(self.k, moments=False, trace=trace)
         self.net.logq(self.batch, out=self.lq_cur, symmetric=self.symmetric)
+        # the sampler's log q is bitwise the one logq() would give the proposal
         self.net.sample(self.count, self.seed, chain0=self.lid0, draw=self.draw, out=self.prop,
-                        logq=self.lq_sampled, symmetric=self.symmetric)
-        self.net.logq(self.prop, out=self.lq_prop, symmetric=self.symmetric)
+                        logq=self.lq_prop, symmetric=self.symmetric)
         ising_batch_mh(self.batch.c, self.L, self.prop.data_ptr(), self.L * self.L,
                        self.lq_cur.data_ptr(), self.lq_prop.data_ptr(), self.beta.data_ptr(),
                        self.draw, self.accepted.data_ptr(), torch.cuda.current_stream().cuda_stream)
