@@ -237,14 +237,15 @@ def moments(E_trace, M_trace) -> dict:
     }
 
 
-def batch_sweep(states, betas, seed: int, lattice_id0: int, t0: int, n: int, nthreads: int = 1):
+def batch_sweep(states, betas, seed: int, lattice_id0: int, t0: int, n: int, nthreads: int = 1,
+                mode: int = MODE_SITE):
     """A batch is a set of independent lattices: lattice j runs its own
-    per-site-draw chain with lattice id lattice_id0 + j at betas[j].  Sweeps
-    every state in place from sweep index t0 and returns the moments of
-    each lattice over these n sweeps."""
+    chain (per-site or bit-plane draws, `mode`) with lattice id
+    lattice_id0 + j at betas[j].  Sweeps every state in place from sweep
+    index t0 and returns the moments of each lattice over these n sweeps."""
     out = []
     for j, s in enumerate(states):
-        E, M = sweep(s, MODE_SITE, seed, lattice_id0 + j, t0, n, betas[j], nthreads=nthreads)
+        E, M = sweep(s, mode, seed, lattice_id0 + j, t0, n, betas[j], nthreads=nthreads)
         out.append(moments(E, M))
     return out
 

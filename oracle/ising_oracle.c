@@ -179,8 +179,9 @@ int oracle_init(int8_t *s, int L, int start, uint64_t seed, uint32_t lattice_id)
  * colour is q = n >> 1 (exact for even L).
  *
  * SITE mode : counter (q>>2, lattice_id, h, TAG_SITE), r = out[q & 3].
- * PLANE mode (L % 64 == 0): the sites with q>>5 == g form group g and lane
- *   l = q & 31.  Plane k (k = 0 is the most significant bit) is
+ * PLANE mode (L % 32 == 0): the sites with q>>5 == g form group g and lane
+ *   l = q & 31 (one row holds L/2 compact indices: a group lies within one
+ *   row when L % 64 == 0 and spans two consecutive rows when L % 64 == 32).  Plane k (k = 0 is the most significant bit) is
  *   P_k = out[k & 3] of counter (g, lattice_id, h, TAG_PLANE | (k>>2) << 8),
  *   and r = sum_k ((P_k >> l) & 1) << (31 - k).
  * ------------------------------------------------------------------- */
@@ -191,7 +192,7 @@ int oracle_fill_uniforms(int L, int mode, uint64_t seed, uint32_t lattice_id,
         nthreads = 1;
     if (L < 4 || (L & 1) || (c != 0 && c != 1))
         return 1;
-    if (mode == MODE_PLANE && (L % 64) != 0)
+    if (mode == MODE_PLANE && (L % 32) != 0)
         return 1;
     if (t >= (1ull << 31))
         return 1;
@@ -213,8 +214,8 @@ int oracle_fill_uniforms(int L, int mode, uint64_t seed, uint32_t lattice_id,
         return 0;
     }
     if (mode == MODE_PLANE) {
-        /* Group g holds compact indices 32g .. 32g+31; with L % 64 == 0 they
-         * are all in one row and all of colour c for the site list below. */
+        /* Group g holds compact indices 32g .. 32g+31 of colour c, in one
+         * row or (L % 64 == 32) in two; the site list below maps each back. */
         int64_t groups = N / 64; /* N/2 compact indices of colour c, 32 per group */
 #ifdef _OPENMP
 #pragma omp parallel for num_threads(nthreads) schedule(static)
@@ -317,7 +318,7 @@ int oracle_sweep(int8_t *s, int L, int mode, uint64_t seed, uint32_t lattice_id,
         return 1;
     if (mode != MODE_SITE && mode != MODE_PLANE)
         return 1;
-    if (mode == MODE_PLANE && (L % 64) != 0)
+    if (mode == MODE_PLANE && (L % 32) != 0)
         return 1;
     if (t0 + (uint64_t)n > (1ull << 31))
         return 1;

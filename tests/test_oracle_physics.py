@@ -74,6 +74,13 @@ def test_L64_plane_mode_critical_energy_matches_kaufman():
     _close(e, want, nbins=20)
 
 
+def test_L32_plane_mode_critical_energy_matches_kaufman():
+    # L % 64 == 32: every draw group spans two rows
+    want = exact.kaufman_energy(BC, 32)
+    e, _, _ = _series(32, PLANE, 11, BC, 40_000, start=oracle.START_RANDOM)
+    _close(e, want, nbins=20)
+
+
 def test_L64_disordered_energy_matches_onsager():
     # xi(0.3) ~ 1.4 lattice spacings: the L = 64 torus is infinite to 1e-12
     want = exact.onsager_energy(0.3)

@@ -248,8 +248,10 @@ def test_site_mode_counter_layout(torch_philox):
         assert int(r[y, x]) == int(out[j])
 
 
-def test_plane_mode_counter_layout(torch_philox):
-    L, seed, lid, t, c = 64, 12345, 0, 3, 0
+@pytest.mark.parametrize("L,c", [(64, 0), (32, 1), (96, 0)])
+def test_plane_mode_counter_layout(torch_philox, L, c):
+    # L = 32 and 96: a group of 32 compact indices spans two rows
+    seed, lid, t = 12345, 0, 3
     r = oracle.fill_uniforms(L, oracle.MODE_PLANE, seed, lid, t, c)
     rng = np.random.default_rng(0)
     picks = [(int(y), int(x)) for y, x in zip(rng.integers(0, L, 40), rng.integers(0, L, 40))]
@@ -288,6 +290,7 @@ def test_uniforms_are_uniform_and_decorrelated(mode):
     assert np.all(np.abs(bits - 0.5) < 5 * 0.5 / np.sqrt(n))
 
 
-def test_plane_mode_requires_L_multiple_of_64():
-    with pytest.raises(ValueError):
-        oracle.fill_uniforms(32, oracle.MODE_PLANE, 1, 0, 0, 0)
+def test_plane_mode_requires_L_multiple_of_32():
+    for L in (48, 16):
+        with pytest.raises(ValueError):
+            oracle.fill_uniforms(L, oracle.MODE_PLANE, 1, 0, 0, 0)
