@@ -157,7 +157,7 @@ def test_lattice_id_and_seed_select_independent_streams():
     assert (runs[0] != runs[1]).any() and (runs[0] != runs[2]).any()
 
 
-@pytest.mark.parametrize("L,mode,t0,n", [(7, SITE, 0, 1), (2, SITE, 0, 1), (32, PLANE, 0, 1),
+@pytest.mark.parametrize("L,mode,t0,n", [(7, SITE, 0, 1), (2, SITE, 0, 1), (48, PLANE, 0, 1),
                                          (16, SITE, 0, -1), (16, SITE, 2 ** 31, 1),
                                          (16, SITE, 2 ** 31 - 1, 2)])
 def test_sweep_rejects_bad_arguments(L, mode, t0, n):
