@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=3, help="learned: training epochs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched: keep the library's default launch shape")
+    ap.add_argument("--draws", choices=("plane", "site"), default="plane",
+                    help="batched: bit-plane draws (32 sites per lane) or per-site draws (INT8)")
     ap.add_argument("--shape", default=None,
                     help="batched: launch shape THREADS,GROUPS_PER_CU instead of autotuning")
     return ap.parse_args()
@@ -64,9 +66,11 @@ def parse():
 
 # Sources whose text determines each profiled sweep kernel's code.
 KERNEL_SOURCES = {
-    "bit1_kernels.hip": ("bit1_kernels.hip", "common.hpp", "kernels.hpp"),
+    "bit1_kernels.hip": ("bit1_kernels.hip", "common.hpp", "kernels.hpp", "bitslice.hpp"),
     "batch_kernels.hip": ("batch_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp"),
     "ea_kernels.hip": ("ea_kernels.hip", "common.hpp", "kernels.hpp", "ea.hpp"),
+    "batch_bit_kernels.hip": ("batch_bit_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp",
+                              "bitslice.hpp"),
 }
 
 
@@ -117,20 +121,21 @@ def cpu_baseline(L: int, seed: int, target_s: float):
     }
 
 
-def cpu_baseline_batched(L, beta, seed: int, target_s: float):
+def cpu_baseline_batched(L, beta, seed: int, target_s: float, draws: str = "plane"):
     """The oracle on a bounded sample of the batched workload: the first
     sweeps of the first lattices, each lattice's chain as in the batch."""
     import oracle
 
+    mode = oracle.MODE_PLANE if draws == "plane" else oracle.MODE_SITE
     threads = max(1, min(16, os.cpu_count() or 1))
     m = 64  # lattices in the sample: one full period of the beta grid
     states = [oracle.init(int(L[j]), oracle.START_RANDOM, seed, j) for j in range(m)]
     t0 = time.perf_counter()
-    oracle.batch_sweep(states, beta[:m], seed, 0, 0, 1, nthreads=threads)
+    oracle.batch_sweep(states, beta[:m], seed, 0, 0, 1, nthreads=threads, mode=mode)
     one = time.perf_counter() - t0
     n = max(1, min(1000, int(target_s / max(one, 1e-6))))
     t0 = time.perf_counter()
-    oracle.batch_sweep(states, beta[:m], seed, 0, 1, n, nthreads=threads)
+    oracle.batch_sweep(states, beta[:m], seed, 0, 1, n, nthreads=threads, mode=mode)
     dt = time.perf_counter() - t0
     spins = int(sum(int(L[j]) ** 2 for j in range(m)))
     return {
@@ -139,7 +144,7 @@ def cpu_baseline_batched(L, beta, seed: int, target_s: float):
         "cores": threads,
         "kind": "oracle",
         "sample": f"lattices 0..{m - 1} of the batch ({spins} spins), sweeps 1..{n} ({dt:.1f} s), "
-                  "per-site draws, OpenMP over rows of one colour",
+                  f"{draws} draws, OpenMP over rows (site) or draw groups (plane) of one colour",
     }
 
 
@@ -154,7 +159,9 @@ def bench_batched(args):
     torch.cuda.set_device(dev)
     seed, nsw = 11, (args.sweeps if args.sweeps != 1000 else 10_000)
     L, beta = batched_workload(seed=seed)
-    b = lib.Batch(L, beta, seed=seed, start="random", device=dev)
+    b = lib.Batch(L, beta, seed=seed, start="random", device=dev, draws=args.draws)
+    plane = args.draws == "plane"
+    kernel = "k_batch_sweep_bit" if plane else "k_batch_sweep"
     tune = None
     if args.shape:
         b.c.threads, b.c.groups_per_cu = (int(v) for v in args.shape.split(","))
@@ -198,7 +205,8 @@ def bench_batched(args):
     achieved_tops = blocks * PHILOX_OPS_PER_BLOCK / (sweep_ms * 1e-3) / 1e12
     alg_bytes = attempts * 2.0  # INT8: read and write each spin once per sweep
     eff_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    prof = profiled_traffic("k_batch_sweep", "batch_int8_1024", "batch_kernels.hip") \
+    prof = (profiled_traffic(kernel, "batch_plane_1024", "batch_bit_kernels.hip") if plane else
+            profiled_traffic(kernel, "batch_int8_1024", "batch_kernels.hip")) \
         if nsw == 10_000 else None
     traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None
     rec = {
@@ -214,7 +222,9 @@ def bench_batched(args):
                         f"(seed {seed}), 64-point beta grid in [0.30, 0.60], random starts, "
                         f"{nsw} sweeps in one persistent launch + init + recount per step",
             "lattices": int(b.count), "spins": spins, "sweeps_per_step": nsw, "seed": seed,
-            "layout": "int8", "parallelism": "single GPU",
+            "draws": args.draws,
+            "layout": "int8 in HBM, colour bit planes in LDS" if plane else "int8",
+            "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "alu",
@@ -224,7 +234,7 @@ def bench_batched(args):
             "frac": round(achieved_tops / VALU_PEAK_TOPS, 4),
             "traffic": round(traffic) if traffic else None,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "kernel": "k_batch_sweep",
+            "kernel": kernel,
             "kernel_ms": round(sweep_ms, 4),
             "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops per launch",
             "valu_issue_utilisation": round(prof["valu_utilisation"], 3) if prof else None,
@@ -243,7 +253,7 @@ def bench_batched(args):
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline_batched(L, beta, seed, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline_batched(L, beta, seed, args.cpu_seconds, args.draws)
     print(json.dumps(rec), flush=True)
 
 

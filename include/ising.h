@@ -162,13 +162,18 @@ ISING_API int ising_check_device_error(const ising_lattice *lat, void *hip_strea
 /* ------------------------------------------------------------------------
  * Batches of small lattices in one persistent launch.
  *
- * Many independent L x L lattices (INT8 layout, SITE draws, each with its
- * own beta), for example a grid of temperatures, a set of replicas or the
- * independent chains of a finite-size study.  The update rule, draws and
- * observables are those above, applied to every lattice; lattice j of the
- * batch draws with lattice_id = lattice_id0 + j.  One workgroup owns one
- * lattice at a time and keeps it in LDS for all n sweeps of a call; the
- * workgroups take lattices from a device work queue, largest L first.
+ * Many independent L x L lattices (INT8 in memory, each with its own beta),
+ * for example a grid of temperatures, a set of replicas or the independent
+ * chains of a finite-size study.  The update rule and observables are those
+ * above, applied to every lattice; lattice j of the batch draws with
+ * lattice_id = lattice_id0 + j, either per site (ISING_DRAWS_SITE: the
+ * draws of an INT8 lattice, any L % 8 == 0) or as bit planes
+ * (ISING_DRAWS_PLANE: the draws of a BIT1 lattice, generalised to L = 32,
+ * where a group of 32 compact columns spans rows 2g and 2g + 1; every L
+ * must be 32 or a multiple of 64).  Each lattice stays in LDS for all n
+ * sweeps of a call, as bytes (site draws) or as two colour bit planes
+ * updated 32 sites per lane (plane draws); workgroups take lattices from
+ * device work queues, largest L first.
  * The sweep index t of the batch lives in device memory (in the
  * workspace) and is advanced on the device, so that the launches of
  * ising_batch_sweep can be captured once in a HIP graph and replayed: each
@@ -177,6 +182,7 @@ ISING_API int ising_check_device_error(const ising_lattice *lat, void *hip_strea
  * ------------------------------------------------------------------------ */
 
 #define ISING_BATCH_MAX_L 256      /* whole lattice in LDS: L*L bytes <= 64 KiB */
+enum { ISING_DRAWS_SITE = 0, ISING_DRAWS_PLANE = 1 };
 #define ISING_BATCH_MAX_COUNT 65536
 
 typedef struct ising_batch {
@@ -190,6 +196,9 @@ typedef struct ising_batch {
                                a multiple of 64 in 64..1024                    */
     int32_t groups_per_cu;  /* workgroups per compute unit: 0 = library choice,
                                else 1..16 (fewer if LDS or threads do not fit) */
+    int32_t draws;          /* ISING_DRAWS_SITE or ISING_DRAWS_PLANE; the same
+                               at setup and at every sweep                     */
+    int32_t reserved;       /* 0                                               */
     uint64_t spins_bytes;   /* size of the spins buffer in bytes               */
     int8_t *spins;          /* device, 256-B aligned: lattice j at byte offset
                                offsets[j] (see ising_batch_spins_bytes),
@@ -216,9 +225,10 @@ ISING_API size_t ising_batch_workspace_bytes(int32_t count);
  * touch the spins or the sweep index, so it may be called again between
  * sweeps to change the temperatures.  The copy is complete when the call
  * returns (it synchronises hip_stream); the host arrays may be freed then.
- * Errors: invalid batch description, an L that is invalid or above max_L,
- * a beta that is negative, NaN or infinite, spins_bytes too small ->
- * ISING_E_INVALID, nothing written. */
+ * Errors: invalid batch description, an L that is invalid or above max_L
+ * (or, with plane draws, neither 32 nor a multiple of 64), a beta that is
+ * negative, NaN or infinite, spins_bytes too small -> ISING_E_INVALID,
+ * nothing written. */
 ISING_API int ising_batch_setup(const ising_batch *b, const int32_t *L_host,
                                 const double *beta_host, void *hip_stream);
 

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libising.so")
 ABI_VERSION = 1
 LAYOUT_INT8 = 0
 LAYOUT_BIT1 = 1
+DRAWS_SITE = 0
+DRAWS_PLANE = 1
 START_COLD_UP = 0
 START_RANDOM = 1
 OK, E_INVALID, E_UNSUPPORTED, E_HIP, E_STATE = 0, 1, 2, 3, 4
@@ -77,6 +79,8 @@ class ising_batch(ctypes.Structure):
         ("max_L", ctypes.c_int32),
         ("threads", ctypes.c_int32),
         ("groups_per_cu", ctypes.c_int32),
+        ("draws", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("spins_bytes", ctypes.c_uint64),
         ("spins", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
@@ -577,10 +581,13 @@ class Lattice:
 
 class Batch:
     """Many small INT8 lattices (sides L_list, temperatures betas) swept in
-    one persistent launch; spins and workspace are torch tensors."""
+    one persistent launch; spins and workspace are torch tensors.  draws:
+    "site" (per-site draws, any L % 8 == 0) or "plane" (bit-plane draws,
+    L = 32 or a multiple of 64, 32 sites per lane)."""
 
     def __init__(self, L_list, betas, seed: int = 1, lattice_id0: int = 0, start: str = "random",
-                 device=None, threads: int = 0, groups_per_cu: int = 0, init: bool = True):
+                 device=None, threads: int = 0, groups_per_cu: int = 0, init: bool = True,
+                 draws: str = "site"):
         import torch
 
         self.device = torch.device(device or "cuda")
@@ -592,8 +599,9 @@ class Batch:
         nw = ising_batch_workspace_bytes(self.count)
         self._spins_raw, self.spins = _aligned_buffer(nb, self.device)
         self._ws_raw, self.workspace = _aligned_buffer(nw, self.device)
+        self.draws = {"site": DRAWS_SITE, "plane": DRAWS_PLANE}[draws]
         self.c = ising_batch(ABI_VERSION, self.count, seed, lattice_id0, int(self.L.max()),
-                             threads, groups_per_cu, nb, self.spins.data_ptr(),
+                             threads, groups_per_cu, self.draws, 0, nb, self.spins.data_ptr(),
                              self.workspace.data_ptr())
         self.set_beta(betas)
         if init:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libising.so")
-SOURCES = ["abi.hip", "abi_batch.hip", "int8_kernels.hip", "bit1_kernels.hip", "batch_kernels.hip", "abi_nn.hip", "nn_kernels.hip", "abi_ea.hip", "ea_kernels.hip", "abi_xy.hip", "xy_kernels.hip"]
+SOURCES = ["abi.hip", "abi_batch.hip", "int8_kernels.hip", "bit1_kernels.hip", "batch_kernels.hip", "batch_bit_kernels.hip", "abi_nn.hip", "nn_kernels.hip", "abi_ea.hip", "ea_kernels.hip", "abi_xy.hip", "xy_kernels.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -46,6 +46,11 @@ int validate(const ising_batch* b) {
                          b->threads);
     if (b->groups_per_cu < 0 || b->groups_per_cu > 16)
         return set_error(ISING_E_INVALID, "groups_per_cu = %d outside 0..16", b->groups_per_cu);
+    if (b->draws != ISING_DRAWS_SITE && b->draws != ISING_DRAWS_PLANE)
+        return set_error(ISING_E_INVALID, "draws = %d: ISING_DRAWS_SITE or ISING_DRAWS_PLANE",
+                         b->draws);
+    if (b->reserved != 0)
+        return set_error(ISING_E_INVALID, "reserved must be 0");
     if (!b->spins || !aligned256(b->spins))
         return set_error(ISING_E_INVALID, "spins must be a non-NULL 256-byte aligned device pointer");
     if (!b->workspace || !aligned256(b->workspace))
@@ -65,8 +70,10 @@ struct Shape {
 };
 
 // Workgroups per CU that fit LDS and the thread limit for this shape.
-int fit_groups(int threads, int want, int max_L) {
-    const size_t lds = ising::batch_lds_bytes(max_L) + 1024;  // + static LDS of the kernel
+int fit_groups(int threads, int want, int max_L, int draws) {
+    const size_t lds = (draws == ISING_DRAWS_PLANE ? ising::batch_bit_lds_bytes(threads, max_L)
+                                                   : ising::batch_lds_bytes(max_L)) +
+                       1024;  // + static LDS of the kernel
     int g = want;
     g = std::min<int>(g, (int)(kLdsPerCU / lds));
     g = std::min<int>(g, kThreadsPerCU / threads);
@@ -78,13 +85,25 @@ int fit_groups(int threads, int want, int max_L) {
 Shape shape_of(const ising_batch* b) {
     Shape s;
     s.threads = b->threads ? b->threads : 512;
-    s.groups_per_cu = fit_groups(s.threads, b->groups_per_cu ? b->groups_per_cu : 16, b->max_L);
+    s.groups_per_cu =
+        fit_groups(s.threads, b->groups_per_cu ? b->groups_per_cu : 16, b->max_L, b->draws);
     return s;
 }
 
 int grid_of(const ising_batch* b, const Shape& s) {
     const int cus = std::max(device_cus(), 1);
     return std::max(1, std::min(b->count, cus * s.groups_per_cu));
+}
+
+// The sweep kernel of the batch's draw mode.
+hipError_t launch_sweep_of(const ising_batch* b, unsigned char* ws, bool scratch_t, int8_t* spins,
+                           int64_t n, int64_t* moments, int64_t* trace, const Shape& s, int grid,
+                           hipStream_t st) {
+    if (b->draws == ISING_DRAWS_PLANE)
+        return ising::launch_batch_sweep_bit(ws, scratch_t, b->count, spins, b->max_L, n,
+                                             key_of(b), moments, trace, s.threads, grid, st);
+    return ising::launch_batch_sweep(ws, scratch_t, b->count, spins, b->max_L, n, key_of(b),
+                                     moments, trace, s.threads, grid, st);
 }
 
 }  // namespace
@@ -119,6 +138,12 @@ int ising_batch_setup(const ising_batch* b, const int32_t* L_host, const double*
     if (!L_host || !beta_host)
         return set_error(ISING_E_INVALID, "L_host and beta_host must be non-NULL");
     const int count = b->count;
+    if (b->draws == ISING_DRAWS_PLANE)
+        for (int j = 0; j < count; ++j)
+            if (L_host[j] != 32 && L_host[j] % 64 != 0)
+                return set_error(ISING_E_INVALID,
+                                 "L[%d] = %d: plane draws need L = 32 or a multiple of 64", j,
+                                 L_host[j]);
     std::vector<uint64_t> off(count);
     for (int j = 0; j < count; ++j)
         if (L_host[j] > b->max_L && valid_batch_L(L_host[j], ISING_BATCH_MAX_L))
@@ -153,9 +178,28 @@ int ising_batch_setup(const ising_batch* b, const int32_t* L_host, const double*
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t c) { return L_host[a] > L_host[c]; });
+    // classes: runs of equal L in the queue order (used by the plane-draw sweep)
+    std::vector<ising::BatchClass> cls;
+    for (int i = 0; i < count; ++i) {
+        const int L = L_host[order[i]];
+        if (cls.empty() || cls.back().L != L)
+            cls.push_back(ising::BatchClass{L, i, 0, 0u});
+        ++cls.back().count;
+    }
+    if (b->draws == ISING_DRAWS_PLANE && cls.size() > (size_t)ising::kBatchMaxClasses)
+        return set_error(ISING_E_INVALID, "more than %d distinct sides", ising::kBatchMaxClasses);
+    const uint32_t ncls = cls.size() <= (size_t)ising::kBatchMaxClasses ? (uint32_t)cls.size() : 0u;
+    cls.resize(ising::kBatchMaxClasses, ising::BatchClass{0, 0, 0, 0u});
+    const uint32_t cls_head[2] = {ncls, (uint32_t)b->draws};
     const uint32_t head[2] = {ising::kBatchMagic, (uint32_t)count};
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     unsigned char* ws = ws_of(b);
+    HIP_TRY(hipMemcpyAsync(ws + BatchWs::kClasses, cls.data(),
+                           cls.size() * sizeof(ising::BatchClass), hipMemcpyHostToDevice, st),
+            "copy class table");
+    HIP_TRY(hipMemcpyAsync(ws + BatchWs::kNClasses, cls_head, sizeof cls_head,
+                           hipMemcpyHostToDevice, st),
+            "copy class count");
     HIP_TRY(hipMemcpyAsync(ws + BatchWs::kOrder, order.data(), order.size() * 4,
                            hipMemcpyHostToDevice, st),
             "copy queue order");
@@ -176,7 +220,7 @@ int ising_batch_init(const ising_batch* b, int32_t start, void* hip_stream) {
         return set_error(ISING_E_INVALID, "unknown start %d", start);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     HIP_TRY(ising::launch_batch_prepare(ws_of(b), false, b->count, b->spins_bytes, b->max_L, 0,
-                                        ising::kPrepareInit, st),
+                                        ising::kPrepareInit, b->draws, st),
             "batch prepare");
     HIP_TRY(ising::launch_batch_init(ws_of(b), b->count, b->spins, start, key_of(b), st),
             "batch init");
@@ -195,10 +239,10 @@ int ising_batch_sweep(const ising_batch* b, int64_t n, int64_t* moments_dev, int
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     const Shape s = shape_of(b);
     HIP_TRY(ising::launch_batch_prepare(ws_of(b), false, b->count, b->spins_bytes, b->max_L, n,
-                                        ising::kPrepareSweep, st),
+                                        ising::kPrepareSweep, b->draws, st),
             "batch prepare");
-    HIP_TRY(ising::launch_batch_sweep(ws_of(b), false, b->count, b->spins, b->max_L, n, key_of(b),
-                                      moments_dev, trace_dev, s.threads, grid_of(b, s), st),
+    HIP_TRY(launch_sweep_of(b, ws_of(b), false, b->spins, n, moments_dev, trace_dev, s,
+                            grid_of(b, s), st),
             "batch sweep");
     HIP_TRY(ising::launch_batch_advance(ws_of(b), n, st), "batch advance");
     return ISING_OK;
@@ -210,7 +254,7 @@ int ising_batch_measure(const ising_batch* b, int64_t* E_dev, int64_t* M_dev, vo
         return rc;
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     HIP_TRY(ising::launch_batch_prepare(ws_of(b), false, b->count, b->spins_bytes, b->max_L, 0,
-                                        ising::kPrepareMeasure, st),
+                                        ising::kPrepareMeasure, b->draws, st),
             "batch prepare");
     HIP_TRY(ising::launch_batch_measure(ws_of(b), b->count, b->spins, E_dev, M_dev, st),
             "batch measure");
@@ -262,10 +306,11 @@ int ising_batch_check_device_error(const ising_batch* b, void* hip_stream) {
         HIP_TRY(hipMemcpyAsync(errp, &zero, sizeof zero, hipMemcpyHostToDevice, st),
                 "clear error word");
         HIP_TRY(hipStreamSynchronize(st), "synchronise");
-        return set_error(ISING_E_STATE, "batch device error word 0x%x:%s%s%s", err,
+        return set_error(ISING_E_STATE, "batch device error word 0x%x:%s%s%s%s", err,
                          (err & ising::kBatchErrNotSetUp) ? " workspace not set up for this batch;" : "",
                          (err & ising::kBatchErrDescriptor) ? " descriptor outside spins or max_L;" : "",
-                         (err & ising::kBatchErrSweepIndex) ? " sweep index + n exceeds 2^31;" : "");
+                         (err & ising::kBatchErrSweepIndex) ? " sweep index + n exceeds 2^31;" : "",
+                         (err & ising::kBatchErrDraws) ? " draw mode differs from setup's;" : "");
     }
     return ISING_OK;
 }
@@ -287,7 +332,7 @@ int ising_batch_autotune(ising_batch* b, int8_t* scratch_spins, int64_t probe_sw
     std::vector<Shape> cand;
     for (int threads : {128, 256, 512, 1024})
         for (int g : {1, 2, 4, 8, 16}) {
-            const int fit = fit_groups(threads, g, b->max_L);
+            const int fit = fit_groups(threads, g, b->max_L, b->draws);
             if (fit != g)
                 continue;
             cand.push_back({threads, g});
@@ -312,15 +357,14 @@ int ising_batch_autotune(ising_batch* b, int8_t* scratch_spins, int64_t probe_sw
                                  hipMemcpyDeviceToDevice, st);
         if (err == hipSuccess)
             err = ising::launch_batch_prepare(ws, true, b->count, b->spins_bytes, b->max_L,
-                                              probe_sweeps, ising::kPrepareSweep, st);
+                                              probe_sweeps, ising::kPrepareSweep, b->draws, st);
         if (err == hipSuccess)
             err = hipEventRecord(e0, st);
         probe.threads = s.threads;
         probe.groups_per_cu = s.groups_per_cu;
         if (err == hipSuccess)
-            err = ising::launch_batch_sweep(ws, true, b->count, scratch_spins, b->max_L,
-                                            probe_sweeps, key_of(b), nullptr, nullptr, s.threads,
-                                            grid_of(&probe, s), st);
+            err = launch_sweep_of(b, ws, true, scratch_spins, probe_sweeps, nullptr, nullptr, s,
+                                  grid_of(&probe, s), st);
         if (err == hipSuccess)
             err = hipEventRecord(e1, st);
         if (err == hipSuccess)

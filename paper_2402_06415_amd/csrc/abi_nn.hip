@@ -175,7 +175,7 @@ int ising_batch_mh(const ising_batch* b, int32_t L_prop, const int8_t* prop_dev,
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     unsigned char* ws = reinterpret_cast<unsigned char*>(b->workspace);
     HIP_TRY(ising::launch_batch_prepare(ws, false, b->count, b->spins_bytes, b->max_L, 0,
-                                        ising::kPrepareMeasure, st),
+                                        ising::kPrepareMeasure, b->draws, st),
             "batch prepare");
     const ising::Key key{(uint32_t)(b->seed & 0xFFFFFFFFu), (uint32_t)(b->seed >> 32)};
     HIP_TRY(ising::launch_batch_mh(ws, b->count, b->spins, L_prop, prop_dev, prop_stride,

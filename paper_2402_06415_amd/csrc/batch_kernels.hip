@@ -196,7 +196,7 @@ __device__ __forceinline__ void count_em(const int8_t* s, int L, long long* red,
 }
 
 __global__ void k_batch_prepare(unsigned char* ws, int scratch_t, int count, uint64_t spins_bytes,
-                                int max_L, int64_t n, int mode) {
+                                int max_L, int64_t n, int mode, int draws) {
     Header* hd = header(ws);
     const BatchDesc* desc = reinterpret_cast<const BatchDesc*>(ws + BatchWs::desc_offset(count));
     const int32_t* order = reinterpret_cast<const int32_t*>(ws + BatchWs::kOrder);
@@ -225,6 +225,8 @@ __global__ void k_batch_prepare(unsigned char* ws, int scratch_t, int count, uin
             const uint64_t t = scratch_t ? hd->t_scratch : hd->t;
             if (t + (uint64_t)n > (1ull << 31))
                 e = kBatchErrSweepIndex;
+            if (*reinterpret_cast<const uint32_t*>(ws + BatchWs::kDraws) != (uint32_t)draws)
+                e |= kBatchErrDraws;
         }
         if (e) {
             hd->err |= e;
@@ -236,6 +238,8 @@ __global__ void k_batch_prepare(unsigned char* ws, int scratch_t, int count, uin
                 hd->t = 0;
         }
     }
+    if (mode == kPrepareSweep && threadIdx.x < kBatchMaxClasses)
+        reinterpret_cast<BatchClass*>(ws + BatchWs::kClasses)[threadIdx.x].next = 0;
     if (mode == kPrepareInit && bad == 0) {
         unsigned long long* slots = reinterpret_cast<unsigned long long*>(ws + BatchWs::kRngBlocks);
         for (int i = threadIdx.x; i < 64; i += blockDim.x)
@@ -398,9 +402,9 @@ __global__ void k_batch_advance(unsigned char* ws, int64_t n) {
 size_t batch_lds_bytes(int max_L) { return (size_t)max_L * (size_t)max_L; }
 
 hipError_t launch_batch_prepare(unsigned char* ws, bool scratch_t, int count, uint64_t spins_bytes,
-                                int max_L, int64_t n, int mode, hipStream_t st) {
+                                int max_L, int64_t n, int mode, int draws, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(256), 0, st, ws, scratch_t ? 1 : 0, count,
-                       spins_bytes, max_L, n, mode);
+                       spins_bytes, max_L, n, mode, draws);
     return hipGetLastError();
 }
 

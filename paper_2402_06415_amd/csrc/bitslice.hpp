@@ -1,0 +1,175 @@
+// Bit-sliced Metropolis update of 32 spins of one colour at once (multi-spin
+// coding, one bit per spin, bit 1 meaning s = -1), shared by the sweep
+// kernels that keep lattices as colour bit planes.
+//
+// Draws follow the bit-plane layout: plane bit k of the 32-bit uniform r of
+// the lanes of group g is word k&3 of the Philox block
+// (g, lattice_id, 2t+c, 1 | (k>>2) << 8).  The comparison r < T is done
+// most-significant bit first for all 32 lanes at once and stops as soon as
+// every lane is decided, which leaves the outcome identical to a full
+// 32-bit comparison.
+#pragma once
+
+#include "common.hpp"
+
+namespace ising {
+
+// Truth tables used by the bit-sliced update (a, b, c = operands 1..3).
+constexpr uint32_t T_XOR3 = tt(kA ^ kB ^ kC);                     // a ^ b ^ c
+constexpr uint32_t T_MAJ = tt((kA & kB) | (kA & kC) | (kB & kC));  // at least two set
+constexpr uint32_t T_OR_AND = tt(kA | (kB & kC));                 // a | (b & c)
+constexpr uint32_t T_NOR3 = tt(~(kA | kB | kC));                  // none set
+constexpr uint32_t T_XOR_ANDN = tt((kA ^ kB) & ~kC);              // (a ^ b) & ~c
+constexpr uint32_t T_AND_ANDN = tt(kA & kB & ~kC);                // a & b & ~c
+constexpr uint32_t T_AND_XNOR = tt(kA & ~(kB ^ kC));              // a & (b == c)
+constexpr uint32_t T_OR2 = tt(kA | kB);                           // a | b   (c unused)
+constexpr uint32_t T_AND2 = tt(kA & kB);                          // a & b   (c unused)
+constexpr uint32_t T_BITSEL = tt((kA & kB) | (~kA & kC));         // a ? b : c, bitwise
+
+// Bit-sliced state of one 32-spin word during its update (steps 2 and 3 of
+// the single-spin-flip trial for 32 sites at once).
+struct WordState {
+    uint32_t W;     // spins before the update (bit 1: s = -1)
+    uint32_t flip;  // lanes decided to flip so far
+    uint32_t und;   // lanes whose comparison r < T is still undecided
+    uint32_t m2;    // lanes with u = 2 (dE = 4); the other undecided lanes have u = 4
+    uint32_t sm, a3, cy;  // A = sm + a3 + 2 cy anti-aligned neighbours (for dE)
+};
+
+// Classify the lanes of word W from its aligned, shifted, upper and lower
+// neighbour words: u = s h = 4 - 2A with A the count of anti-aligned bonds.
+__device__ __forceinline__ WordState classify(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
+                                              uint32_t D, const Accept& acc) {
+    const uint32_t a0 = W ^ O, a1 = W ^ S, a2 = W ^ U, a3 = W ^ D;
+    WordState st;
+    st.W = W;
+    st.a3 = a3;
+    st.sm = bop3<T_XOR3>(a0, a1, a2);  // low bit of a0 + a1 + a2
+    st.cy = bop3<T_MAJ>(a0, a1, a2);   // its carry
+    st.flip = bop3<T_OR_AND>(st.cy, st.sm, a3);       // A >= 2: dE <= 0, always flips
+    uint32_t m4 = bop3<T_NOR3>(st.sm, st.cy, a3);     // A == 0: u = 4
+    uint32_t m2 = bop3<T_XOR_ANDN>(st.sm, a3, st.cy); // A == 1: u = 2
+    if (acc.always2) {
+        st.flip = bop3<T_OR2>(st.flip, m2, m2);
+        m2 = 0;
+    }
+    if (acc.always4) {
+        st.flip = bop3<T_OR2>(st.flip, m4, m4);
+        m4 = 0;
+    }
+    st.m2 = m2;
+    st.und = bop3<T_OR2>(m2, m4, m4);
+    return st;
+}
+
+// Per-thread constants of the comparison: the Philox round keys and, for
+// the first eight planes, the threshold bits as all-ones/all-zero masks
+// (t2m[k] for T2, t4m[k] for T4), both in vector registers.
+struct DrawConsts {
+    RoundKeys rk;
+    uint32_t t2m[8], t4m[8];
+};
+
+__device__ __forceinline__ DrawConsts draw_consts(Key key, const Accept& acc) {
+    DrawConsts dc;
+    dc.rk = round_keys(key);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        dc.t2m[k] = 0u - ((acc.T2 >> (31 - k)) & 1u);
+        dc.t4m[k] = 0u - ((acc.T4 >> (31 - k)) & 1u);
+        asm volatile("" : "+v"(dc.t2m[k]), "+v"(dc.t4m[k]));
+    }
+    return dc;
+}
+
+// Bit-select with the middle operand in a scalar register (a wave-uniform
+// value; one scalar source is within the VALU's constant-bus limit).
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t bop3_vsv(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:%4" : "=v"(r) : "v"(a), "s"(b), "v"(c), "i"(TT));
+    return r;
+}
+
+// One plane of the most-significant-bit-first comparison r < T: P holds bit
+// (31 - k) of r for the 32 lanes and tm the threshold bit of each lane (T2's
+// for u = 2 lanes, T4's for u = 4 lanes).  Lanes that are already decided
+// ignore tm, so tm = m2 ? t2 : t4 suffices.  A lane is decided at the first
+// bit where r and its threshold differ: accepted when r has 0 there
+// (r < T), rejected when r has 1.
+__device__ __forceinline__ void compare_plane(WordState& st, uint32_t P, uint32_t tm) {
+    st.flip = bop3<T_OR2>(st.flip, bop3<T_AND_ANDN>(st.und, tm, P), P);
+    st.und = bop3<T_AND_XNOR>(st.und, P, tm);
+}
+
+// Draw the Philox blocks of word group g and compare r < T plane by plane.
+// kUniformAccept: the thresholds are the same in every lane of the wave
+// (the tail's threshold bits then go in as scalar operands).
+// Blocks 0 and 1 (planes 0-7) are drawn unconditionally: some lane of a
+// wave needs them almost always.  Further blocks are drawn while the lane
+// still has undecided sites.  nblk counts the blocks the lane needed (those
+// drawn while it still had an undecided site).
+template <bool kUniformAccept = true>
+__device__ __forceinline__ void draw_planes(WordState& st, uint32_t g, uint32_t h, uint32_t lid,
+                                            const Accept& acc, const DrawConsts& dc,
+                                            unsigned long long& nblk) {
+    const uint32_t m2 = st.m2;
+#pragma unroll
+    for (uint32_t b = 0; b < 2; ++b) {
+        nblk += st.und ? 1u : 0u;
+        const U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, dc.rk);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * (int)b + kk;
+            compare_plane(st, u4_get(out, kk), bop3<T_BITSEL>(m2, dc.t2m[k], dc.t4m[k]));
+        }
+    }
+    for (uint32_t b = 2; b < 8u && st.und; ++b) {
+        ++nblk;
+        const U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, dc.rk);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const uint32_t sh = 31u - (4u * b + (uint32_t)kk);
+            const uint32_t t2m = 0u - ((acc.T2 >> sh) & 1u), t4m = 0u - ((acc.T4 >> sh) & 1u);
+            if (kUniformAccept)
+                compare_plane(st, u4_get(out, kk), bop3_vsv<T_BITSEL>(m2, t2m, t4m));
+            else
+                compare_plane(st, u4_get(out, kk), bop3<T_BITSEL>(m2, t2m, t4m));
+        }
+    }
+}
+
+// New word after all draws (lanes still undecided have r == T: rejected);
+// with kObs also the energy and magnetisation changes of the flips.
+template <bool kObs>
+__device__ __forceinline__ uint32_t finalize(const WordState& st, int& dE, int& dM) {
+    if (kObs) {
+        const uint32_t f = st.flip;
+        const int nf = __popc(f);
+        // dM = sum over flips of -2 s_old = 2 (#flipped down - #flipped up)
+        dM += 2 * (2 * __popc(bop3<T_AND2>(f, st.W, st.W)) - nf);
+        // dE = sum over flips of 2u = 8 - 4A;  A = sm + a3 + 2 cy
+        dE += 8 * nf - 4 * (__popc(bop3<T_AND2>(f, st.sm, st.sm)) +
+                            __popc(bop3<T_AND2>(f, st.a3, st.a3)) +
+                            2 * __popc(bop3<T_AND2>(f, st.cy, st.cy)));
+    }
+    return st.W ^ st.flip;
+}
+
+// Complete Metropolis update of one word (all 32 planes available).
+template <bool kObs>
+__device__ __forceinline__ uint32_t update_word(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
+                                                uint32_t D, uint32_t g, uint32_t h, uint32_t lid,
+                                                const Accept& acc, const DrawConsts& dc, int& dE,
+                                                int& dM, unsigned long long& nblk) {
+    WordState st = classify(W, O, S, U, D, acc);
+    draw_planes(st, g, h, lid, acc, dc, nblk);
+    return finalize<kObs>(st, dE, dM);
+}
+
+__device__ __forceinline__ uint32_t side_word(uint32_t O, uint32_t Oprev, uint32_t Onext, int p) {
+    // p == 0: left neighbour (compact column i-1); p == 1: right (i+1)
+    return p == 0 ? (O << 1) | (Oprev >> 31) : (O >> 1) | (Onext << 31);
+}
+
+}  // namespace ising

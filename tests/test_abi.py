@@ -148,9 +148,10 @@ def test_product_path_does_not_import_oracle():
 
 # ------------------------------------------------------------ batch API (host side only)
 def test_batch_struct_layout_matches_header():
-    assert ctypes.sizeof(binding.ising_batch) == 56
-    assert binding.ising_batch.spins_bytes.offset == 32
-    assert binding.ising_batch.spins.offset == 40
+    assert ctypes.sizeof(binding.ising_batch) == 64
+    assert binding.ising_batch.draws.offset == 32
+    assert binding.ising_batch.spins_bytes.offset == 40
+    assert binding.ising_batch.spins.offset == 48
 
 
 def test_batch_spins_bytes_and_offsets():
@@ -177,7 +178,7 @@ def _batch(**kw):
     dict(abi_version=3), dict(count=0), dict(count=65537), dict(max_L=12), dict(max_L=264),
     dict(threads=100), dict(threads=2048), dict(groups_per_cu=17), dict(spins=0),
     dict(spins=0x10010), dict(workspace=0), dict(workspace=0x20004),
-    dict(lattice_id0=2 ** 32 - 1),
+    dict(lattice_id0=2 ** 32 - 1), dict(draws=2), dict(draws=-1), dict(reserved=1),
 ])
 def test_invalid_batches_are_rejected_before_any_launch(kw):
     b = _batch(**kw)
@@ -202,6 +203,14 @@ def test_batch_setup_rejects_bad_lattices_before_copying(L, beta, msg):
         lib.ising_batch_setup(b, L, beta)
     assert e.value.code == binding.E_INVALID
     assert msg in lib.ising_last_error()
+
+
+@pytest.mark.parametrize("L", [[32, 48], [96, 16]])
+def test_plane_draws_need_L_32_or_multiple_of_64(L):
+    b = _batch(draws=binding.DRAWS_PLANE, max_L=96, spins_bytes=1 << 16)
+    with pytest.raises(lib.IsingError) as e:
+        lib.ising_batch_setup(b, L, [0.4, 0.4])
+    assert e.value.code == binding.E_INVALID and "plane draws" in lib.ising_last_error()
 
 
 def test_batch_sweep_argument_errors():
