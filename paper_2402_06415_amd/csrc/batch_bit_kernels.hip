@@ -55,33 +55,60 @@ __device__ __forceinline__ BitGeom bit_geom(int L) {
     return b;
 }
 
-// The four neighbour words of word g of colour c, from the other plane Po:
-// O aligned (same compact index, same row), S the same row shifted by one
-// compact column (left when the row's parity (y + c) & 1 is 0, right when
-// 1), U and D the rows above and below, periodic.
-__device__ __forceinline__ void neighbours(const uint32_t* Po, const BitGeom& b, int g, int c,
-                                           uint32_t& O, uint32_t& S, uint32_t& U, uint32_t& D) {
-    O = Po[g];
+// Where the neighbour words of word g come from, fixed for a lattice: the
+// side words (left, for rows of parity (y + c) & 1 == 0, and right), the
+// rows above and below (word indices < 2^15), and the parity of y, packed
+// in two registers.  Computed once per word and bundle, used in every
+// half-sweep.
+struct WordNb {
+    uint32_t lr;  // left | right << 16 | (y & 1) << 31
+    uint32_t ud;  // up | down << 16
+};
+
+__device__ __forceinline__ WordNb word_nb(const BitGeom& b, int g) {
+    uint32_t iL, iR, iU, iD, py;
     if (b.nw > 0) {
         // exact for g < 2^31: the words of a lattice are at most 1024
         const int y = b.nw == 1 ? g : (int)__umulhi((uint32_t)g, b.magic), w = g - y * b.nw;
         const int row = y * b.nw;
-        const int wm = w == 0 ? b.nw - 1 : w - 1, wp = w + 1 == b.nw ? 0 : w + 1;
+        iL = (uint32_t)(row + (w == 0 ? b.nw - 1 : w - 1));
+        iR = (uint32_t)(row + (w + 1 == b.nw ? 0 : w + 1));
+        iU = (uint32_t)((y == 0 ? b.L - 1 : y - 1) * b.nw + w);
+        iD = (uint32_t)((y + 1 == b.L ? 0 : y + 1) * b.nw + w);
+        py = (uint32_t)y & 1u;
+    } else {
+        iL = iR = (uint32_t)g;
+        iU = (uint32_t)(g + 15) & 15u;  // L = 32: 16 words of two rows
+        iD = (uint32_t)(g + 1) & 15u;
+        py = 0u;
+    }
+    return WordNb{iL | iR << 16 | py << 31, iU | iD << 16};
+}
+
+// The four neighbour words of word g of colour c, from the other plane Po:
+// O aligned (same compact index, same row), S the same row shifted by one
+// compact column (left when the row's parity (y + c) & 1 is 0, right when
+// 1), U and D the rows above and below, periodic.
+__device__ __forceinline__ void neighbours(const uint32_t* Po, const BitGeom& b, int g,
+                                           const WordNb& n, int c, uint32_t& O, uint32_t& S,
+                                           uint32_t& U, uint32_t& D) {
+    O = Po[g];
+    if (b.nw > 0) {
         // left: bit i <- compact i - 1 (bit 0 from the previous word's bit 31);
         // right: bit i <- compact i + 1
-        S = ((y + c) & 1) == 0 ? __builtin_amdgcn_alignbit(O, Po[row + wm], 31)
-                               : __builtin_amdgcn_alignbit(Po[row + wp], O, 1);
-        U = Po[(y == 0 ? b.L - 1 : y - 1) * b.nw + w];
-        D = Po[(y + 1 == b.L ? 0 : y + 1) * b.nw + w];
+        const bool left = (((n.lr >> 31) + (uint32_t)c) & 1u) == 0u;
+        const uint32_t X = Po[left ? (n.lr & 0xFFFFu) : ((n.lr >> 16) & 0x7FFFu)];
+        S = left ? __builtin_amdgcn_alignbit(O, X, 31) : __builtin_amdgcn_alignbit(X, O, 1);
+        U = Po[n.ud & 0xFFFFu];
+        D = Po[n.ud >> 16];
     } else {
         // L = 32: the halves are rows 2g (parity c) and 2g + 1 (parity 1 - c),
         // sixteen compact columns each, periodic within the half
         const uint32_t left = bop3<T_SEL>(0xFFFEFFFEu, O << 1, O >> 15);
         const uint32_t right = bop3<T_SEL>(0x7FFF7FFFu, O >> 1, O << 15);
         S = c == 0 ? bop3<T_SEL>(0x0000FFFFu, left, right) : bop3<T_SEL>(0x0000FFFFu, right, left);
-        const uint32_t Om = Po[(g + 15) & 15], Op = Po[(g + 1) & 15];
-        U = __builtin_amdgcn_alignbit(O, Om, 16);  // rows 2g - 1 | 2g
-        D = __builtin_amdgcn_alignbit(Op, O, 16);  // rows 2g + 1 | 2g + 2
+        U = __builtin_amdgcn_alignbit(O, Po[n.ud & 0xFFFFu], 16);  // rows 2g - 1 | 2g
+        D = __builtin_amdgcn_alignbit(Po[n.ud >> 16], O, 16);     // rows 2g + 1 | 2g + 2
     }
 }
 
@@ -150,7 +177,7 @@ __device__ __forceinline__ void count_bits(const uint32_t* P, const BitGeom& b, 
     ones = 0;
     for (int g = tl; g < b.nwc; g += tt) {
         uint32_t O, S, U, D;
-        neighbours(P + b.nwc, b, g, 0, O, S, U, D);
+        neighbours(P + b.nwc, b, g, word_nb(b, g), 0, O, S, U, D);
         const uint32_t W = P[g];
         anti += __popc(W ^ O) + __popc(W ^ S) + __popc(W ^ U) + __popc(W ^ D);
         ones += __popc(W) + __popc(O);
@@ -259,6 +286,10 @@ __global__ void __launch_bounds__(1024) k_batch_sweep_bit(unsigned char* ws, int
         }
         long long sE = 0, sE2 = 0, sAM = 0, sM2 = 0;
         unsigned long long m4lo = 0, m4hi = 0;
+        // neighbour sources of this lane's first two words (the launch shapes
+        // of the autotuner give at most two words per lane from 512 threads)
+        const WordNb nb0 = word_nb(b, tl < b.nwc ? tl : 0);
+        const WordNb nb1 = word_nb(b, tl + tt < b.nwc ? tl + tt : 0);
         for (int64_t sw = 0; sw < n; ++sw) {
             int dE = 0, dM = 0;
             for (int c = 0; c < 2; ++c) {
@@ -266,9 +297,10 @@ __global__ void __launch_bounds__(1024) k_batch_sweep_bit(unsigned char* ws, int
                 if (active) {
                     uint32_t* Pc = P + c * b.nwc;
                     const uint32_t* Po = P + (c ^ 1) * b.nwc;
-                    for (int g = tl; g < b.nwc; g += tt) {
+                    for (int g = tl, k = 0; g < b.nwc; g += tt, ++k) {
                         uint32_t O, S, U, D;
-                        neighbours(Po, b, g, c, O, S, U, D);
+                        neighbours(Po, b, g, k == 0 ? nb0 : (k == 1 ? nb1 : word_nb(b, g)), c, O,
+                                   S, U, D);
                         WordState st = classify(Pc[g], O, S, U, D, acc);
                         draw_planes<false>(st, (uint32_t)g, h, d.lid, acc, dc, nblk);
                         Pc[g] = finalize<true>(st, dE, dM);

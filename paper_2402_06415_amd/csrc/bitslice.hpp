@@ -130,11 +130,15 @@ __device__ __forceinline__ void draw_planes(WordState& st, uint32_t g, uint32_t 
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const uint32_t sh = 31u - (4u * b + (uint32_t)kk);
-            const uint32_t t2m = 0u - ((acc.T2 >> sh) & 1u), t4m = 0u - ((acc.T4 >> sh) & 1u);
-            if (kUniformAccept)
+            if (kUniformAccept) {
+                const uint32_t t2m = 0u - ((acc.T2 >> sh) & 1u), t4m = 0u - ((acc.T4 >> sh) & 1u);
                 compare_plane(st, u4_get(out, kk), bop3_vsv<T_BITSEL>(m2, t2m, t4m));
-            else
+            } else {
+                // per-lane thresholds: one signed one-bit field extract each
+                const uint32_t t2m = (uint32_t)__builtin_amdgcn_sbfe((int)acc.T2, (int)sh, 1);
+                const uint32_t t4m = (uint32_t)__builtin_amdgcn_sbfe((int)acc.T4, (int)sh, 1);
                 compare_plane(st, u4_get(out, kk), bop3<T_BITSEL>(m2, t2m, t4m));
+            }
         }
     }
 }
