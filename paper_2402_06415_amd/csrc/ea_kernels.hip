@@ -70,6 +70,25 @@ __device__ __forceinline__ uint32_t unsat(uint32_t a, uint32_t b, uint32_t j) {
     return xor3(a, b, j) & 0x02020202u;
 }
 
+// Fourth word of a raw buffer resource on gfx950 (32-bit data, no swizzle).
+constexpr int kBufferWord3 = 0x00020000;
+
+// Philox round keys left to the scalar unit: a thread of the half-sweep
+// draws at most one block, so a key schedule in vector registers would cost
+// as much as the block itself.
+__device__ __forceinline__ RoundKeys scalar_round_keys(Key key) {
+    RoundKeys rk;
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        rk.k[2 * i] = k0;
+        rk.k[2 * i + 1] = k1;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    return rk;
+}
+
 __global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* spins,
                                const int8_t* bonds, int lgL, int R, int c, Key key) {
     EaHeader* hd = ea_header(ws);
@@ -94,27 +113,37 @@ __global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* sp
         const uint32_t rbk = (z == 0 ? row + N - LL : row - LL);     // z - 1
         const uint32_t rft = (z + 1 == L ? row - N + LL : row + LL); // z + 1
         const int xe = p ? (x0 + 8 == L ? 0 : x0 + 8) : (x0 == 0 ? L - 1 : x0 - 1);
-        const int8_t* sr = spins + (size_t)r * N;
-        const int8_t* Jx = bonds;
-        const int8_t* Jy = bonds + N;
-        const int8_t* Jz = bonds + 2 * N;
-        const uint2 Rw = *reinterpret_cast<const uint2*>(sr + row + x0);
-        const Span sp = split_row(Rw, (uint8_t)sr[row + xe], p);
+        // Buffer loads: the replica's spins and the couplings are addressed by
+        // 32-bit offsets from a wave-uniform base (no 64-bit address math per
+        // load); Jy and Jz are the coupling buffer at scalar offsets N and 2N.
+        const __amdgpu_buffer_rsrc_t bs = __builtin_amdgcn_make_buffer_rsrc(
+            spins + (size_t)r * N, (short)0, (int)N, kBufferWord3);
+        const __amdgpu_buffer_rsrc_t bj = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<int8_t*>(bonds), (short)0, (int)(3 * N), kBufferWord3);
+        auto ld = [&](__amdgpu_buffer_rsrc_t b, uint32_t off, uint32_t soff) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(b, off, soff, 0);
+            return make_uint2(v[0], v[1]);
+        };
+        const uint2 Rw = ld(bs, row + x0, 0u);
+        const Span sp = split_row(Rw, __builtin_amdgcn_raw_buffer_load_b8(bs, row + xe, 0u, 0), p);
         const uint32_t sel = p ? kSelOdd : kSelEven;
-        auto at = [&](const int8_t* base, uint32_t rb) {
-            const uint2 w = *reinterpret_cast<const uint2*>(base + rb + x0);
+        auto at = [&](__amdgpu_buffer_rsrc_t b, uint32_t rb, uint32_t soff) {
+            const uint2 w = ld(b, rb + x0, soff);
             return perm(w.y, w.x, sel);
         };
         // couplings: right bond J_x(n) at the sites; left bond J_x(n - e_x)
-        const uint2 Jxw = *reinterpret_cast<const uint2*>(Jx + row + x0);
+        const uint2 Jxw = ld(bj, row + x0, 0u);
         const uint32_t jev = perm(Jxw.y, Jxw.x, kSelEven), jod = perm(Jxw.y, Jxw.x, kSelOdd);
         const uint32_t JR = p ? jod : jev;
-        const uint32_t JL = p ? jev : ((jod << 8) | (uint8_t)Jx[row + (x0 == 0 ? L - 1 : x0 - 1)]);
+        const uint32_t JL =
+            p ? jev
+              : ((jod << 8) |
+                 __builtin_amdgcn_raw_buffer_load_b8(bj, row + (x0 == 0 ? L - 1 : x0 - 1), 0u, 0));
         const uint32_t a2 = unsat(sp.S, sp.Lf, JL) + unsat(sp.S, sp.Rt, JR) +
-                            unsat(sp.S, at(sr, rup), at(Jy, rup)) +
-                            unsat(sp.S, at(sr, rdn), at(Jy, row)) +
-                            unsat(sp.S, at(sr, rbk), at(Jz, rbk)) +
-                            unsat(sp.S, at(sr, rft), at(Jz, row));
+                            unsat(sp.S, at(bs, rup, 0u), at(bj, rup, N)) +
+                            unsat(sp.S, at(bs, rdn, 0u), at(bj, row, N)) +
+                            unsat(sp.S, at(bs, rbk, 0u), at(bj, rbk, 2 * N)) +
+                            unsat(sp.S, at(bs, rft, 0u), at(bj, row, 2 * N));
         // a2 = 2 n_u per byte (0..12); classes on n_u = 0, 1, 2 (bits 0..2 of n_u)
         // (multi-input logic through bop3 with explicit tables, as elsewhere)
         const uint32_t nu = (a2 >> 1) & 0x07070707u;
@@ -132,7 +161,7 @@ __global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* sp
         if (need) {
             rr = philox4x32_10({(row + (uint32_t)x0) >> 3, (uint32_t)r,
                                 2u * (uint32_t)hd->t + (uint32_t)c, kTagSite},
-                               key);
+                               scalar_round_keys(key));
             nblk = 1;
         }
         uint32_t lvl = 4u * kOnes;  // 4 + lvl_j - need_j stays in 1..7
@@ -150,8 +179,8 @@ __global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* sp
         dE = 12 * (int)__popc(fb) - 2 * (int)__builtin_amdgcn_udot4(a2, fb, 0u, false);
         const uint32_t Fx = perm(F, 0u, p ? 0x05000400u : 0x00050004u);
         const uint32_t Fy = perm(F, 0u, p ? 0x07000600u : 0x00070006u);
-        *reinterpret_cast<uint2*>(const_cast<int8_t*>(sr) + row + x0) =
-            make_uint2(Rw.x ^ Fx, Rw.y ^ Fy);
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{Rw.x ^ Fx, Rw.y ^ Fy}, bs, row + x0, 0u, 0);
     }
     // block sums of dE and of the Philox blocks drawn -> partials[c][r][bi]
     __shared__ int red[2][4];
