@@ -37,7 +37,8 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-// H of an L x L lattice (angles `th`, LDS or global), summed into thread 0.
+// H of an L x L lattice (angles `th`, LDS or global), summed into thread 0;
+// `red` holds one slot per wave (at most 16).
 __device__ __forceinline__ double energy_to0(const double* th, int L, double* red) {
 #pragma clang fp contract(off)
     double e = 0.0;
@@ -105,12 +106,12 @@ __global__ void k_xy_advance(unsigned char* ws, int64_t n) {
         hd->t += (uint64_t)n;
 }
 
-__global__ void __launch_bounds__(256) k_xy_sweep(unsigned char* ws, double* theta, int L,
+__global__ void __launch_bounds__(512) k_xy_sweep(unsigned char* ws, double* theta, int L,
                                                   int count, int64_t n, double beta, Key key,
                                                   uint32_t lid0, double* E_trace) {
 #pragma clang fp contract(off)
     extern __shared__ double th[];
-    __shared__ double red[4];
+    __shared__ double red[16];
     XyHeader* hd = xy_header(ws);
     if (hd->ok == 0)
         return;
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(256) k_xy_sweep(unsigned char* ws, double* the
     for (int i = threadIdx.x; i < N; i += blockDim.x)
         g[i] = th[i];
     // accepted rotations of this lattice
-    __shared__ unsigned long long racc[4];
+    __shared__ unsigned long long racc[16];
     unsigned long long a = acc;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
@@ -167,13 +168,16 @@ __global__ void __launch_bounds__(256) k_xy_sweep(unsigned char* ws, double* the
     if ((threadIdx.x & 63) == 0)
         racc[threadIdx.x >> 6] = a;
     __syncthreads();
-    if (threadIdx.x == 0)
-        reinterpret_cast<unsigned long long*>(ws + kXyAccepted)[j] +=
-            racc[0] + racc[1] + racc[2] + racc[3];
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+            t += racc[w];
+        reinterpret_cast<unsigned long long*>(ws + kXyAccepted)[j] += t;
+    }
 }
 
 __global__ void k_xy_energy(const double* theta, int L, double* E_out) {
-    __shared__ double red[4];
+    __shared__ double red[16];
     const double E = energy_to0(theta + (int64_t)blockIdx.x * L * L, L, red);
     if (threadIdx.x == 0)
         E_out[blockIdx.x] = E;
@@ -194,8 +198,13 @@ hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, in
 hipError_t launch_xy_sweep(unsigned char* ws, double* theta, int L, int count, int64_t n,
                            double beta, Key key, uint32_t lid0, double* E_trace, hipStream_t st) {
     hipLaunchKernelGGL(k_xy_prepare, dim3(1), dim3(1), 0, st, ws, count, n);
-    hipLaunchKernelGGL(k_xy_sweep, dim3(count), dim3(256), (size_t)L * L * sizeof(double), st, ws,
-                       theta, L, count, n, beta, key, lid0, E_trace);
+    // one trial per thread per half-sweep where the lattice allows (up to 512:
+    // the double-precision trial needs more than the 128 registers a lane
+    // has at 1024 threads)
+    int threads = ((L * L / 2 + 63) / 64) * 64;
+    threads = threads < 64 ? 64 : (threads > 512 ? 512 : threads);
+    hipLaunchKernelGGL(k_xy_sweep, dim3(count), dim3(threads), (size_t)L * L * sizeof(double), st,
+                       ws, theta, L, count, n, beta, key, lid0, E_trace);
     hipLaunchKernelGGL(k_xy_advance, dim3(1), dim3(1), 0, st, ws, n);
     return hipGetLastError();
 }
