@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libising.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 LAYOUT_INT8 = 0
 LAYOUT_BIT1 = 1
 DRAWS_SITE = 0

@@ -73,14 +73,14 @@ def test_thresholds_reject(beta):
 
 
 def _lat(**kw):
-    d = dict(abi_version=1, dim=2, L=16, layout=0, seed=1, lattice_id=0, flags=0,
+    d = dict(abi_version=binding.ABI_VERSION, dim=2, L=16, layout=0, seed=1, lattice_id=0, flags=0,
              sweep_index=0, spins=0x1000, workspace=0x2000)
     d.update(kw)
     return binding.ising_lattice(**d)
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(abi_version=2), binding.E_INVALID),
+    (dict(abi_version=1), binding.E_INVALID),
     (dict(dim=3), binding.E_UNSUPPORTED),
     (dict(L=7), binding.E_INVALID),
     (dict(L=2), binding.E_INVALID),
@@ -168,7 +168,7 @@ def test_batch_spins_bytes_and_offsets():
 
 
 def _batch(**kw):
-    d = dict(abi_version=1, count=2, seed=1, lattice_id0=0, max_L=32, threads=0, groups_per_cu=0,
+    d = dict(abi_version=binding.ABI_VERSION, count=2, seed=1, lattice_id0=0, max_L=32, threads=0, groups_per_cu=0,
              spins_bytes=4096, spins=0x10000, workspace=0x20000)
     d.update(kw)
     return binding.ising_batch(**d)

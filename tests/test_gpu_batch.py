@@ -189,7 +189,7 @@ def test_sweep_without_setup_is_a_device_error_not_a_fault():
     raw_s, spins = lib.binding._aligned_buffer(nb, "cuda")
     raw_w, ws = lib.binding._aligned_buffer(lib.ising_batch_workspace_bytes(2), "cuda")
     spins.fill_(1)
-    c = lib.ising_batch(1, 2, 1, 0, 16, 0, 0, 0, 0, nb, spins.data_ptr(), ws.data_ptr())
+    c = lib.ising_batch(lib.binding.ABI_VERSION, 2, 1, 0, 16, 0, 0, 0, 0, nb, spins.data_ptr(), ws.data_ptr())
     lib.ising_batch_sweep(c, 5)
     with pytest.raises(lib.IsingError) as e:
         lib.ising_batch_check_device_error(c)

@@ -113,7 +113,7 @@ def test_sweep_without_setup_is_a_device_error():
     raw_b, bonds = lib.binding._aligned_buffer(3 * L ** 3, "cuda")
     raw_w, ws = lib.binding._aligned_buffer(lib.ising_ea_workspace_bytes(L, R), "cuda")
     spins.fill_(1)
-    c = lib.ising_ea(1, L, R, 0, 1, spins.data_ptr(), bonds.data_ptr(), ws.data_ptr())
+    c = lib.ising_ea(lib.binding.ABI_VERSION, L, R, 0, 1, spins.data_ptr(), bonds.data_ptr(), ws.data_ptr())
     lib.ising_ea_sweep(c, 3, 1)
     with pytest.raises(lib.IsingError) as e:
         lib.ising_ea_check_device_error(c)

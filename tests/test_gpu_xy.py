@@ -88,7 +88,7 @@ def test_xy_sweep_before_init_is_a_device_error():
     raw_t, th = lib.binding._aligned_buffer(4 * 4 * 8, "cuda")
     raw_w, ws = lib.binding._aligned_buffer(lib.ising_xy_workspace_bytes(1), "cuda")
     th.fill_(0)
-    c = lib.ising_xy(1, 4, 1, 0, 1, th.data_ptr(), ws.data_ptr())
+    c = lib.ising_xy(lib.binding.ABI_VERSION, 4, 1, 0, 1, th.data_ptr(), ws.data_ptr())
     lib.ising_xy_sweep(c, 1.0, 3)
     with pytest.raises(lib.IsingError):
         lib.ising_xy_check_device_error(c)
