@@ -97,14 +97,17 @@ def _load():
     lib.oracle_ea_init.restype = None
     lib.oracle_ea_halfsweep.argtypes = [i8p, i8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                         ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, i64p,
-                                        ctypes.c_int]
+                                        ctypes.c_int, ctypes.c_int]
+    lib.oracle_ea_fill_plane.argtypes = [u32p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                         ctypes.c_uint32, ctypes.c_uint32]
+    lib.oracle_ea_fill_plane.restype = None
     lib.oracle_ea_halfsweep.restype = ctypes.c_int
     lib.oracle_ea_exchange.argtypes = [i64p, i32p, ctypes.c_int, f64p, ctypes.c_uint64,
                                        ctypes.c_uint64, u64p]
     lib.oracle_ea_exchange.restype = None
     lib.oracle_ea_run.argtypes = [i8p, i8p, ctypes.c_int, ctypes.c_int, f64p, ctypes.c_uint64,
                                   ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, i32p, i64p, u64p,
-                                  i64p, ctypes.c_int]
+                                  i64p, ctypes.c_int, ctypes.c_int]
     lib.oracle_ea_run.restype = ctypes.c_int
     lib.oracle_xy_init.argtypes = [f64p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                    ctypes.c_uint32]
@@ -286,19 +289,29 @@ def ea_init(L: int, start: int, seed: int, replica_id: int) -> np.ndarray:
     return s
 
 
+def ea_fill_plane(L: int, c: int, seed: int, replica_id: int, t: int) -> np.ndarray:
+    """Plane draws of half-sweep 2t + c: r [L, L, L] for the colour-c sites
+    (zero elsewhere)."""
+    r = np.zeros((L, L, L), np.uint32)
+    _load().oracle_ea_fill_plane(_ptr(r, ctypes.c_uint32), L, c, seed, replica_id,
+                                 (2 * t + c) & 0xFFFFFFFF)
+    return r
+
+
 def ea_halfsweep(s: np.ndarray, J: np.ndarray, c: int, seed: int, replica_id: int, t: int,
-                 beta: float, nthreads: int = 1) -> int:
+                 beta: float, nthreads: int = 1, mode: int = MODE_SITE) -> int:
     dE = ctypes.c_int64(0)
     J = np.ascontiguousarray(J, np.int8)
     if _load().oracle_ea_halfsweep(_ptr(s, ctypes.c_int8), _ptr(J, ctypes.c_int8), s.shape[0], c,
-                                   seed, replica_id, t, float(beta), ctypes.byref(dE), nthreads):
+                                   seed, replica_id, t, float(beta), ctypes.byref(dE), nthreads,
+                                   mode):
         raise ValueError("oracle_ea_halfsweep rejected its arguments")
     return dE.value
 
 
 def ea_run(spins: np.ndarray, J: np.ndarray, beta, seed: int, t0: int, n: int, every: int,
            perm: np.ndarray, E: np.ndarray, accepts: np.ndarray = None, trace: bool = True,
-           nthreads: int = 1):
+           nthreads: int = 1, mode: int = MODE_SITE):
     """n sweeps of the replicas spins [R, L, L, L] in place (replica id r),
     temperatures beta [R] increasing, exchange after every `every`-th
     sweep; perm (int32 [R], temperature -> replica), E (int64 [R], current
@@ -314,7 +327,7 @@ def ea_run(spins: np.ndarray, J: np.ndarray, beta, seed: int, t0: int, n: int, e
                                _ptr(beta, ctypes.c_double), seed, t0, n, every,
                                _ptr(perm, ctypes.c_int32), _ptr(E, ctypes.c_int64),
                                _ptr(accepts, ctypes.c_uint64),
-                               _ptr(tr, ctypes.c_int64) if trace else None, nthreads)
+                               _ptr(tr, ctypes.c_int64) if trace else None, nthreads, mode)
     if rc:
         raise ValueError("oracle_ea_run rejected its arguments")
     return tr[:n] if trace else None

@@ -26,6 +26,12 @@
  *   - beta_k) D)) with r = out[0] of counter (k, m, 0, 5).
  *   Random start: s = -1 iff the top bit of out[n & 3] of counter
  *   (n >> 2, replica id, 0, 2) is set.
+ *   Plane draws (mode 1, the bit-plane layout of the 2D oracle carried to
+ *   3D): the colour-c sites with q >> 5 == g form group g, lane l = q & 31;
+ *   plane k (k = 0 most significant) is P_k = out[k & 3] of counter
+ *   (g, replica id, 2t + c, 1 | (k >> 2) << 8), and
+ *   r = sum_k ((P_k >> l) & 1) << (31 - k).  Mode 0 is the per-site draw
+ *   above.
  */
 #include <math.h>
 #include <stdint.h>
@@ -123,17 +129,60 @@ void oracle_ea_init(int8_t *s, int L, int start, uint64_t seed, uint32_t replica
     }
 }
 
-/* Update every site of colour c of one replica at inverse temperature beta
- * (sweep index t); the energy change goes to *dE. */
-int oracle_ea_halfsweep(int8_t *s, const int8_t *J, int L, int c, uint64_t seed,
-                        uint32_t replica_id, uint64_t t, double beta, int64_t *dE, int nthreads)
+/* Plane draws of half-sweep h for every colour-c site: r[n] for the sites
+ * of colour c (entries of the other colour untouched). */
+void oracle_ea_fill_plane(uint32_t *r, int L, int c, uint64_t seed, uint32_t replica_id,
+                          uint32_t h)
 {
+    int64_t N = (int64_t)L * L * L, half = N / 2, row = L / 2;
+    int64_t groups = (half + 31) / 32;
+    for (int64_t g = 0; g < groups; ++g) {
+        uint32_t planes[32];
+        for (int b = 0; b < 8; ++b) {
+            uint32_t out[4];
+            ea_philox(seed, (uint32_t)g, replica_id, h, 1u | ((uint32_t)b << 8), out);
+            for (int j = 0; j < 4; ++j)
+                planes[4 * b + j] = out[j];
+        }
+        for (int l = 0; l < 32; ++l) {
+            int64_t q = 32 * g + l;
+            if (q >= half)
+                break;
+            /* the colour-c site with compact index q: row q / (L/2) of the
+             * (z, y) rows, column 2 (q % (L/2)) + parity */
+            int64_t R = q / row, i = q % row;
+            int64_t y = R % L, z = R / L;
+            int64_t x = 2 * i + ((y + z + c) & 1);
+            uint32_t v = 0;
+            for (int k = 0; k < 32; ++k)
+                v |= ((planes[k] >> l) & 1u) << (31 - k);
+            r[R * L + x] = v;
+        }
+    }
+}
+
+/* Update every site of colour c of one replica at inverse temperature beta
+ * (sweep index t) with per-site (mode 0) or plane (mode 1) draws; the
+ * energy change goes to *dE. */
+int oracle_ea_halfsweep(int8_t *s, const int8_t *J, int L, int c, uint64_t seed,
+                        uint32_t replica_id, uint64_t t, double beta, int64_t *dE, int nthreads,
+                        int mode)
+{
+    if (mode != 0 && mode != 1)
+        return 1;
     uint32_t T[3];
     uint8_t always_flip[3];
     if (oracle_ea_thresholds(beta, T, always_flip))
         return 1;
     int64_t N = (int64_t)L * L * L, total = 0;
     uint32_t h = (uint32_t)(2 * t + (uint64_t)c);
+    uint32_t *rp = NULL;
+    if (mode == 1) {
+        rp = (uint32_t *)calloc((size_t)N, sizeof(uint32_t));
+        if (!rp)
+            return 2;
+        oracle_ea_fill_plane(rp, L, c, seed, replica_id, h);
+    }
 #ifdef _OPENMP
 #pragma omp parallel for num_threads(nthreads) reduction(+ : total) schedule(static)
 #endif
@@ -147,6 +196,8 @@ int oracle_ea_halfsweep(int8_t *s, const int8_t *J, int L, int c, uint64_t seed,
             int i = u / 2 - 1;
             if (always_flip[i]) {
                 flip = 1;
+            } else if (mode == 1) {
+                flip = rp[n] < T[i];
             } else {
                 uint32_t out[4];
                 uint64_t q = (uint64_t)n >> 1;
@@ -160,6 +211,7 @@ int oracle_ea_halfsweep(int8_t *s, const int8_t *J, int L, int c, uint64_t seed,
         }
     }
     (void)nthreads;
+    free(rp);
     *dE = total;
     return 0;
 }
@@ -197,7 +249,7 @@ void oracle_ea_exchange(const int64_t *E, int32_t *perm, int R, const double *be
  * receives E of replica r after sweep j. */
 int oracle_ea_run(int8_t *spins, const int8_t *J, int L, int R, const double *beta,
                   uint64_t seed, uint64_t t0, int64_t n, int every, int32_t *perm, int64_t *E,
-                  uint64_t *accepts, int64_t *E_trace, int nthreads)
+                  uint64_t *accepts, int64_t *E_trace, int nthreads, int mode)
 {
     if (L < 2 || (L & 1) || R < 1 || n < 0 || every < 0)
         return 1;
@@ -215,7 +267,7 @@ int oracle_ea_run(int8_t *spins, const int8_t *J, int L, int R, const double *be
             for (int r = 0; r < R; ++r) {
                 int64_t dE = 0;
                 if (oracle_ea_halfsweep(spins + (int64_t)r * N, J, L, c, seed, (uint32_t)r, t,
-                                        beta[tidx[r]], &dE, nthreads)) {
+                                        beta[tidx[r]], &dE, nthreads, mode)) {
                     free(tidx);
                     return 1;
                 }

@@ -153,3 +153,95 @@ def test_replica_exchange_samples_each_temperature():
         blocks = x[: len(x) // 50 * 50].reshape(50, -1).mean(axis=1)
         err = blocks.std(ddof=1) / np.sqrt(50)
         assert abs(blocks.mean() - exact[k]) < 4 * err + 1e-9, (k, blocks.mean(), exact[k], err)
+
+
+PLANE = oracle.MODE_PLANE
+
+
+@pytest.mark.parametrize("L,c,t", [(8, 0, 3), (16, 1, 0), (64, 0, 7)])
+def test_plane_draw_counter_layout(torch_philox, L, c, t):
+    """Plane draws of the spin glass: site q = n >> 1 of colour c takes bit
+    q & 31 of the eight blocks (q >> 5, replica, 2t + c, 1 | b << 8) as its
+    32-bit r, most significant plane first (checked against PyTorch's own
+    Philox for sampled sites; at L = 8 and 16 a group spans several rows)."""
+    seed, rid = 4242, 5
+    r = oracle.ea_fill_plane(L, c, seed, rid, t)
+    rng = np.random.default_rng(L)
+    picks = rng.integers(0, L, size=(24, 3))
+    for z, y, x in picks:
+        if (x + y + z) % 2 != c:
+            x = (x + 1) % L
+        n = (int(z) * L + int(y)) * L + int(x)
+        q = n >> 1
+        g, lane = q >> 5, q & 31
+        rows = [[seed, 0, g, rid, 2 * t + c, 1 | (b << 8)] for b in range(8)]
+        ref = torch_philox(rows)
+        planes = [int(ref[k >> 2][k & 3]) for k in range(32)]
+        want = sum(((planes[k] >> lane) & 1) << (31 - k) for k in range(32))
+        assert int(r[z, y, x]) == want
+    other = ((np.arange(L)[:, None, None] + np.arange(L)[None, :, None] +
+              np.arange(L)[None, None, :]) % 2) != c
+    assert (r[other] == 0).all()
+
+
+def test_plane_draws_are_uniform_and_decorrelated():
+    L = 32
+    r = oracle.ea_fill_plane(L, 0, 99, 0, 0)
+    mask = ((np.arange(L)[:, None, None] + np.arange(L)[None, :, None] +
+             np.arange(L)[None, None, :]) % 2) == 0
+    v = r[mask].astype(np.float64) / 2 ** 32
+    n = v.size
+    hist = np.bincount((r[mask] >> 28).astype(np.int64), minlength=16)
+    chi2 = ((hist - n / 16) ** 2 / (n / 16)).sum()
+    assert chi2 < 50  # 15 dof
+    assert abs(v.mean() - 0.5) < 5 * np.sqrt(1 / 12 / n)
+    w = v - 0.5
+    assert abs((w[1:] * w[:-1]).mean() * 12) < 5 / np.sqrt(n)
+    v2 = oracle.ea_fill_plane(L, 0, 99, 0, 1)[mask].astype(np.float64) / 2 ** 32 - 0.5
+    assert abs((w * v2).mean() * 12) < 5 / np.sqrt(n)
+    bits = ((r[mask][:, None] >> np.arange(32)) & 1).mean(axis=0)
+    assert np.all(np.abs(bits - 0.5) < 5 * 0.5 / np.sqrt(n))
+
+
+def test_plane_mode_replica_exchange_samples_each_temperature():
+    """The plane-draw chain (one partial draw group per colour on the 2x2x2
+    glass) with exchanges after every sweep: each temperature's mean energy
+    is the exact Boltzmann mean."""
+    J = ea_bonds(2, 23)
+    beta = np.array([0.3, 0.6, 0.9])
+    S = _all_states_3d()
+    E_all = np.array([oracle.ea_energy(x, J) for x in S], np.float64)
+    exact = [float((E_all * np.exp(-b * E_all)).sum() / np.exp(-b * E_all).sum()) for b in beta]
+    R = 3
+    spins = np.stack([oracle.ea_init(2, 1, 37, r) for r in range(R)])
+    E = np.array([oracle.ea_energy(x, J) for x in spins])
+    perm = np.arange(R, dtype=np.int32)
+    acc = np.zeros(R - 1, np.uint64)
+    n = 30000
+    hist = np.zeros((n, R))
+    for t in range(n):
+        oracle.ea_run(spins, J, beta, 37, t, 1, 1, perm, E, acc, trace=False, mode=PLANE)
+        hist[t] = E[perm]
+    assert (acc > 0).all()
+    for k in range(R):
+        x = hist[1000:, k]
+        blocks = x[: len(x) // 50 * 50].reshape(50, -1).mean(axis=1)
+        err = blocks.std(ddof=1) / np.sqrt(50)
+        assert abs(blocks.mean() - exact[k]) < 4 * err + 1e-9, (k, blocks.mean(), exact[k], err)
+    assert (E == [oracle.ea_energy(x, J) for x in spins]).all()
+
+
+def test_plane_and_site_modes_differ_but_share_everything_else():
+    """Same start, same couplings: the two draw modes give different chains,
+    and at beta = 0 (every site flips) identical ones."""
+    J = ea_bonds(8, 5)
+    a = np.stack([oracle.ea_init(8, 1, 3, r) for r in range(2)])
+    b = a.copy()
+    for beta, same in ((np.array([0.4, 0.8]), False), (np.array([0.0, 0.0]), True)):
+        Ea = np.array([oracle.ea_energy(x, J) for x in a])
+        Eb = Ea.copy()
+        pa, pb = np.arange(2, dtype=np.int32), np.arange(2, dtype=np.int32)
+        oracle.ea_run(a, J, beta, 3, 0, 4, 0, pa, Ea, trace=False)
+        oracle.ea_run(b, J, beta, 3, 0, 4, 0, pb, Eb, trace=False, mode=PLANE)
+        assert (a == b).all() == same
+        b[:] = a
