@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched: keep the library's default launch shape")
     ap.add_argument("--draws", choices=("plane", "site"), default="plane",
-                    help="batched: bit-plane draws (32 sites per lane) or per-site draws (INT8)")
+                    help="batched and ea: bit-plane draws (32 sites per lane) or per-site draws")
     ap.add_argument("--shape", default=None,
                     help="batched: launch shape THREADS,GROUPS_PER_CU instead of autotuning")
     return ap.parse_args()
@@ -68,7 +68,7 @@ def parse():
 KERNEL_SOURCES = {
     "bit1_kernels.hip": ("bit1_kernels.hip", "common.hpp", "kernels.hpp", "bitslice.hpp"),
     "batch_kernels.hip": ("batch_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp"),
-    "ea_kernels.hip": ("ea_kernels.hip", "common.hpp", "kernels.hpp", "ea.hpp"),
+    "ea_kernels.hip": ("ea_kernels.hip", "common.hpp", "kernels.hpp", "ea.hpp", "bitslice.hpp"),
     "batch_bit_kernels.hip": ("batch_bit_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp",
                               "bitslice.hpp"),
 }
@@ -396,26 +396,30 @@ def bench_learned(args):
     print(json.dumps(rec), flush=True)
 
 
-def cpu_baseline_ea(J, betas, seed: int, every: int, target_s: float):
+def cpu_baseline_ea(J, betas, seed: int, every: int, target_s: float, draws: str = "plane"):
     """The oracle on a bounded sample of the spin-glass workload: all
     replicas from the same random starts, the first sweeps."""
     import oracle
 
+    mode = oracle.MODE_PLANE if draws == "plane" else oracle.MODE_SITE
     threads = max(1, min(16, os.cpu_count() or 1))
     R, L = len(betas), J.shape[1]
     spins = np.stack([oracle.ea_init(L, oracle.START_RANDOM, seed, r) for r in range(R)])
     E = np.array([oracle.ea_energy(x, J) for x in spins])
     perm = np.arange(R, dtype=np.int32)
     t0 = time.perf_counter()
-    oracle.ea_run(spins, J, betas, seed, 0, 1, every, perm, E, trace=False, nthreads=threads)
+    oracle.ea_run(spins, J, betas, seed, 0, 1, every, perm, E, trace=False, nthreads=threads,
+                  mode=mode)
     one = time.perf_counter() - t0
     n = max(1, min(50, int(target_s / max(one, 1e-6))))
     t0 = time.perf_counter()
-    oracle.ea_run(spins, J, betas, seed, 1, n, every, perm, E, trace=False, nthreads=threads)
+    oracle.ea_run(spins, J, betas, seed, 1, n, every, perm, E, trace=False, nthreads=threads,
+                  mode=mode)
     dt = time.perf_counter() - t0
     return {"value": R * L ** 3 * n / (dt * 1e9), "unit": "spin-flip attempts/ns", "cores": threads,
             "kind": "oracle",
-            "sample": f"all {R} replicas, sweeps 1..{n} ({dt:.1f} s), exchange every {every}"}
+            "sample": f"all {R} replicas, sweeps 1..{n} ({dt:.1f} s), exchange every {every}, "
+                      f"{draws} draws"}
 
 
 def bench_ea(args):
@@ -432,7 +436,9 @@ def bench_ea(args):
     R = len(betas)
     nsw = args.sweeps if args.sweeps != 1000 else wl["sweeps"]
     J = ea_bonds(L, wl["bond_seed"])
-    g = lib.SpinGlass(J, betas, seed=wl["seed"], device=dev)
+    plane = args.draws == "plane"
+    kernel = "k_ea_halfsweep_bit" if plane else "k_ea_halfsweep"
+    g = lib.SpinGlass(J, betas, seed=wl["seed"], device=dev, draws=args.draws)
     # one block of `every` sweeps (4 launches per sweep) captured once and replayed
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -479,8 +485,8 @@ def bench_ea(args):
     attempts = R * L ** 3 * nsw
     ms_per_step = total_ms / args.steps
     achieved_tops = blocks * PHILOX_OPS_PER_BLOCK / (sweep_ms * 1e-3) / 1e12
-    prof = profiled_traffic("k_ea_halfsweep", "ea_L128_R64", "ea_kernels.hip") \
-        if (L == 128 and R == 64) else None
+    prof = profiled_traffic(kernel, "ea_plane_L128_R64" if plane else "ea_L128_R64",
+                            "ea_kernels.hip") if (L == 128 and R == 64) else None
     eff_gbs = attempts * 2.0 / (sweep_ms * 1e-3) / 1e9
     rec = {
         "metric": METRIC,
@@ -495,15 +501,17 @@ def bench_ea(args):
                         f"replicas at beta in [0.5, 1.2], exchange every {every} sweeps, {nsw} "
                         "sweeps per step (HIP-graph replay of one exchange period) + init + recount",
             "L": L, "replicas": R, "sweeps_per_step": nsw, "every": every,
-            "layout": "int8", "parallelism": "single GPU",
+            "draws": args.draws,
+            "layout": "int8 in HBM, colour bit planes in the workspace during a call" if plane
+                      else "int8", "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "TOP/s", "frac": round(achieved_tops / VALU_PEAK_TOPS, 4),
             "traffic": round(prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"])
             if prof else None,
-            "traffic_unit": "bytes per k_ea_halfsweep launch (rocprofv3, copy-scaled)",
-            "kernel": "k_ea_halfsweep (+ reduce and exchange kernels)",
+            "traffic_unit": f"bytes per {kernel} launch (rocprofv3, copy-scaled)",
+            "kernel": f"{kernel} (+ reduce and exchange kernels)",
             "kernel_ms": round(sweep_ms, 3),
             "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops in the last step",
         },
@@ -521,7 +529,8 @@ def bench_ea(args):
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline_ea(J, betas, wl["seed"], every, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline_ea(J, betas, wl["seed"], every, args.cpu_seconds,
+                                              args.draws)
     print(json.dumps(rec), flush=True)
 
 

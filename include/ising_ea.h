@@ -24,6 +24,13 @@
  *   iff r < ceil(2^32 exp(-beta dE)) (thresholds on the host in double).
  *   Random start: s = -1 iff the top bit of out[n & 3] of counter
  *   (n >> 2, r_id, 0, 2) is set.
+ *   Plane draws (draws = ISING_DRAWS_PLANE, L >= 64): the colour-c sites
+ *   with q >> 5 == g (one row) share the Philox blocks
+ *   (g, r_id, 2t + c, 1 | b << 8), b = 0..7, and the r of lane l = q & 31
+ *   has bit 31 - k equal to bit l of out[k & 3] of block k >> 2 (as the
+ *   BIT1 lattices of ising.h).  The spins stay INT8 in `spins`; a sweep
+ *   call packs them and the couplings into colour bit planes in the
+ *   workspace, updates 32 sites per lane, and unpacks the spins at its end.
  *   Exchange after sweep t when (t + 1) % every == 0, as exchange number
  *   m = (t + 1) / every - 1, over the pairs (k, k+1) with k = m & 1,
  *   (m & 1) + 2, ...; with D = E(replica at k) - E(replica at k+1): swapped
@@ -49,7 +56,7 @@ typedef struct ising_ea {
     int32_t abi_version;  /* must equal ISING_ABI_VERSION                     */
     int32_t L;            /* a power of two, 8..ISING_EA_MAX_L                  */
     int32_t replicas;     /* R, 1..ISING_EA_MAX_REPLICAS                        */
-    int32_t reserved;     /* 0                                                  */
+    int32_t draws;        /* ISING_DRAWS_SITE, or ISING_DRAWS_PLANE (L >= 64)   */
     uint64_t seed;        /* Philox key of starts, sweeps and exchanges        */
     int8_t *spins;        /* device, 256-B aligned, >= ising_ea_spins_bytes     */
     const int8_t *bonds;  /* device, 256-B aligned, int8 [3][L^3] of +1/-1      */
@@ -58,7 +65,8 @@ typedef struct ising_ea {
 
 ISING_API size_t ising_ea_spins_bytes(int32_t L, int32_t replicas);
 /* Workspace: sweep index, ladder order, energies, thresholds, swap
- * tables, per-block energy changes, error word.  0 if invalid. */
+ * tables, per-block energy changes, error word, and the bit planes of the
+ * plane-draw mode (R L^3/8 + 3 L^3/8 bytes).  0 if invalid. */
 ISING_API size_t ising_ea_workspace_bytes(int32_t L, int32_t replicas);
 
 /* Tabulate the Metropolis thresholds of every beta and the swap thresholds

@@ -131,11 +131,15 @@ void oracle_ea_init(int8_t *s, int L, int start, uint64_t seed, uint32_t replica
 
 /* Plane draws of half-sweep h for every colour-c site: r[n] for the sites
  * of colour c (entries of the other colour untouched). */
-void oracle_ea_fill_plane(uint32_t *r, int L, int c, uint64_t seed, uint32_t replica_id,
-                          uint32_t h)
+static void ea_fill_plane_threads(uint32_t *r, int L, int c, uint64_t seed, uint32_t replica_id,
+                                  uint32_t h, int nthreads)
 {
     int64_t N = (int64_t)L * L * L, half = N / 2, row = L / 2;
     int64_t groups = (half + 31) / 32;
+    (void)nthreads;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+#endif
     for (int64_t g = 0; g < groups; ++g) {
         uint32_t planes[32];
         for (int b = 0; b < 8; ++b) {
@@ -161,6 +165,12 @@ void oracle_ea_fill_plane(uint32_t *r, int L, int c, uint64_t seed, uint32_t rep
     }
 }
 
+void oracle_ea_fill_plane(uint32_t *r, int L, int c, uint64_t seed, uint32_t replica_id,
+                          uint32_t h)
+{
+    ea_fill_plane_threads(r, L, c, seed, replica_id, h, 1);
+}
+
 /* Update every site of colour c of one replica at inverse temperature beta
  * (sweep index t) with per-site (mode 0) or plane (mode 1) draws; the
  * energy change goes to *dE. */
@@ -181,7 +191,7 @@ int oracle_ea_halfsweep(int8_t *s, const int8_t *J, int L, int c, uint64_t seed,
         rp = (uint32_t *)calloc((size_t)N, sizeof(uint32_t));
         if (!rp)
             return 2;
-        oracle_ea_fill_plane(rp, L, c, seed, replica_id, h);
+        ea_fill_plane_threads(rp, L, c, seed, replica_id, h, nthreads < 1 ? 1 : nthreads);
     }
 #ifdef _OPENMP
 #pragma omp parallel for num_threads(nthreads) reduction(+ : total) schedule(static)

@@ -119,7 +119,7 @@ class ising_ea(ctypes.Structure):
         ("abi_version", ctypes.c_int32),
         ("L", ctypes.c_int32),
         ("replicas", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("draws", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("spins", ctypes.c_void_p),
         ("bonds", ctypes.c_void_p),
@@ -771,10 +771,12 @@ class Net:
 
 class SpinGlass:
     """R replicas of the 3D +-J glass (couplings `bonds`, int8 [3, L, L, L])
-    on a beta ladder, with replica exchange; torch-backed buffers."""
+    on a beta ladder, with replica exchange; torch-backed buffers.  draws:
+    "site" (per-site draws) or "plane" (bit-plane draws, L >= 64, 32 sites
+    per lane)."""
 
     def __init__(self, bonds, betas, seed: int = 3, start: str = "random", device=None,
-                 init: bool = True):
+                 init: bool = True, draws: str = "site"):
         import torch
 
         self.device = torch.device(device or "cuda")
@@ -789,7 +791,8 @@ class SpinGlass:
         self._bonds_raw, self.bonds = _aligned_buffer(bonds.nbytes, self.device)
         self.bonds.copy_(torch.from_numpy(bonds.reshape(-1).view(np.uint8)))
         self._ws_raw, self.workspace = _aligned_buffer(nw, self.device)
-        self.c = ising_ea(ABI_VERSION, self.L, self.R, 0, seed, self.spins.data_ptr(),
+        self.draws = {"site": DRAWS_SITE, "plane": DRAWS_PLANE}[draws]
+        self.c = ising_ea(ABI_VERSION, self.L, self.R, self.draws, seed, self.spins.data_ptr(),
                           self.bonds.data_ptr(), self.workspace.data_ptr())
         self.beta = np.ascontiguousarray(betas, np.float64)
         ising_ea_setup(self.c, self.beta, self._stream())

@@ -28,8 +28,11 @@ int validate(const ising_ea* ea) {
     if (ea->replicas < 1 || ea->replicas > ISING_EA_MAX_REPLICAS)
         return set_error(ISING_E_INVALID, "replicas = %d outside 1..%d", ea->replicas,
                          ISING_EA_MAX_REPLICAS);
-    if (ea->reserved != 0)
-        return set_error(ISING_E_INVALID, "reserved must be 0");
+    if (ea->draws != ISING_DRAWS_SITE && ea->draws != ISING_DRAWS_PLANE)
+        return set_error(ISING_E_INVALID, "draws = %d: ISING_DRAWS_SITE or ISING_DRAWS_PLANE",
+                         ea->draws);
+    if (ea->draws == ISING_DRAWS_PLANE && ea->L < 64)
+        return set_error(ISING_E_INVALID, "L = %d: plane draws need L >= 64", ea->L);
     if (!ea->spins || !aligned256(ea->spins) || !ea->bonds || !aligned256(ea->bonds) ||
         !ea->workspace || !aligned256(ea->workspace))
         return set_error(ISING_E_INVALID,
@@ -191,6 +194,18 @@ int ising_ea_sweep(const ising_ea* ea, int64_t n, int32_t every, int64_t* trace_
     unsigned char* ws = ws_of(ea);
     HIP_TRY(ising::launch_ea_prepare(ws, lay, ea->replicas, n, ising::kEaPrepareSweep, st),
             "ea prepare");
+    if (ea->draws == ISING_DRAWS_PLANE) {
+        HIP_TRY(ising::launch_ea_pack_bonds(ws, lay, ea->bonds, ea->L, st), "ea pack couplings");
+        HIP_TRY(ising::launch_ea_pack_spins(ws, lay, ea->spins, ea->L, ea->replicas, st),
+                "ea pack spins");
+        for (int64_t j = 0; j < n; ++j)
+            HIP_TRY(ising::launch_ea_sweep_bit(ws, lay, ea->L, ea->replicas, every, key_of(ea),
+                                               trace_dev, st),
+                    "ea sweep");
+        HIP_TRY(ising::launch_ea_unpack_spins(ws, lay, ea->spins, ea->L, ea->replicas, st),
+                "ea unpack spins");
+        return ISING_OK;
+    }
     for (int64_t j = 0; j < n; ++j)
         HIP_TRY(ising::launch_ea_sweep(ws, lay, ea->spins, ea->bonds, ea->L, ea->replicas, every,
                                        key_of(ea), trace_dev, st),

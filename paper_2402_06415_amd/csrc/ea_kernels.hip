@@ -15,6 +15,7 @@
 // Per-block energy changes go to a partials array; a per-sweep kernel sums
 // them in a fixed order, then the exchange kernel (a no-op between
 // exchanges) swaps temperatures and advances the device sweep index.
+#include "bitslice.hpp"
 #include "ea.hpp"
 
 namespace ising {
@@ -193,6 +194,208 @@ __global__ void k_ea_halfsweep(unsigned char* ws, const EaLayout lay, int8_t* sp
     __syncthreads();
     if (threadIdx.x == 0) {
         const int64_t at = ((int64_t)c * R + r) * bpr + bi;
+        reinterpret_cast<int32_t*>(ws + lay.partial)[at] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        reinterpret_cast<int32_t*>(ws + lay.partial_blk)[at] =
+            red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plane draws (L >= 64, a power of two): the colour-c spins of a replica are
+// bit planes, word g holding compact indices q = 32g .. 32g + 31 (q = n >> 1,
+// all in one row (z, y): g = (z L + y) L/64 + w), bit 1 meaning s = -1; the
+// couplings J_d(n) likewise by the colour of n.  One lane updates the 32
+// sites of a word with bitwise logic: a bond is unsatisfied where the XOR of
+// the two spin bits and the coupling bit is 1, the six unsatisfied bits are
+// summed bit-sliced into n_u (0..6), and the draws of group g (Philox blocks
+// (g, replica, 2t + c, 1 | b << 8), most significant plane first) are
+// compared with the class's threshold plane by plane until every site is
+// decided.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t T_NOR_OR = tt(~(kA | kB | kC));       // none set
+constexpr uint32_t T_A_NOT_BC = tt(kA & ~(kB | kC));     // a and neither b nor c
+constexpr uint32_t T_MAJ3 = tt((kA & kB) | (kA & kC) | (kB & kC));
+constexpr uint32_t T_OR_AND3 = tt(kA | (kB & kC));       // a | (b & c)
+constexpr uint32_t T_SEL3 = tt((kA & kB) | (~kA & kC));  // a ? b : c, bitwise
+constexpr uint32_t T_X3 = tt(kA ^ kB ^ kC);
+
+// Pack 64 bytes (x = 64w .. 64w + 63 of one row) into the word of the even
+// columns and the word of the odd ones (bit j <-> column 2j or 2j + 1).
+__device__ __forceinline__ void pack64(const int8_t* src, uint32_t& even, uint32_t& odd) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+    even = 0;
+    odd = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const uint4 u = s4[v];
+        const uint32_t wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 8 * v + 2 * e;  // compact column of byte 0 of this word
+            even |= ((wd[e] >> 7) & 1u) << j | ((wd[e] >> 23) & 1u) << (j + 1);
+            odd |= ((wd[e] >> 15) & 1u) << j | ((wd[e] >> 31) & 1u) << (j + 1);
+        }
+    }
+}
+
+// Spins: one thread per (replica, row, 64-column span) -> word w of both colours.
+__global__ void k_ea_pack_spins(uint32_t* sbits, const int8_t* spins, int lgL, int R) {
+    const int L = 1 << lgL, lgnw = lgL - 6;
+    const uint32_t wpc = 1u << (3 * lgL - 6);
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (g >= wpc)
+        return;
+    const uint32_t row = g >> lgnw, w = g & ((1u << lgnw) - 1);
+    const uint32_t y = row & (uint32_t)(L - 1), z = row >> lgL;
+    uint32_t even, odd;
+    pack64(spins + (size_t)r * ((size_t)wpc << 6) + ((size_t)row << lgL) + 64 * w, even, odd);
+    const int c_even = (int)((y + z) & 1u);  // colour of the even columns
+    sbits[((size_t)r * 2 + c_even) * wpc + g] = even;
+    sbits[((size_t)r * 2 + (c_even ^ 1)) * wpc + g] = odd;
+}
+
+__global__ void k_ea_unpack_spins(int8_t* spins, const uint32_t* sbits, int lgL, int R) {
+    const int L = 1 << lgL, lgnw = lgL - 6;
+    const uint32_t wpc = 1u << (3 * lgL - 6);
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (g >= wpc)
+        return;
+    const uint32_t row = g >> lgnw, w = g & ((1u << lgnw) - 1);
+    const uint32_t y = row & (uint32_t)(L - 1), z = row >> lgL;
+    const int c_even = (int)((y + z) & 1u);
+    const uint32_t even = sbits[((size_t)r * 2 + c_even) * wpc + g];
+    const uint32_t odd = sbits[((size_t)r * 2 + (c_even ^ 1)) * wpc + g];
+    uint4* dst = reinterpret_cast<uint4*>(spins + (size_t)r * ((size_t)wpc << 6) +
+                                          ((size_t)row << lgL) + 64 * w);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        uint32_t out[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 8 * v + 2 * e;
+            const uint32_t b0 = (even >> j) & 1u, b1 = (odd >> j) & 1u;
+            const uint32_t b2 = (even >> (j + 1)) & 1u, b3 = (odd >> (j + 1)) & 1u;
+            out[e] = (b0 ? 0xFFu : 0x01u) | (b1 ? 0xFF00u : 0x0100u) |
+                     (b2 ? 0xFF0000u : 0x010000u) | (b3 ? 0xFF000000u : 0x01000000u);
+        }
+        dst[v] = make_uint4(out[0], out[1], out[2], out[3]);
+    }
+}
+
+// Couplings: bonds[d N + n] -> jbits[d][colour of n][word].
+__global__ void k_ea_pack_bonds(uint32_t* jbits, const int8_t* bonds, int lgL) {
+    const int L = 1 << lgL, lgnw = lgL - 6;
+    const uint32_t wpc = 1u << (3 * lgL - 6);
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const int d = blockIdx.y;
+    if (g >= wpc)
+        return;
+    const uint32_t row = g >> lgnw, w = g & ((1u << lgnw) - 1);
+    const uint32_t y = row & (uint32_t)(L - 1), z = row >> lgL;
+    uint32_t even, odd;
+    pack64(bonds + (size_t)d * ((size_t)wpc << 6) + ((size_t)row << lgL) + 64 * w, even, odd);
+    const int c_even = (int)((y + z) & 1u);
+    jbits[((size_t)d * 2 + c_even) * wpc + g] = even;
+    jbits[((size_t)d * 2 + (c_even ^ 1)) * wpc + g] = odd;
+}
+
+// One half-sweep (colour c) of every replica with plane draws: grid
+// (words / 256, replica), one word per thread.
+__global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, const EaLayout lay,
+                                                          int lgL, int R, int c, Key key) {
+    EaHeader* hd = ea_header(ws);
+    if (hd->ok == 0)
+        return;
+    const int L = 1 << lgL, lgnw = lgL - 6;
+    const uint32_t wpc = 1u << (3 * lgL - 6);
+    const uint32_t nwm = (1u << lgnw) - 1, Lm = (uint32_t)L - 1;
+    const int r = blockIdx.y;
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    int dE = 0;
+    unsigned long long nblk = 0;
+    if (g < wpc) {
+        const uint32_t* sb = reinterpret_cast<const uint32_t*>(ws + lay.sbits);
+        const uint32_t* jb = reinterpret_cast<const uint32_t*>(ws + lay.jbits);
+        uint32_t* Pc = const_cast<uint32_t*>(sb) + ((size_t)r * 2 + c) * wpc;
+        const uint32_t* Po = sb + ((size_t)r * 2 + (c ^ 1)) * wpc;
+        const uint32_t* Jc[3] = {jb + (size_t)c * wpc, jb + (size_t)(2 + c) * wpc,
+                                 jb + (size_t)(4 + c) * wpc};
+        const uint32_t* Jo[3] = {jb + (size_t)(c ^ 1) * wpc, jb + (size_t)(2 + (c ^ 1)) * wpc,
+                                 jb + (size_t)(4 + (c ^ 1)) * wpc};
+        const uint32_t row = g >> lgnw, w = g & nwm;
+        const uint32_t y = row & Lm, z = row >> lgL;
+        const uint32_t p = (y + z + (uint32_t)c) & 1u;
+        const uint32_t rowb = g - w;
+        const uint32_t wm = rowb + ((w - 1) & nwm), wp = rowb + ((w + 1) & nwm);
+        const uint32_t gU = ((((z << lgL) | ((y - 1) & Lm)) << lgnw) | w);
+        const uint32_t gD = ((((z << lgL) | ((y + 1) & Lm)) << lgnw) | w);
+        const uint32_t gB = ((((((z - 1) & Lm) << lgL) | y) << lgnw) | w);
+        const uint32_t gF = ((((((z + 1) & Lm) << lgL) | y) << lgnw) | w);
+        const uint32_t W = Pc[g], O = Po[g];
+        // p = 0: O is the right neighbour (x + 1), the side word the left one;
+        // p = 1: O is the left neighbour, the side word the right one.
+        const uint32_t X = Po[p ? wp : wm];
+        const uint32_t S = p ? __builtin_amdgcn_alignbit(X, O, 1) : __builtin_amdgcn_alignbit(O, X, 31);
+        const uint32_t J0c = Jc[0][g], J0o = Jo[0][g];
+        const uint32_t bO = p ? J0o : J0c;  // J_x at the left site (p = 1) or at n (p = 0)
+        const uint32_t bS = p ? J0c : __builtin_amdgcn_alignbit(J0o, Jo[0][wm], 31);
+        const uint32_t u0 = bop3<T_X3>(W, O, bO);
+        const uint32_t u1 = bop3<T_X3>(W, S, bS);
+        const uint32_t u2 = bop3<T_X3>(W, Po[gU], Jo[1][gU]);  // y - 1: J_y at (x, y - 1, z)
+        const uint32_t u3 = bop3<T_X3>(W, Po[gD], Jc[1][g]);   // y + 1: J_y at n
+        const uint32_t u4 = bop3<T_X3>(W, Po[gB], Jo[2][gB]);  // z - 1: J_z at (x, y, z - 1)
+        const uint32_t u5 = bop3<T_X3>(W, Po[gF], Jc[2][g]);   // z + 1: J_z at n
+        // n_u = b0 + 2 b1 + 4 b2, bit-sliced
+        const uint32_t s1 = bop3<T_X3>(u0, u1, u2), c1 = bop3<T_MAJ3>(u0, u1, u2);
+        const uint32_t s2 = bop3<T_X3>(u3, u4, u5), c2 = bop3<T_MAJ3>(u3, u4, u5);
+        const uint32_t b0 = s1 ^ s2, k0 = s1 & s2;
+        const uint32_t b1 = bop3<T_X3>(c1, c2, k0), b2 = bop3<T_MAJ3>(c1, c2, k0);
+        // n_u >= 3 (u <= 0) flips without a draw; n_u = 2, 1, 0 are u = 2, 4, 6
+        const uint32_t ge3 = bop3<T_OR_AND3>(b2, b1, b0);
+        const uint32_t is0 = bop3<T_NOR_OR>(b0, b1, b2);
+        const uint32_t is1 = bop3<T_A_NOT_BC>(b0, b1, b2);
+        const uint32_t is2 = bop3<T_A_NOT_BC>(b1, b0, b2);
+        const EaAccept a = reinterpret_cast<const EaAccept*>(ws + lay.thr)[
+            reinterpret_cast<const int32_t*>(ws + lay.tidx)[r]];
+        const bool al2 = a.M2 == 0, al4 = a.M4 == 0, al6 = a.M6 == 0;  // always flips
+        WordState st;
+        st.W = W;
+        st.flip = ge3 | (al2 ? is2 : 0u) | (al4 ? is1 : 0u) | (al6 ? is0 : 0u);
+        st.und = (al2 ? 0u : is2) | (al4 ? 0u : is1) | (al6 ? 0u : is0);
+        const RoundKeys rk = scalar_round_keys(key);
+        const uint32_t h = 2u * (uint32_t)hd->t + (uint32_t)c;
+        for (uint32_t blk = 0; blk < 8u && (blk < 2u || st.und); ++blk) {
+            nblk += st.und ? 1u : 0u;
+            const U4 out = philox4x32_10({g, (uint32_t)r, h, kTagPlane | (blk << 8)}, rk);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int sh = 31 - (int)(4 * blk) - kk;
+                const uint32_t t2 = (uint32_t)((int)(a.T2 << (31 - sh)) >> 31);
+                const uint32_t t4 = (uint32_t)((int)(a.T4 << (31 - sh)) >> 31);
+                const uint32_t t6 = (uint32_t)((int)(a.T6 << (31 - sh)) >> 31);
+                const uint32_t tm = bop3<T_SEL3>(is2, t2, bop3<T_SEL3>(is1, t4, t6));
+                compare_plane(st, u4_get(out, kk), tm);
+            }
+        }
+        const uint32_t f = st.flip;
+        // dE = 2u = 12 - 4 n_u per flip
+        dE = 12 * __popc(f) - 4 * (__popc(f & b0) + 2 * __popc(f & b1) + 4 * __popc(f & b2));
+        Pc[g] = W ^ f;
+    }
+    // block sums of dE and of the Philox blocks drawn -> partials[c][r][bi]
+    __shared__ int red[2][4];
+    dE = wave_sum_i32(dE);
+    const int nb = wave_sum_i32((int)nblk);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = dE;
+        red[1][threadIdx.x >> 6] = nb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t at = ((int64_t)c * R + r) * lay.bpr_bit + blockIdx.x;
         reinterpret_cast<int32_t*>(ws + lay.partial)[at] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
         reinterpret_cast<int32_t*>(ws + lay.partial_blk)[at] =
             red[1][0] + red[1][1] + red[1][2] + red[1][3];
@@ -388,6 +591,12 @@ EaLayout ea_ws_layout(int L, int R) {
     o += up((size_t)2 * R * l.bpr * 4);
     l.rng_blocks = o;
     o += 256;
+    const size_t wpc = (size_t)L * L * L / 64;  // words per colour
+    l.bpr_bit = (int)((wpc + 255) / 256);
+    l.sbits = o;
+    o += up((size_t)R * 2 * wpc * 4);
+    l.jbits = o;
+    o += up((size_t)3 * 2 * wpc * 4);
     l.bytes = o;
     return l;
 }
@@ -425,6 +634,48 @@ hipError_t launch_ea_sweep(unsigned char* ws, const EaLayout& lay, int8_t* spins
         hipLaunchKernelGGL(k_ea_halfsweep, dim3((unsigned)lay.plane_blocks, (unsigned)L, (unsigned)R),
                            dim3(256), 0, st, ws, lay, spins, bonds, lgL, R, c, key);
     hipLaunchKernelGGL(k_ea_reduce, dim3(R), dim3(256), 0, st, ws, lay, R, lay.bpr, trace);
+    hipLaunchKernelGGL(k_ea_exchange, dim3(1), dim3(512), 0, st, ws, lay, R, every, key);
+    return hipGetLastError();
+}
+
+namespace {
+int log2_of(int L) {
+    int lg = 0;
+    while ((1 << lg) < L)
+        ++lg;
+    return lg;
+}
+}  // namespace
+
+hipError_t launch_ea_pack_bonds(unsigned char* ws, const EaLayout& lay, const int8_t* bonds, int L,
+                                hipStream_t st) {
+    const unsigned blocks = (unsigned)((((size_t)L * L * L / 64) + 255) / 256);
+    hipLaunchKernelGGL(k_ea_pack_bonds, dim3(blocks, 3), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t*>(ws + lay.jbits), bonds, log2_of(L));
+    return hipGetLastError();
+}
+
+hipError_t launch_ea_pack_spins(unsigned char* ws, const EaLayout& lay, const int8_t* spins, int L,
+                                int R, hipStream_t st) {
+    hipLaunchKernelGGL(k_ea_pack_spins, dim3((unsigned)lay.bpr_bit, (unsigned)R), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t*>(ws + lay.sbits), spins, log2_of(L), R);
+    return hipGetLastError();
+}
+
+hipError_t launch_ea_unpack_spins(unsigned char* ws, const EaLayout& lay, int8_t* spins, int L,
+                                  int R, hipStream_t st) {
+    hipLaunchKernelGGL(k_ea_unpack_spins, dim3((unsigned)lay.bpr_bit, (unsigned)R), dim3(256), 0,
+                       st, spins, reinterpret_cast<const uint32_t*>(ws + lay.sbits), log2_of(L), R);
+    return hipGetLastError();
+}
+
+hipError_t launch_ea_sweep_bit(unsigned char* ws, const EaLayout& lay, int L, int R, int every,
+                               Key key, int64_t* trace, hipStream_t st) {
+    const int lgL = log2_of(L);
+    for (int c = 0; c < 2; ++c)
+        hipLaunchKernelGGL(k_ea_halfsweep_bit, dim3((unsigned)lay.bpr_bit, (unsigned)R), dim3(256),
+                           0, st, ws, lay, lgL, R, c, key);
+    hipLaunchKernelGGL(k_ea_reduce, dim3(R), dim3(256), 0, st, ws, lay, R, lay.bpr_bit, trace);
     hipLaunchKernelGGL(k_ea_exchange, dim3(1), dim3(512), 0, st, ws, lay, R, every, key);
     return hipGetLastError();
 }

@@ -222,3 +222,28 @@ def test_batch_sweep_argument_errors():
     lib.ising_batch_sweep(b, 0)  # host-only early return
     with pytest.raises(lib.IsingError):
         lib.ising_batch_init(b, 9)
+
+
+def _ea(**kw):
+    d = dict(abi_version=binding.ABI_VERSION, L=64, replicas=2, draws=0, seed=1, spins=0x10000,
+             bonds=0x20000, workspace=0x30000)
+    d.update(kw)
+    return binding.ising_ea(**d)
+
+
+def test_ea_struct_layout_matches_header():
+    assert ctypes.sizeof(binding.ising_ea) == 48
+    assert binding.ising_ea.draws.offset == 12 and binding.ising_ea.seed.offset == 16
+
+
+@pytest.mark.parametrize("kw,msg", [(dict(draws=2), "draws"), (dict(draws=-1), "draws"),
+                                    (dict(draws=1, L=32), "plane draws need L >= 64"),
+                                    (dict(L=24), "power of two"),
+                                    (dict(workspace=0x30004), "aligned")])
+def test_invalid_spin_glasses_are_rejected_before_any_launch(kw, msg):
+    e = _ea(**kw)
+    before = bytes(e)
+    with pytest.raises(lib.IsingError) as err:
+        lib.ising_ea_setup(e, [0.4, 0.8])
+    assert err.value.code == binding.E_INVALID and msg in lib.ising_last_error()
+    assert bytes(e) == before
