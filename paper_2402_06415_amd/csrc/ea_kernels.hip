@@ -302,8 +302,10 @@ __global__ void k_ea_pack_bonds(uint32_t* jbits, const int8_t* bonds, int lgL) {
     jbits[((size_t)d * 2 + (c_even ^ 1)) * wpc + g] = odd;
 }
 
-// One half-sweep (colour c) of every replica with plane draws: grid
-// (words / 256, replica), one word per thread.
+// One half-sweep (colour c) of every replica with plane draws: one word per
+// thread, bpr_bit workgroups per replica.  Workgroups are dealt to the eight
+// XCDs in turn; when R is a multiple of 8 the blocks of replica r all go to
+// XCD r mod 8, so a replica's planes stay in one XCD's L2.
 __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, const EaLayout lay,
                                                           int lgL, int R, int c, Key key) {
     EaHeader* hd = ea_header(ws);
@@ -312,8 +314,17 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
     const int L = 1 << lgL, lgnw = lgL - 6;
     const uint32_t wpc = 1u << (3 * lgL - 6);
     const uint32_t nwm = (1u << lgnw) - 1, Lm = (uint32_t)L - 1;
-    const int r = blockIdx.y;
-    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t bpr = (uint32_t)lay.bpr_bit, i = blockIdx.x;
+    uint32_t r, bx;
+    if ((R & 7) == 0) {
+        const uint32_t j = i >> 3;
+        r = (i & 7u) + 8u * (j / bpr);
+        bx = j % bpr;
+    } else {
+        r = i / bpr;
+        bx = i % bpr;
+    }
+    const uint32_t g = bx * 256u + threadIdx.x;
     int dE = 0;
     unsigned long long nblk = 0;
     if (g < wpc) {
@@ -395,7 +406,7 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int64_t at = ((int64_t)c * R + r) * lay.bpr_bit + blockIdx.x;
+        const int64_t at = ((int64_t)c * R + r) * lay.bpr_bit + bx;
         reinterpret_cast<int32_t*>(ws + lay.partial)[at] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
         reinterpret_cast<int32_t*>(ws + lay.partial_blk)[at] =
             red[1][0] + red[1][1] + red[1][2] + red[1][3];
@@ -673,8 +684,8 @@ hipError_t launch_ea_sweep_bit(unsigned char* ws, const EaLayout& lay, int L, in
                                Key key, int64_t* trace, hipStream_t st) {
     const int lgL = log2_of(L);
     for (int c = 0; c < 2; ++c)
-        hipLaunchKernelGGL(k_ea_halfsweep_bit, dim3((unsigned)lay.bpr_bit, (unsigned)R), dim3(256),
-                           0, st, ws, lay, lgL, R, c, key);
+        hipLaunchKernelGGL(k_ea_halfsweep_bit, dim3((unsigned)(lay.bpr_bit * R)), dim3(256), 0, st,
+                           ws, lay, lgL, R, c, key);
     hipLaunchKernelGGL(k_ea_reduce, dim3(R), dim3(256), 0, st, ws, lay, R, lay.bpr_bit, trace);
     hipLaunchKernelGGL(k_ea_exchange, dim3(1), dim3(512), 0, st, ws, lay, R, every, key);
     return hipGetLastError();
