@@ -302,10 +302,16 @@ __global__ void k_ea_pack_bonds(uint32_t* jbits, const int8_t* bonds, int lgL) {
     jbits[((size_t)d * 2 + (c_even ^ 1)) * wpc + g] = odd;
 }
 
-// One half-sweep (colour c) of every replica with plane draws: one word per
-// thread, bpr_bit workgroups per replica.  Workgroups are dealt to the eight
-// XCDs in turn; when R is a multiple of 8 the blocks of replica r all go to
-// XCD r mod 8, so a replica's planes stay in one XCD's L2.
+// Words per thread of the plane half-sweep: the round keys and the
+// threshold masks of the first eight planes are set up once per thread and
+// reused for each of its words.
+constexpr int kEaWordsPerThread = 4;
+
+// One half-sweep (colour c) of every replica with plane draws: kEaWordsPerThread
+// words per thread (256 words apart), bpr_bit / kEaWordsPerThread workgroups
+// per replica.  Workgroups are dealt to the eight XCDs in turn; when R is a
+// multiple of 8 the blocks of replica r all go to XCD r mod 8, so a replica's
+// planes stay in one XCD's L2.
 __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, const EaLayout lay,
                                                           int lgL, int R, int c, Key key) {
     EaHeader* hd = ea_header(ws);
@@ -314,7 +320,7 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
     const int L = 1 << lgL, lgnw = lgL - 6;
     const uint32_t wpc = 1u << (3 * lgL - 6);
     const uint32_t nwm = (1u << lgnw) - 1, Lm = (uint32_t)L - 1;
-    const uint32_t bpr = (uint32_t)lay.bpr_bit, i = blockIdx.x;
+    const uint32_t bpr = (uint32_t)lay.bpr_bit / kEaWordsPerThread, i = blockIdx.x;
     uint32_t r, bx;
     if ((R & 7) == 0) {
         const uint32_t j = i >> 3;
@@ -324,18 +330,36 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
         r = i / bpr;
         bx = i % bpr;
     }
-    const uint32_t g = bx * 256u + threadIdx.x;
+    const uint32_t* sb = reinterpret_cast<const uint32_t*>(ws + lay.sbits);
+    const uint32_t* jb = reinterpret_cast<const uint32_t*>(ws + lay.jbits);
+    uint32_t* Pc = const_cast<uint32_t*>(sb) + ((size_t)r * 2 + c) * wpc;
+    const uint32_t* Po = sb + ((size_t)r * 2 + (c ^ 1)) * wpc;
+    const uint32_t* J0c = jb + (size_t)c * wpc;
+    const uint32_t* J0o = jb + (size_t)(c ^ 1) * wpc;
+    const uint32_t* J1c = jb + (size_t)(2 + c) * wpc;
+    const uint32_t* J1o = jb + (size_t)(2 + (c ^ 1)) * wpc;
+    const uint32_t* J2c = jb + (size_t)(4 + c) * wpc;
+    const uint32_t* J2o = jb + (size_t)(4 + (c ^ 1)) * wpc;
+    const EaAccept a = reinterpret_cast<const EaAccept*>(ws + lay.thr)[
+        reinterpret_cast<const int32_t*>(ws + lay.tidx)[r]];
+    const bool al2 = a.M2 == 0, al4 = a.M4 == 0, al6 = a.M6 == 0;  // always flips
+    // per-thread constants: Philox round keys, threshold masks of planes 0-7
+    const RoundKeys rk = round_keys(key);
+    uint32_t t2m[8], t4m[8], t6m[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        t2m[k] = 0u - ((a.T2 >> (31 - k)) & 1u);
+        t4m[k] = 0u - ((a.T4 >> (31 - k)) & 1u);
+        t6m[k] = 0u - ((a.T6 >> (31 - k)) & 1u);
+        asm volatile("" : "+v"(t2m[k]), "+v"(t4m[k]), "+v"(t6m[k]));
+    }
+    const uint32_t h = 2u * (uint32_t)hd->t + (uint32_t)c;
     int dE = 0;
     unsigned long long nblk = 0;
-    if (g < wpc) {
-        const uint32_t* sb = reinterpret_cast<const uint32_t*>(ws + lay.sbits);
-        const uint32_t* jb = reinterpret_cast<const uint32_t*>(ws + lay.jbits);
-        uint32_t* Pc = const_cast<uint32_t*>(sb) + ((size_t)r * 2 + c) * wpc;
-        const uint32_t* Po = sb + ((size_t)r * 2 + (c ^ 1)) * wpc;
-        const uint32_t* Jc[3] = {jb + (size_t)c * wpc, jb + (size_t)(2 + c) * wpc,
-                                 jb + (size_t)(4 + c) * wpc};
-        const uint32_t* Jo[3] = {jb + (size_t)(c ^ 1) * wpc, jb + (size_t)(2 + (c ^ 1)) * wpc,
-                                 jb + (size_t)(4 + (c ^ 1)) * wpc};
+    for (int k = 0; k < kEaWordsPerThread; ++k) {
+        const uint32_t g = (bx * kEaWordsPerThread + (uint32_t)k) * 256u + threadIdx.x;
+        if (g >= wpc)
+            break;
         const uint32_t row = g >> lgnw, w = g & nwm;
         const uint32_t y = row & Lm, z = row >> lgL;
         const uint32_t p = (y + z + (uint32_t)c) & 1u;
@@ -350,15 +374,15 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
         // p = 1: O is the left neighbour, the side word the right one.
         const uint32_t X = Po[p ? wp : wm];
         const uint32_t S = p ? __builtin_amdgcn_alignbit(X, O, 1) : __builtin_amdgcn_alignbit(O, X, 31);
-        const uint32_t J0c = Jc[0][g], J0o = Jo[0][g];
-        const uint32_t bO = p ? J0o : J0c;  // J_x at the left site (p = 1) or at n (p = 0)
-        const uint32_t bS = p ? J0c : __builtin_amdgcn_alignbit(J0o, Jo[0][wm], 31);
+        const uint32_t jc = J0c[g], jo = J0o[g];
+        const uint32_t bO = p ? jo : jc;  // J_x at the left site (p = 1) or at n (p = 0)
+        const uint32_t bS = p ? jc : __builtin_amdgcn_alignbit(jo, J0o[wm], 31);
         const uint32_t u0 = bop3<T_X3>(W, O, bO);
         const uint32_t u1 = bop3<T_X3>(W, S, bS);
-        const uint32_t u2 = bop3<T_X3>(W, Po[gU], Jo[1][gU]);  // y - 1: J_y at (x, y - 1, z)
-        const uint32_t u3 = bop3<T_X3>(W, Po[gD], Jc[1][g]);   // y + 1: J_y at n
-        const uint32_t u4 = bop3<T_X3>(W, Po[gB], Jo[2][gB]);  // z - 1: J_z at (x, y, z - 1)
-        const uint32_t u5 = bop3<T_X3>(W, Po[gF], Jc[2][g]);   // z + 1: J_z at n
+        const uint32_t u2 = bop3<T_X3>(W, Po[gU], J1o[gU]);  // y - 1: J_y at (x, y - 1, z)
+        const uint32_t u3 = bop3<T_X3>(W, Po[gD], J1c[g]);   // y + 1: J_y at n
+        const uint32_t u4 = bop3<T_X3>(W, Po[gB], J2o[gB]);  // z - 1: J_z at (x, y, z - 1)
+        const uint32_t u5 = bop3<T_X3>(W, Po[gF], J2c[g]);   // z + 1: J_z at n
         // n_u = b0 + 2 b1 + 4 b2, bit-sliced
         const uint32_t s1 = bop3<T_X3>(u0, u1, u2), c1 = bop3<T_MAJ3>(u0, u1, u2);
         const uint32_t s2 = bop3<T_X3>(u3, u4, u5), c2 = bop3<T_MAJ3>(u3, u4, u5);
@@ -369,34 +393,43 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
         const uint32_t is0 = bop3<T_NOR_OR>(b0, b1, b2);
         const uint32_t is1 = bop3<T_A_NOT_BC>(b0, b1, b2);
         const uint32_t is2 = bop3<T_A_NOT_BC>(b1, b0, b2);
-        const EaAccept a = reinterpret_cast<const EaAccept*>(ws + lay.thr)[
-            reinterpret_cast<const int32_t*>(ws + lay.tidx)[r]];
-        const bool al2 = a.M2 == 0, al4 = a.M4 == 0, al6 = a.M6 == 0;  // always flips
         WordState st;
         st.W = W;
         st.flip = ge3 | (al2 ? is2 : 0u) | (al4 ? is1 : 0u) | (al6 ? is0 : 0u);
         st.und = (al2 ? 0u : is2) | (al4 ? 0u : is1) | (al6 ? 0u : is0);
-        const RoundKeys rk = scalar_round_keys(key);
-        const uint32_t h = 2u * (uint32_t)hd->t + (uint32_t)c;
-        for (uint32_t blk = 0; blk < 8u && (blk < 2u || st.und); ++blk) {
+        // blocks 0 and 1 straight-line with the masks in registers
+#pragma unroll
+        for (uint32_t blk = 0; blk < 2; ++blk) {
             nblk += st.und ? 1u : 0u;
-            const U4 out = philox4x32_10({g, (uint32_t)r, h, kTagPlane | (blk << 8)}, rk);
+            const U4 out = philox4x32_10({g, r, h, kTagPlane | (blk << 8)}, rk);
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const int sh = 31 - (int)(4 * blk) - kk;
-                const uint32_t t2 = (uint32_t)((int)(a.T2 << (31 - sh)) >> 31);
-                const uint32_t t4 = (uint32_t)((int)(a.T4 << (31 - sh)) >> 31);
-                const uint32_t t6 = (uint32_t)((int)(a.T6 << (31 - sh)) >> 31);
-                const uint32_t tm = bop3<T_SEL3>(is2, t2, bop3<T_SEL3>(is1, t4, t6));
+                const int q = 4 * (int)blk + kk;
+                const uint32_t tm = bop3<T_SEL3>(is2, t2m[q], bop3<T_SEL3>(is1, t4m[q], t6m[q]));
+                compare_plane(st, u4_get(out, kk), tm);
+            }
+        }
+        // further blocks while the lane has undecided sites
+        for (uint32_t blk = 2; blk < 8u && st.und; ++blk) {
+            ++nblk;
+            const U4 out = philox4x32_10({g, r, h, kTagPlane | (blk << 8)}, rk);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const uint32_t sh = 31u - (4u * blk + (uint32_t)kk);
+                // uniform values: these stay on the scalar unit
+                const uint32_t t2 = 0u - ((a.T2 >> sh) & 1u), t4 = 0u - ((a.T4 >> sh) & 1u);
+                const uint32_t t6 = 0u - ((a.T6 >> sh) & 1u);
+                const uint32_t tm = bop3_vsv<T_SEL3>(is2, t2, bop3_vsv<T_SEL3>(is1, t4, t6));
                 compare_plane(st, u4_get(out, kk), tm);
             }
         }
         const uint32_t f = st.flip;
         // dE = 2u = 12 - 4 n_u per flip
-        dE = 12 * __popc(f) - 4 * (__popc(f & b0) + 2 * __popc(f & b1) + 4 * __popc(f & b2));
+        dE += 12 * __popc(f) - 4 * (__popc(f & b0) + 2 * __popc(f & b1) + 4 * __popc(f & b2));
         Pc[g] = W ^ f;
     }
-    // block sums of dE and of the Philox blocks drawn -> partials[c][r][bi]
+    // block sums of dE and of the Philox blocks drawn -> partials[c][r][bx],
+    // bpr entries per replica
     __shared__ int red[2][4];
     dE = wave_sum_i32(dE);
     const int nb = wave_sum_i32((int)nblk);
@@ -406,7 +439,7 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int64_t at = ((int64_t)c * R + r) * lay.bpr_bit + bx;
+        const int64_t at = ((int64_t)c * R + r) * bpr + bx;
         reinterpret_cast<int32_t*>(ws + lay.partial)[at] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
         reinterpret_cast<int32_t*>(ws + lay.partial_blk)[at] =
             red[1][0] + red[1][1] + red[1][2] + red[1][3];
@@ -684,9 +717,10 @@ hipError_t launch_ea_sweep_bit(unsigned char* ws, const EaLayout& lay, int L, in
                                Key key, int64_t* trace, hipStream_t st) {
     const int lgL = log2_of(L);
     for (int c = 0; c < 2; ++c)
-        hipLaunchKernelGGL(k_ea_halfsweep_bit, dim3((unsigned)(lay.bpr_bit * R)), dim3(256), 0, st,
-                           ws, lay, lgL, R, c, key);
-    hipLaunchKernelGGL(k_ea_reduce, dim3(R), dim3(256), 0, st, ws, lay, R, lay.bpr_bit, trace);
+        hipLaunchKernelGGL(k_ea_halfsweep_bit, dim3((unsigned)(lay.bpr_bit / kEaWordsPerThread * R)),
+                           dim3(256), 0, st, ws, lay, lgL, R, c, key);
+    hipLaunchKernelGGL(k_ea_reduce, dim3(R), dim3(256), 0, st, ws, lay, R,
+                       lay.bpr_bit / kEaWordsPerThread, trace);
     hipLaunchKernelGGL(k_ea_exchange, dim3(1), dim3(512), 0, st, ws, lay, R, every, key);
     return hipGetLastError();
 }
