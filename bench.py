@@ -97,6 +97,20 @@ def profiled_traffic(kernel_name: str, summary: str = "sweep_bit1_L4096",
     return rec
 
 
+def tile_plan_fits(L: int, cus: int) -> bool:
+    """Whether the bit-packed sweep of side L runs as the LDS-resident tile
+    kernel: the host-side rule of the library's tile plan (tiles that divide
+    L, up to four per CU once each keeps four rows, at most 1024, each within
+    its share of the CU's 160 KiB of LDS and 64 KiB)."""
+    nw = L >> 6
+    if nw < 1 or cus < 1:
+        return False
+    tpc = 4 if L >= 16 * cus else 1
+    cap = min(160 * 1024 // tpc, 64 * 1024)
+    return any(L % t == 0 and 2 * (L // t + 2) * nw * 4 <= cap
+               for t in range(min(cus * tpc, 1024, L), 1, -1))
+
+
 def cpu_baseline(L: int, seed: int, target_s: float):
     """The oracle (unchanged, plane draws, OpenMP over rows) on a bounded
     sample: the first sweeps of the same lattice from the same start."""
@@ -668,10 +682,10 @@ def main():
     # effective HBM roofline: 2 bits per attempt (read + write once per sweep)
     alg_bytes = attempts * 0.25
     eff_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    # the library's tile plan (one LDS-resident tile of rows per workgroup,
-    # at most 64 KiB each, one workgroup per CU) covers L <= 8192 on 256 CUs;
-    # larger lattices run one launch per half-sweep from global memory
-    tiles = not args.global_halfsweep and L <= 8192
+    # the library's tile plan keeps the lattice in LDS while its tiles fit
+    # (L <= 16384 on 256 CUs); larger lattices run one launch per half-sweep
+    # from global memory
+    tiles = not args.global_halfsweep and tile_plan_fits(L, torch.cuda.get_device_properties(0).multi_processor_count)
     kernel_name = "k_sweep_bit1_tiles" if tiles else "k_halfsweep_bit1"
     prof = profiled_traffic(kernel_name) if (L == 4096 and nsw == 1000) else None
     traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None

@@ -115,9 +115,6 @@ unsigned long long* ws_blocks(const ising_lattice* lat) {
 // healthy wait lasts microseconds, so this only ends a broken run.
 constexpr uint32_t kSpinLimit = 1u << 24;
 
-// Tiles (workgroups) of the persistent bit-packed sweep per CU.
-constexpr int kTilesPerCU = 1;
-
 // Zero acc[0..1] and recount E, M of the current spins into acc (raw
 // counts) then finish into E_out/M_out and copies.
 int measure_into(const ising_lattice* lat, long long* E_out, long long* M_out, long long* E_copy,
@@ -269,7 +266,7 @@ int ising_sweep(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev, int6
     } else {
         uint32_t* planes = reinterpret_cast<uint32_t*>(lat->spins);
         ising::Bit1TilePlan plan;
-        if (!global_only && ising::plan_bit1_tiles(L, device_cus(), kTilesPerCU, &plan)) {
+        if (!global_only && ising::plan_bit1_tiles(L, device_cus(), &plan)) {
             HIP_TRY(ising::launch_sweep_bit1_tiles(planes, L, plan, n, t0, key, lat->lattice_id,
                                                    acc, Etr, Mtr, ws_of(lat), kSpinLimit, st),
                     "sweep_bit1_tiles");

@@ -452,10 +452,15 @@ size_t tile_lds_bytes(int L, int rows) {
     return (size_t)2 * (rows + 2) * (L >> 6) * sizeof(uint32_t);
 }
 
-bool plan_bit1_tiles(int L, int device_cus, int tiles_per_cu, Bit1TilePlan* plan) {
+// Tiles (workgroups) per CU: four when each still holds at least four rows,
+// so that a half-sweep barrier spans a quarter of the CU's waves and the
+// other tiles keep its SIMDs busy meanwhile; one for smaller lattices, whose
+// tiles would be all edge rows waiting on their neighbours.
+bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
     const int nw = L >> 6;
-    if (nw < 1 || nw > 0xFFFF || tiles_per_cu < 1)
+    if (nw < 1 || nw > 0xFFFF || device_cus < 1)
         return false;
+    const int tiles_per_cu = (int64_t)L >= (int64_t)16 * device_cus ? 4 : 1;
     int maxt = device_cus * tiles_per_cu;
     if (maxt > WsLayout::kMaxTiles)
         maxt = WsLayout::kMaxTiles;
@@ -484,7 +489,9 @@ bool plan_bit1_tiles(int L, int device_cus, int tiles_per_cu, Bit1TilePlan* plan
         return false;
     plan->ntiles = best;
     plan->rows = L / best;
-    plan->threads = 64 * (plan->rows < 16 ? plan->rows : 16);
+    // at most 16 waves per CU in all: the tiles sharing a CU split them
+    const int wmax = 16 / tiles_per_cu > 1 ? 16 / tiles_per_cu : 1;
+    plan->threads = 64 * (plan->rows < wmax ? plan->rows : wmax);
     plan->lds = tile_lds_bytes(L, plan->rows);
     return true;
 }

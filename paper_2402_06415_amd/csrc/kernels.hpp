@@ -49,11 +49,10 @@ hipError_t launch_from_int8_bit1(uint32_t* planes, int L, const int8_t* in, hipS
 struct Bit1TilePlan {
     int ntiles = 0;     // workgroups, one tile of rows each
     int rows = 0;       // rows per tile
-    int threads = 0;    // workgroup size: one wave per row, at most 16 waves
+    int threads = 0;    // workgroup size: one wave per row, at most 16 waves per CU
     size_t lds = 0;     // dynamic LDS bytes
 };
-// tiles_per_cu: how many tiles (workgroups) may share one CU.
-bool plan_bit1_tiles(int L, int device_cus, int tiles_per_cu, Bit1TilePlan* plan);
+bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan);
 hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& plan,
                                    int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
                                    long long* dE, long long* dM, unsigned char* ws,

@@ -185,6 +185,18 @@ def test_throughput_workload_L4096_bit1_first_sweeps(record):
     _compare_stepwise(4096, "bit1", 7, "random", BC, 6, chunk=2, record=record)
 
 
+def test_bit1_tile_kernel_L8192_two_rows_per_wave():
+    """L = 8192 puts four tiles of eight rows on each CU, four waves per
+    tile: every wave updates two rows per half-sweep."""
+    _compare_stepwise(8192, "bit1", 3, "random", BC, 3, chunk=2, record=True)
+
+
+def test_bit1_tile_kernel_L16384_four_words_per_lane():
+    """L = 16384: four tiles of sixteen rows per CU still fit LDS; a lane
+    updates four words of each of its four rows per half-sweep."""
+    _compare_stepwise(16384, "bit1", 4, "random", BC, 2, chunk=2, record=True)
+
+
 def test_throughput_workload_L4096_sampled_over_1000_sweeps():
     """Full 10^3-sweep run: one call equals the split run, and sampled
     sweeps are checked one by one against the oracle from the GPU state."""
