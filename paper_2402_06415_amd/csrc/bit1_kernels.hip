@@ -200,11 +200,17 @@ __global__ void k_from_int8_bit1(uint32_t* planes, int L, const int8_t* in) {
 //
 // Each workgroup owns `rows` consecutive full-width rows (both colours) in
 // LDS for the whole call, the GPU analogue of the paper's supercell with a
-// dedicated update block per group of spins.  Per half-sweep the waves
-// holding the first and last row need the facing row of the neighbouring
-// tile, of the other colour, from the previous half-sweep; they run first,
-// at raised priority, and the interior rows, which depend only on the
-// tile itself, are updated behind them.
+// dedicated update block per group of spins.  The tile also keeps one halo
+// row above and below it, per colour: the facing rows of the neighbouring
+// tiles.  In each half-sweep the waves holding the first and last row
+// update them first, at raised priority, and publish them.  When a wave
+// holds several rows, the edge waves, once done with all their rows, wait
+// for the neighbours' facing rows of the colour just updated and store them
+// as the tile's halo rows while the interior rows are still being updated
+// (the next half-sweep then reads LDS only).  With one row per wave that
+// wait would hold up the half-sweep's barrier, so the edge waves instead
+// wait for the neighbours' rows at the start of the next half-sweep, while
+// the interior rows proceed.
 //
 // Rows are handed over through halo slots of 64-bit words, each carrying
 // the 32-bit spin word and, in the high half, the number of the half-sweep
@@ -212,11 +218,11 @@ __global__ void k_from_int8_bit1(uint32_t* planes, int L, const int8_t* in) {
 // the one it expects, so each hand-off involves a single memory location
 // (relaxed agent-scope atomics: no cache write-back or invalidation, no
 // grid-wide barrier).  A slot of colour c is rewritten two half-sweeps
-// later, only after its writer has read the neighbour's next row, which
-// the neighbour publishes after reading the slot.  Slots are zeroed before
-// every call, so no tag from an earlier call can match.  Waits are bounded:
-// on time-out the device error word is set and the kernel runs to
-// completion.
+// later, only after its writer has received the neighbour's next row,
+// which the neighbour publishes only after it has received the slot (both
+// receipts precede a workgroup barrier).  Slots are zeroed before every
+// call, so no tag from an earlier call can match.  Waits are bounded: on
+// time-out the device error word is set and the kernel runs to completion.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint32_t wait_slot(const unsigned long long* slot, uint32_t tag,
@@ -292,16 +298,16 @@ __device__ __forceinline__ void store_tile(uint32_t* planes, const uint32_t* til
                     tile[(col * t.tr + r + 1) * t.nw + w];
 }
 
-// Update row r of colour c of the tile (both neighbours of every word are
-// available): one word per lane, 64-word chunks.  Rows 0 and rows-1 read
-// the facing row of the neighbouring tile from its halo slot (after the
-// first half-sweep) and publish their own.
-template <bool kObs>
+// Update row r of colour c of the tile: one word per lane, 64-word chunks.
+// Rows 0 and rows-1 publish their new words for the neighbouring tiles;
+// with kLate they first take the neighbours' facing rows from the slots
+// (after the first half-sweep), otherwise from the tile's halo rows.
+template <bool kObs, bool kLate>
 __device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, int rows, int r,
                                            int64_t hs, uint32_t t0, uint32_t lid,
                                            const Accept& acc, const DrawConsts& dc,
-                                           unsigned long long* halo,
-                                           uint32_t* err, uint32_t spin_limit, int& dE, int& dM,
+                                           unsigned long long* halo, uint32_t* err,
+                                           uint32_t spin_limit, int& dE, int& dM,
                                            unsigned long long& nblk) {
     const int c = (int)(hs & 1), o = c ^ 1;
     const int nw = t.nw;
@@ -311,6 +317,7 @@ __device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, in
     uint32_t* Tc = tile + c * t.tr * nw;
     const uint32_t* To = tile + o * t.tr * nw;
     const bool first = (r == 0), last = (r == rows - 1);
+    const bool wait = kLate && hs > 0;
     const int y = t.y0 + r;
     for (int w = (int)(threadIdx.x & 63); w < nw; w += 64) {
         const int wm = (w == 0) ? nw - 1 : w - 1;
@@ -319,10 +326,10 @@ __device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, in
         const uint32_t W = Tc[(r + 1) * nw + w];
         const uint32_t O = Orow[w];
         const uint32_t S = side_word(O, Orow[wm], Orow[wp], (y + c) & 1);
-        const uint32_t U = (hs > 0 && first)
+        const uint32_t U = (wait && first)
                                ? wait_slot(halo_row(halo, nw, t.up, o, 1) + w, tag_in, spin_limit, err)
                                : To[r * nw + w];
-        const uint32_t D = (hs > 0 && last)
+        const uint32_t D = (wait && last)
                                ? wait_slot(halo_row(halo, nw, t.down, o, 0) + w, tag_in, spin_limit, err)
                                : To[(r + 2) * nw + w];
         WordState st = classify(W, O, S, U, D, acc);
@@ -336,6 +343,17 @@ __device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, in
     }
 }
 
+// Receive the facing row of colour c that a neighbouring tile published in
+// half-sweep hs (tag hs + 1) into halo row `dst` (0 above the tile, rows + 1
+// below it) of the tile's colour-c plane.
+__device__ __forceinline__ void receive_row(uint32_t* tile, const TileGeom& t, int c, int dst,
+                                            const unsigned long long* slots, uint32_t tag,
+                                            uint32_t spin_limit, uint32_t* err) {
+    uint32_t* row = tile + (c * t.tr + dst) * t.nw;
+    for (int w = (int)(threadIdx.x & 63); w < t.nw; w += 64)
+        row[w] = wait_slot(slots + w, tag, spin_limit, err);
+}
+
 // Row order within a half-sweep: the first and last rows, which the
 // neighbouring tiles wait for, come first; interior rows after them.
 __device__ __forceinline__ int row_of(int k, int rows) {
@@ -345,7 +363,7 @@ __device__ __forceinline__ int row_of(int k, int rows) {
 // All rows of a half-sweep complete before the next starts (one workgroup
 // barrier per half-sweep); with kObs the workgroup also sums the energy and
 // magnetisation changes of each sweep into the traces.
-template <bool kObs>
+template <bool kObs, bool kLate>
 __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
     uint32_t* planes, int L, int rows, int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
     long long* dEtr, long long* dMtr, unsigned long long* halo, uint32_t* err,
@@ -367,10 +385,22 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
             const bool edge = (r == 0) || (r == rows - 1);
             if (edge)
                 __builtin_amdgcn_s_setprio(3);
-            update_row<kObs>(tile, t, rows, r, hs, t0, lid, acc, dc, halo, err, spin_limit, dE, dM,
-                             nblk);
+            update_row<kObs, kLate>(tile, t, rows, r, hs, t0, lid, acc, dc, halo, err, spin_limit,
+                                    dE, dM, nblk);
             if (edge)
                 __builtin_amdgcn_s_setprio(0);
+        }
+        // with several rows per wave, the waves of the first and last row
+        // take in the neighbours' rows of this colour for the next
+        // half-sweep (row_of: k = 0 is the first row, k = 1 the last)
+        if (!kLate && hs + 1 < 2 * n) {
+            const int c = (int)(hs & 1);
+            const uint32_t tag = (uint32_t)hs + 1u;
+            if (wave == 0)
+                receive_row(tile, t, c, 0, halo_row(halo, t.nw, t.up, c, 1), tag, spin_limit, err);
+            if (wave == (rows == 1 ? 0 : 1 % nwaves))
+                receive_row(tile, t, c, rows + 1, halo_row(halo, t.nw, t.down, c, 0), tag,
+                            spin_limit, err);
         }
         sE += dE;
         sM += dM;
@@ -511,8 +541,15 @@ hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& 
     int rows = plan.rows;
     void* args[] = {&planes, (void*)&L, &rows, &n, &t0, &key, &lid, &acc, &dE, &dM,
                     &halo, &err, &nblk, &spin_limit};
-    const void* kern = (dE || dM) ? reinterpret_cast<const void*>(k_sweep_bit1_tiles<true>)
-                                  : reinterpret_cast<const void*>(k_sweep_bit1_tiles<false>);
+    // one row per wave: the edge waves wait for the neighbours' rows when
+    // they next need them; several: they receive them before the barrier
+    const bool late = plan.rows * 64 <= plan.threads;
+    const bool obs = dE || dM;
+    const void* kern =
+        obs ? (late ? reinterpret_cast<const void*>(k_sweep_bit1_tiles<true, true>)
+                    : reinterpret_cast<const void*>(k_sweep_bit1_tiles<true, false>))
+            : (late ? reinterpret_cast<const void*>(k_sweep_bit1_tiles<false, true>)
+                    : reinterpret_cast<const void*>(k_sweep_bit1_tiles<false, false>));
     return hipLaunchCooperativeKernel(kern, dim3(plan.ntiles), dim3(plan.threads), args, plan.lds,
                                       st);
 }
