@@ -56,7 +56,9 @@ ISING_API int ising_xy_init(const ising_xy *xy, int32_t start, void *hip_stream)
 
 /* n sweeps of every lattice at inverse temperature beta from the device
  * sweep index; E_trace_dev (device double[n][count], may be NULL)
- * receives H of every lattice after every sweep.  Errors: invalid
+ * receives H of every lattice after every sweep: H summed over the
+ * lattice at the start of the call, plus the energy changes of the trials
+ * accepted since (equal to a recount up to rounding).  Errors: invalid
  * description, beta negative or not finite, n < 0 -> ISING_E_INVALID;
  * device: workspace not initialised or t + n > 2^31 (see
  * ising_xy_check_device_error). */

@@ -4,8 +4,20 @@
 // sweeps of a call (L <= 128: 128 KiB).  Within a half-sweep the threads
 // take the sites of one colour in turn; a site's trial reads its four
 // neighbours (the other colour) from LDS and writes its own angle, so the
-// update is in place and race-free.  After each sweep the workgroup sums H
-// for the energy trace.  Every floating-point operation is rounded on its
+// update is in place and race-free.
+//
+// Where LDS also holds cos and sin of every angle (24 bytes per site, L <= 82)
+// the energy change of a trial is formed from them by the angle-difference
+// identity, cos(a - b) = cos a cos b + sin a sin b: one sincos of the
+// proposed angle per trial instead of eight cosines, and an accepted angle
+// stores the pair just computed.  The result equals the direct sum up to
+// rounding, so the two forms can decide a trial differently only when the
+// uniform draw lies within a few units in the last place of the acceptance
+// probability.  For the energy trace H is summed over
+// the lattice once per call and then carried from sweep to sweep by adding
+// the energy changes of the accepted trials (each wave sums its own, and
+// thread 0 adds the per-wave partials in a fixed order behind the next
+// half-sweep barrier).  Every floating-point operation is rounded on its
 // own (no fused multiply-add), as the trial is defined operation by
 // operation.
 #include "xy.hpp"
@@ -15,6 +27,8 @@ namespace ising {
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586;  // nearest double to 2 pi
+// dynamic LDS up to which the sweep also keeps cos and sin of every angle
+constexpr size_t kXyCacheLds = 156 * 1024;
 
 struct XyHeader {
     uint32_t magic, count;
@@ -106,11 +120,12 @@ __global__ void k_xy_advance(unsigned char* ws, int64_t n) {
         hd->t += (uint64_t)n;
 }
 
+template <bool kCache>
 __global__ void __launch_bounds__(512) k_xy_sweep(unsigned char* ws, double* theta, int L,
                                                   int count, int64_t n, double beta, Key key,
                                                   uint32_t lid0, double* E_trace) {
 #pragma clang fp contract(off)
-    extern __shared__ double th[];
+    extern __shared__ double th[];  // [N] angles, then with kCache [N] cos and [N] sin
     __shared__ double red[16];
     XyHeader* hd = xy_header(ws);
     if (hd->ok == 0)
@@ -120,11 +135,23 @@ __global__ void __launch_bounds__(512) k_xy_sweep(unsigned char* ws, double* the
     const int N = L * L, half = L >> 1;
     const uint32_t t0 = (uint32_t)hd->t;
     double* g = theta + (int64_t)j * N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x)
+    double* const cs = th + N;
+    double* const sn = th + 2 * N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
         th[i] = g[i];
+        if (kCache)
+            sincos(th[i], &sn[i], &cs[i]);
+    }
     __syncthreads();
     const RoundKeys rk = round_keys(key);
     unsigned long long acc = 0;
+    // per-wave sums of the accepted energy changes, by sweep parity
+    __shared__ double part[2][16];
+    const int nwaves = (int)(blockDim.x >> 6), wave = (int)(threadIdx.x >> 6);
+    double E = 0.0;  // thread 0: H after the sweeps so far
+    if (E_trace)
+        E = energy_to0(th, L, red);
+    double dEs = 0.0;  // this thread's accepted changes in the current sweep
     for (int64_t sw = 0; sw < n; ++sw) {
         for (int c = 0; c < 2; ++c) {
             const uint32_t h = 2u * (t0 + (uint32_t)sw) + (uint32_t)c;
@@ -134,27 +161,59 @@ __global__ void __launch_bounds__(512) k_xy_sweep(unsigned char* ws, double* the
                 const U4 o = philox4x32_10({(uint32_t)q, lid, h, kTagXy}, rk);
                 const double th_new = unit53(o.x, o.y) * kTwoPi;
                 const double p = unit53(o.z, o.w);
-                const double t = th[row + x];
-                const double nb[4] = {th[row + (x + 1 == L ? 0 : x + 1)],
-                                      th[row + (x == 0 ? L - 1 : x - 1)],
-                                      th[(y + 1 == L ? 0 : y + 1) * L + x],
-                                      th[(y == 0 ? L - 1 : y - 1) * L + x]};
-                double d = 0.0;
+                const int i = row + x;
+                const int nbi[4] = {row + (x + 1 == L ? 0 : x + 1), row + (x == 0 ? L - 1 : x - 1),
+                                    (y + 1 == L ? 0 : y + 1) * L + x,
+                                    (y == 0 ? L - 1 : y - 1) * L + x};
+                double d = 0.0, c_new = 0.0, s_new = 0.0;
+                if (kCache) {
+                    // sum_k cos(a - b_k) = cos a sum_k cos b_k + sin a sum_k sin b_k
+                    sincos(th_new, &s_new, &c_new);
+                    double sc = 0.0, ss = 0.0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    d += cos(th_new - nb[k]) - cos(t - nb[k]);
+                    for (int k = 0; k < 4; ++k) {
+                        sc += cs[nbi[k]];
+                        ss += sn[nbi[k]];
+                    }
+                    d = (c_new - cs[i]) * sc + (s_new - sn[i]) * ss;
+                } else {
+                    const double t = th[i];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        d += cos(th_new - th[nbi[k]]) - cos(t - th[nbi[k]]);
+                }
                 const double dE = -d;
                 const double P = exp(-beta * dE);
                 if (p < P) {
-                    th[row + x] = th_new;
+                    th[i] = th_new;
+                    if (kCache) {
+                        cs[i] = c_new;
+                        sn[i] = s_new;
+                    }
                     ++acc;
+                    dEs += dE;
                 }
             }
+            if (E_trace && c == 1) {
+                const double w = wave_sum_f64(dEs);
+                dEs = 0.0;
+                if ((threadIdx.x & 63) == 0)
+                    part[sw & 1][wave] = w;
+            }
             __syncthreads();
+            // the previous sweep's partials are complete behind this barrier
+            // and are rewritten only after the next one
+            if (E_trace && c == 0 && sw > 0 && threadIdx.x == 0) {
+                for (int v = 0; v < nwaves; ++v)
+                    E += part[(sw - 1) & 1][v];
+                E_trace[(sw - 1) * count + j] = E;
+            }
         }
-        const double E = energy_to0(th, L, red);
-        if (threadIdx.x == 0 && E_trace)
-            E_trace[sw * count + j] = E;
+    }
+    if (E_trace && n > 0 && threadIdx.x == 0) {
+        for (int v = 0; v < nwaves; ++v)
+            E += part[(n - 1) & 1][v];
+        E_trace[(n - 1) * count + j] = E;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x)
         g[i] = th[i];
@@ -203,8 +262,13 @@ hipError_t launch_xy_sweep(unsigned char* ws, double* theta, int L, int count, i
     // has at 1024 threads)
     int threads = ((L * L / 2 + 63) / 64) * 64;
     threads = threads < 64 ? 64 : (threads > 512 ? 512 : threads);
-    hipLaunchKernelGGL(k_xy_sweep, dim3(count), dim3(threads), (size_t)L * L * sizeof(double), st,
-                       ws, theta, L, count, n, beta, key, lid0, E_trace);
+    const size_t plane = (size_t)L * L * sizeof(double);
+    if (3 * plane <= kXyCacheLds)
+        hipLaunchKernelGGL(k_xy_sweep<true>, dim3(count), dim3(threads), 3 * plane, st, ws, theta,
+                           L, count, n, beta, key, lid0, E_trace);
+    else
+        hipLaunchKernelGGL(k_xy_sweep<false>, dim3(count), dim3(threads), plane, st, ws, theta, L,
+                           count, n, beta, key, lid0, E_trace);
     hipLaunchKernelGGL(k_xy_advance, dim3(1), dim3(1), 0, st, ws, n);
     return hipGetLastError();
 }

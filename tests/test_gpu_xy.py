@@ -1,11 +1,14 @@
 """GPU parity of the XY model against the float64 oracle (oracle/xy_oracle.c).
 
-Both sides draw the same Philox trials and evaluate the trial operation by
-operation in double precision without fused multiply-adds, so the angles
-must agree bit for bit: a decision could only differ where p lies within
-the last-place difference of the two libraries' cos/exp of the threshold
-(probability ~1e-16 per trial).  Energies are sums of L^2 cosines in
-different orders: within 1e-12 relative of 2 L^2."""
+Both sides draw the same Philox trials and form the energy change in
+double precision without fused multiply-adds: the oracle as the sum of
+eight cosines of angle differences, the kernel the same way for L > 82 and
+through cached cos/sin of every angle and the angle-difference identity
+below that.  The two agree to a few units in the last place, so the angles
+must agree bit for bit: a decision could only differ where p lies that
+close to the acceptance probability (probability ~1e-15 per trial).  The
+energy trace is a recount at the start of each call plus the accepted
+changes: within 1e-12 relative of 2 L^2 of the oracle's recount."""
 import sys
 
 import numpy as np
@@ -76,6 +79,13 @@ def test_xy_bit_exact_at_the_papers_temperature(L):
 @pytest.mark.parametrize("beta", [0.0, 0.3, 20.0])
 def test_xy_beta_cases(beta):
     _compare(8, 2, beta, 5, (6,), start="cold" if beta == 20.0 else "random")
+
+
+@pytest.mark.parametrize("L", [64, 80, 84])
+def test_xy_cos_sin_cache_boundary(L):
+    """L = 80 is the largest side whose angles, cosines and sines fit LDS
+    together (150 KiB); L = 84 takes the direct form."""
+    _compare(L, 2, BETA_XY, 13, (4, 3), lid0=1)
 
 
 def test_xy_papers_largest_size():
