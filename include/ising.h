@@ -172,8 +172,11 @@ ISING_API int ising_check_device_error(const ising_lattice *lat, void *hip_strea
  * where a group of 32 compact columns spans rows 2g and 2g + 1; every L
  * must be 32 or a multiple of 64).  Each lattice stays in LDS for all n
  * sweeps of a call, as bytes (site draws) or as two colour bit planes
- * updated 32 sites per lane (plane draws); workgroups take lattices from
- * device work queues, largest L first.
+ * updated 32 sites per lane (plane draws).  With site draws workgroups take
+ * lattices from a device work queue, largest L first; with plane draws the
+ * largest-first order is dealt out to the workgroups in a snake (positions
+ * g, 2G - 1 - g, 2G + g, ... to workgroup g of G), and each workgroup sweeps
+ * its lattices together, one team of lanes per lattice.
  * The sweep index t of the batch lives in device memory (in the
  * workspace) and is advanced on the device, so that the launches of
  * ising_batch_sweep can be captured once in a HIP graph and replayed: each

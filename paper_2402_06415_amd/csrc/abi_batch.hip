@@ -73,7 +73,7 @@ struct Shape {
 int fit_groups(int threads, int want, int max_L, int draws) {
     const size_t lds = (draws == ISING_DRAWS_PLANE ? ising::batch_bit_lds_bytes(threads, max_L)
                                                    : ising::batch_lds_bytes(max_L)) +
-                       1024;  // + static LDS of the kernel
+                       2048;  // + static LDS of the kernel
     int g = want;
     g = std::min<int>(g, (int)(kLdsPerCU / lds));
     g = std::min<int>(g, kThreadsPerCU / threads);
@@ -95,13 +95,24 @@ int grid_of(const ising_batch* b, const Shape& s) {
     return std::max(1, std::min(b->count, cus * s.groups_per_cu));
 }
 
+// Dynamic LDS of a plane-draw workgroup: its share of the CU's LDS (at most
+// 128 KiB), and at least both planes of one lattice of side max_L.
+size_t plane_lds_bytes(const ising_batch* b, const Shape& s) {
+    const size_t need = ising::batch_bit_lds_bytes(s.threads, b->max_L);
+    size_t share = kLdsPerCU / (size_t)s.groups_per_cu;
+    share = share > 2048 ? share - 2048 : 0;  // static LDS of the kernel
+    share = std::min<size_t>(share, 128 * 1024) & ~(size_t)255;
+    return std::max(need, share);
+}
+
 // The sweep kernel of the batch's draw mode.
 hipError_t launch_sweep_of(const ising_batch* b, unsigned char* ws, bool scratch_t, int8_t* spins,
                            int64_t n, int64_t* moments, int64_t* trace, const Shape& s, int grid,
                            hipStream_t st) {
     if (b->draws == ISING_DRAWS_PLANE)
-        return ising::launch_batch_sweep_bit(ws, scratch_t, b->count, spins, b->max_L, n,
-                                             key_of(b), moments, trace, s.threads, grid, st);
+        return ising::launch_batch_sweep_bit(ws, scratch_t, b->count, spins, n, key_of(b),
+                                             moments, trace, s.threads, grid,
+                                             plane_lds_bytes(b, s), st);
     return ising::launch_batch_sweep(ws, scratch_t, b->count, spins, b->max_L, n, key_of(b),
                                      moments, trace, s.threads, grid, st);
 }
@@ -178,28 +189,12 @@ int ising_batch_setup(const ising_batch* b, const int32_t* L_host, const double*
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t c) { return L_host[a] > L_host[c]; });
-    // classes: runs of equal L in the queue order (used by the plane-draw sweep)
-    std::vector<ising::BatchClass> cls;
-    for (int i = 0; i < count; ++i) {
-        const int L = L_host[order[i]];
-        if (cls.empty() || cls.back().L != L)
-            cls.push_back(ising::BatchClass{L, i, 0, 0u});
-        ++cls.back().count;
-    }
-    if (b->draws == ISING_DRAWS_PLANE && cls.size() > (size_t)ising::kBatchMaxClasses)
-        return set_error(ISING_E_INVALID, "more than %d distinct sides", ising::kBatchMaxClasses);
-    const uint32_t ncls = cls.size() <= (size_t)ising::kBatchMaxClasses ? (uint32_t)cls.size() : 0u;
-    cls.resize(ising::kBatchMaxClasses, ising::BatchClass{0, 0, 0, 0u});
-    const uint32_t cls_head[2] = {ncls, (uint32_t)b->draws};
+    const uint32_t draws = (uint32_t)b->draws;
     const uint32_t head[2] = {ising::kBatchMagic, (uint32_t)count};
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     unsigned char* ws = ws_of(b);
-    HIP_TRY(hipMemcpyAsync(ws + BatchWs::kClasses, cls.data(),
-                           cls.size() * sizeof(ising::BatchClass), hipMemcpyHostToDevice, st),
-            "copy class table");
-    HIP_TRY(hipMemcpyAsync(ws + BatchWs::kNClasses, cls_head, sizeof cls_head,
-                           hipMemcpyHostToDevice, st),
-            "copy class count");
+    HIP_TRY(hipMemcpyAsync(ws + BatchWs::kDraws, &draws, sizeof draws, hipMemcpyHostToDevice, st),
+            "copy draw mode");
     HIP_TRY(hipMemcpyAsync(ws + BatchWs::kOrder, order.data(), order.size() * 4,
                            hipMemcpyHostToDevice, st),
             "copy queue order");

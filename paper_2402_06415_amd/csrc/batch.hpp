@@ -13,9 +13,7 @@ struct BatchWs {
     static constexpr size_t kOk = 24;         // uint32: the last prepare found everything valid
     static constexpr size_t kQueue = 32;      // uint32 work-queue head (cleared per launch)
     static constexpr size_t kErr = 40;        // uint32 device error word
-    static constexpr size_t kNClasses = 48;   // uint32: entries of the class table
     static constexpr size_t kDraws = 52;      // uint32: the draw mode given at setup
-    static constexpr size_t kClasses = 64;    // BatchClass[kBatchMaxClasses]
     static constexpr size_t kRngBlocks = 256; // uint64[64] Philox blocks since init
     static constexpr size_t kRngScratch = 768;// uint64[64] Philox blocks of autotuner runs
     static constexpr size_t kOrder = 1280;    // int32[count]: queue position -> lattice
@@ -52,23 +50,12 @@ struct BatchDesc {
 };
 static_assert(sizeof(BatchDesc) == 32, "descriptor layout");
 
-// Lattices of one side, consecutive in the queue order (which is sorted by
-// side, largest first); the bit-plane sweep hands them out in bundles.
-struct BatchClass {
-    int32_t L, start, count;
-    uint32_t next;  // queue head of the class (cleared per launch)
-};
-static_assert(sizeof(BatchClass) == 16, "class layout");
-constexpr int kBatchMaxClasses = 8;
-static_assert(BatchWs::kClasses + kBatchMaxClasses * sizeof(BatchClass) <= BatchWs::kRngBlocks,
-              "class table overlaps the draw counters");
-
 enum BatchPrepareMode { kPrepareSweep = 0, kPrepareInit = 1, kPrepareMeasure = 2 };
 // Validate the workspace against (count, spins_bytes, max_L) and, for a
 // sweep, t + n; write the ok word; init mode also zeroes t and the draw
 // counters, sweep mode clears the queue head.  One small workgroup.
 // draws: the sweep's draw mode (0 site, 1 plane), checked against setup's in
-// sweep mode; the class queues are cleared there too.
+// sweep mode.
 hipError_t launch_batch_prepare(unsigned char* ws, bool scratch_t, int count, uint64_t spins_bytes,
                                 int max_L, int64_t n, int mode, int draws, hipStream_t st);
 hipError_t launch_batch_init(unsigned char* ws, int count, int8_t* spins, int start, Key key,
@@ -82,11 +69,12 @@ hipError_t launch_batch_measure(unsigned char* ws, int count, const int8_t* spin
                                 int64_t* M, hipStream_t st);
 size_t batch_lds_bytes(int max_L);
 // Bit-plane draws: lattices of side 32 or a multiple of 64, kept in LDS as
-// colour bit planes and updated 32 sites per lane (bitslice.hpp); lattices
-// of one side are handed out in bundles that fill a workgroup.
+// colour bit planes and updated 32 sites per lane (bitslice.hpp); each
+// workgroup runs its share of the lattices together, as many at once as fit
+// lds_bytes of dynamic LDS (at least batch_bit_lds_bytes).
 hipError_t launch_batch_sweep_bit(unsigned char* ws, bool scratch_t, int count, int8_t* spins,
-                                  int max_L, int64_t n, Key key, int64_t* moments, int64_t* trace,
-                                  int threads, int blocks, hipStream_t st);
+                                  int64_t n, Key key, int64_t* moments, int64_t* trace,
+                                  int threads, int blocks, size_t lds_bytes, hipStream_t st);
 size_t batch_bit_lds_bytes(int threads, int max_L);
 
 }  // namespace ising

@@ -11,11 +11,13 @@
 // 2g (bits 0-15) and 2g + 1 (bits 16-31).  Word g draws the Philox blocks
 // (g, lattice id, 2t + c, 1 | b << 8), as the oracle's plane mode.
 //
-// Work is handed out in bundles: lattices of one side are consecutive in
-// the queue order, and a workgroup takes as many of them as it has teams
-// of one lane per word (tt = min(L^2/64, threads) lanes per team), so a
-// bundle is about the same work for every side.  Teams of at most 64
-// lanes sit inside one wave and need no workgroup barrier.
+// Work is dealt out statically: the queue order is sorted by side, largest
+// first, and workgroup g of G takes positions g, 2G - 1 - g, 2G + g, ...
+// (a snake over the workgroups), so every workgroup gets lattices of every
+// side and a near-equal share of words.  A workgroup runs its lattices
+// together, one team of lanes per lattice with the same number of words
+// per lane, in lockstep: one barrier per half-sweep, none at all when every
+// team sits inside one wave.
 #include "batch.hpp"
 #include "bitslice.hpp"
 
@@ -184,76 +186,129 @@ __device__ __forceinline__ void count_bits(const uint32_t* P, const BitGeom& b, 
     }
 }
 
-// Sum over the lanes of a team of tt <= 64 lanes (aligned within the wave).
-__device__ __forceinline__ int team_sum_small(int v, int tt) {
-    for (int off = tt >> 1; off > 0; off >>= 1)
-        v += __shfl_xor(v, off, 64);
+// Lanes of a team for nwc words at k words per lane: whole waves from 64
+// lanes up, a power of two below (so that teams sorted by size stay aligned).
+__device__ __forceinline__ int team_lanes(int nwc, int k) {
+    const int x = (nwc + k - 1) / k;
+    if (x >= 64)
+        return (x + 63) & ~63;
+    int p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+// Sum over an aligned team of tt lanes (tt a power of two up to 64; a team
+// of more lanes gets the sum over its part of this wave).  Every lane takes
+// part in every shuffle.
+__device__ __forceinline__ int team_sum(int v, int tt) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(v, off, 64);
+        if (off < tt)
+            v += o;
+    }
     return v;
 }
 
-// Persistent sweep with bit-plane draws.  Workgroups take bundles off the
-// class queues, largest side first, until every queue is empty; no
-// workgroup waits on another.
+// Most lattices a workgroup runs at once, one team of lanes each.
+constexpr int kMaxTeams = 64;
+
+// Persistent sweep with bit-plane draws.  Workgroup g of G owns the
+// lattices at queue positions r G + g for even r and r G + G - 1 - g for
+// odd r (the queue is sorted by side, largest first, so each workgroup gets
+// a near-equal share of words).  It runs as many of them at once as fit its
+// LDS (lds_words) and kMaxTeams: with k words per lane, the smallest k for
+// which every lattice gets a team of ceil(words / k) lanes, all lattices of
+// the pass sweep in lockstep with one barrier per half-sweep.  No workgroup
+// waits on another.
 __global__ void __launch_bounds__(1024) k_batch_sweep_bit(unsigned char* ws, int scratch_t,
                                                           int count, int8_t* spins, int64_t n,
                                                           Key key, int64_t* moments,
-                                                          int64_t* trace) {
+                                                          int64_t* trace, int lds_words) {
     extern __shared__ uint32_t planes[];
-    __shared__ int s_cls, s_idx;
+    __shared__ int s_team[kMaxTeams][4];  // lattice, first lane, lanes, LDS word offset
+    __shared__ int s_nteam, s_next, s_small;
     __shared__ int redi[2][2][16];
     __shared__ long long red[16];
     if (ws_u32(ws, BatchWs::kOk) == 0)
         return;  // uniform: every workgroup reads the same word
     const BatchDesc* desc = reinterpret_cast<const BatchDesc*>(ws + BatchWs::desc_offset(count));
     const int32_t* order = reinterpret_cast<const int32_t*>(ws + BatchWs::kOrder);
-    BatchClass* cls = reinterpret_cast<BatchClass*>(ws + BatchWs::kClasses);
-    const int ncls = (int)ws_u32(ws, BatchWs::kNClasses);
     unsigned long long* slots = reinterpret_cast<unsigned long long*>(
         ws + (scratch_t ? BatchWs::kRngScratch : BatchWs::kRngBlocks));
     const uint32_t t0 = (uint32_t)*reinterpret_cast<const uint64_t*>(
         ws + (scratch_t ? BatchWs::kTScratch : BatchWs::kT));
     const int tid = threadIdx.x, bd = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63;
+    const int G = (int)gridDim.x, gid = (int)blockIdx.x;
     unsigned long long nblk = 0;
-    int kc = 0;  // class cursor (thread 0)
+    int r = 0;  // next round of this workgroup's queue positions
     for (;;) {
         if (tid == 0) {
-            int got = -1;
-            while (kc < ncls) {
-                const int L = cls[kc].L, nwc = L * L / 64;
-                const int tt = nwc < bd ? nwc : bd;
-                const uint32_t i = atomicAdd(&cls[kc].next, (uint32_t)(bd / tt));
-                if (i < (uint32_t)cls[kc].count) {
-                    got = (int)i;
+            // the next lattices of this workgroup while they fit
+            int nt = 0, words = 0, lds = 0, rr = r;
+            for (; nt < kMaxTeams; ++rr) {
+                const int64_t pos = (int64_t)rr * G + ((rr & 1) ? G - 1 - gid : gid);
+                if (pos >= count)
                     break;
-                }
-                ++kc;
+                const int j = order[pos];
+                const int nwc = desc[j].L * desc[j].L / 64;
+                if (nt > 0 && lds + 2 * nwc > lds_words)
+                    break;
+                s_team[nt][0] = j;
+                s_team[nt][3] = lds;
+                lds += 2 * nwc;
+                words += nwc;
+                ++nt;
             }
-            s_cls = got < 0 ? -1 : kc;
-            s_idx = got;
+            int k = words > bd ? (words + bd - 1) / bd : 1;
+            for (;; ++k) {
+                int lanes = 0;
+                for (int q = 0; q < nt; ++q) {
+                    const int L = desc[s_team[q][0]].L;
+                    lanes += team_lanes(L * L / 64, k);
+                }
+                if (lanes <= bd)
+                    break;
+            }
+            int lane0 = 0, small = 1;
+            for (int q = 0; q < nt; ++q) {
+                const int L = desc[s_team[q][0]].L;
+                const int tt = team_lanes(L * L / 64, k);
+                s_team[q][1] = lane0;
+                s_team[q][2] = tt;
+                lane0 += tt;
+                small &= tt <= 64 ? 1 : 0;
+            }
+            s_nteam = nt;
+            s_next = rr;
+            s_small = small;
         }
         __syncthreads();
-        const int kcl = s_cls, i0 = s_idx;
-        __syncthreads();
-        if (kcl < 0)
-            break;
-        const BatchClass C = cls[kcl];
-        const BitGeom b = bit_geom(C.L);
-        if (!(b.L == 32 || (b.L % 64) == 0)) {
-            if (tid == 0)
-                atomicOr(&ws_u32(ws, BatchWs::kErr), kBatchErrDraws);
-            continue;  // uniform
-        }
-        const int tt = b.nwc < bd ? b.nwc : bd;
-        const int per = bd / tt;
-        const bool big = tt > 64;  // the team spans waves: workgroup barriers
-        const int team = tid / tt, tl = tid - team * tt;
-        const bool active = team < per && i0 + team < C.count;
-        const int j = active ? order[C.start + i0 + team] : 0;
+        const int nt = s_nteam;
+        if (nt == 0)
+            break;  // uniform
+        const bool small = s_small != 0;  // every team within one wave: no workgroup barriers
+        int team = -1;
+        for (int q = 0; q < nt; ++q)
+            if (tid >= s_team[q][1] && tid < s_team[q][1] + s_team[q][2])
+                team = q;
+        const int j = team >= 0 ? s_team[team][0] : 0;
+        const int tt = team >= 0 ? s_team[team][2] : 1;
+        const int tl = team >= 0 ? tid - s_team[team][1] : 0;
+        const bool big = tt > 64;  // the team spans waves
         const BatchDesc d = desc[j];
+        const BitGeom b = bit_geom(d.L);
+        bool active = team >= 0;
+        if (active && !(b.L == 32 || (b.L % 64) == 0)) {
+            if (tl == 0)
+                atomicOr(&ws_u32(ws, BatchWs::kErr), kBatchErrDraws);
+            active = false;
+        }
         const Accept acc{d.T2, d.T4, d.always & 1u, (d.always >> 1) & 1u};
         const DrawConsts dc = draw_consts(key, acc);
-        uint32_t* P = planes + (size_t)(team < per ? team : 0) * 2 * b.nwc;
+        uint32_t* P = planes + (team >= 0 ? s_team[team][3] : 0);
         if (active)
             pack_lattice(P, spins + d.off, b, tl, tt);
         __syncthreads();
@@ -262,32 +317,29 @@ __global__ void __launch_bounds__(1024) k_batch_sweep_bit(unsigned char* ws, int
         if (active)
             count_bits(P, b, tl, tt, anti, ones);
         long long E = 0, M = 0;
-        if (big) {
-            const int a = wave_sum_i32(anti), o = wave_sum_i32(ones);
-            if (lane == 0) {
+        {
+            const int a = team_sum(anti, tt), o = team_sum(ones, tt);
+            if (big && lane == 0) {
                 redi[0][0][wave] = a;
                 redi[0][1][wave] = o;
             }
             __syncthreads();
-            if (tl == 0 && active) {
-                long long A = 0, Oc = 0;
-                for (int w = team * (tt >> 6); w < (team + 1) * (tt >> 6); ++w) {
+            long long A = a, Oc = o;
+            if (big && tl == 0) {
+                A = 0;
+                Oc = 0;
+                for (int w = (tid >> 6); w < (tid >> 6) + (tt >> 6); ++w) {
                     A += redi[0][0][w];
                     Oc += redi[0][1][w];
                 }
-                E = 2 * A - 2 * (long long)b.L * b.L;
-                M = (long long)b.L * b.L - 2 * Oc;
             }
+            E = 2 * A - 2 * (long long)b.L * b.L;
+            M = (long long)b.L * b.L - 2 * Oc;
             __syncthreads();
-        } else {
-            const int a = team_sum_small(anti, tt), o = team_sum_small(ones, tt);
-            E = 2 * (long long)a - 2 * (long long)b.L * b.L;
-            M = (long long)b.L * b.L - 2 * (long long)o;
         }
         long long sE = 0, sE2 = 0, sAM = 0, sM2 = 0;
         unsigned long long m4lo = 0, m4hi = 0;
-        // neighbour sources of this lane's first two words (the launch shapes
-        // of the autotuner give at most two words per lane from 512 threads)
+        // neighbour sources of this lane's first two words
         const WordNb nb0 = word_nb(b, tl < b.nwc ? tl : 0);
         const WordNb nb1 = word_nb(b, tl + tt < b.nwc ? tl + tt : 0);
         for (int64_t sw = 0; sw < n; ++sw) {
@@ -297,39 +349,41 @@ __global__ void __launch_bounds__(1024) k_batch_sweep_bit(unsigned char* ws, int
                 if (active) {
                     uint32_t* Pc = P + c * b.nwc;
                     const uint32_t* Po = P + (c ^ 1) * b.nwc;
-                    for (int g = tl, k = 0; g < b.nwc; g += tt, ++k) {
+                    for (int g = tl, q = 0; g < b.nwc; g += tt, ++q) {
                         uint32_t O, S, U, D;
-                        neighbours(Po, b, g, k == 0 ? nb0 : (k == 1 ? nb1 : word_nb(b, g)), c, O,
+                        neighbours(Po, b, g, q == 0 ? nb0 : (q == 1 ? nb1 : word_nb(b, g)), c, O,
                                    S, U, D);
                         WordState st = classify(Pc[g], O, S, U, D, acc);
                         draw_planes<false>(st, (uint32_t)g, h, d.lid, acc, dc, nblk);
                         Pc[g] = finalize<true>(st, dE, dM);
                     }
                 }
-                if (big) {
-                    if (c == 0)
-                        __syncthreads();
-                } else {
+                if (small) {
                     wave_sync();
+                } else if (c == 0) {
+                    __syncthreads();
                 }
             }
-            if (big) {
+            const int e = team_sum(dE, tt), m = team_sum(dM, tt);
+            if (small) {
+                E += e;
+                M += m;
+            } else {
                 const int par = (int)(sw & 1);
-                const int e = wave_sum_i32(dE), m = wave_sum_i32(dM);
-                if (lane == 0) {
+                if (big && lane == 0) {
                     redi[par][0][wave] = e;
                     redi[par][1][wave] = m;
                 }
                 __syncthreads();
-                if (tl == 0 && active) {
-                    for (int w = team * (tt >> 6); w < (team + 1) * (tt >> 6); ++w) {
+                if (!big) {
+                    E += e;
+                    M += m;
+                } else if (tl == 0) {
+                    for (int w = (tid >> 6); w < (tid >> 6) + (tt >> 6); ++w) {
                         E += redi[par][0][w];
                         M += redi[par][1][w];
                     }
                 }
-            } else {
-                E += team_sum_small(dE, tt);
-                M += team_sum_small(dM, tt);
             }
             if (tl == 0 && active) {
                 sE += E;
@@ -361,7 +415,8 @@ __global__ void __launch_bounds__(1024) k_batch_sweep_bit(unsigned char* ws, int
             mo[6] = (int64_t)m4lo;
             mo[7] = (int64_t)m4hi;
         }
-        __syncthreads();
+        r = s_next;
+        __syncthreads();  // s_team and the planes are rewritten by the next pass
     }
     // draw counters: one atomic per workgroup
     long long v = wave_sum_i64((long long)nblk);
@@ -381,18 +436,17 @@ __global__ void __launch_bounds__(1024) k_batch_sweep_bit(unsigned char* ws, int
 }  // namespace
 
 size_t batch_bit_lds_bytes(int threads, int max_L) {
-    // a bundle: at most threads / tt teams of 2 nwc words, tt = min(nwc, threads)
-    const size_t big = (size_t)max_L * max_L / 64 * 2 * 4;
-    const size_t small = (size_t)threads * 2 * 4;
-    return big > small ? big : small;
+    // the least a workgroup needs: both planes of one lattice of side max_L
+    (void)threads;
+    return (size_t)max_L * max_L / 64 * 2 * 4;
 }
 
 hipError_t launch_batch_sweep_bit(unsigned char* ws, bool scratch_t, int count, int8_t* spins,
-                                  int max_L, int64_t n, Key key, int64_t* moments, int64_t* trace,
-                                  int threads, int blocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_sweep_bit, dim3(blocks), dim3(threads),
-                       batch_bit_lds_bytes(threads, max_L), st, ws, scratch_t ? 1 : 0, count,
-                       spins, n, key, moments, trace);
+                                  int64_t n, Key key, int64_t* moments, int64_t* trace,
+                                  int threads, int blocks, size_t lds_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_sweep_bit, dim3(blocks), dim3(threads), lds_bytes, st, ws,
+                       scratch_t ? 1 : 0, count, spins, n, key, moments, trace,
+                       (int)(lds_bytes / 4));
     return hipGetLastError();
 }
 

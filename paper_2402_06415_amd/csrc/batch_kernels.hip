@@ -238,8 +238,6 @@ __global__ void k_batch_prepare(unsigned char* ws, int scratch_t, int count, uin
                 hd->t = 0;
         }
     }
-    if (mode == kPrepareSweep && threadIdx.x < kBatchMaxClasses)
-        reinterpret_cast<BatchClass*>(ws + BatchWs::kClasses)[threadIdx.x].next = 0;
     if (mode == kPrepareInit && bad == 0) {
         unsigned long long* slots = reinterpret_cast<unsigned long long*>(ws + BatchWs::kRngBlocks);
         for (int i = threadIdx.x; i < 64; i += blockDim.x)
