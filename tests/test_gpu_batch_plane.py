@@ -170,6 +170,32 @@ def test_autotune_keeps_the_chain():
     assert tuned.rng_blocks() == plain.rng_blocks()
 
 
+def test_several_passes_per_workgroup():
+    """20,000 lattices of side 32 on 64-thread workgroups, one per CU: each
+    workgroup holds about 78 lattices, more than the 64 teams of one pass,
+    so it sweeps them in two passes of one lane per lattice.  Lattices from
+    both passes and from both ends of the snake are checked bit for bit."""
+    say("plane batch, two passes per workgroup")
+    cnt, n, seed = 20_000, 5, 29
+    Ls = [32] * cnt
+    betas = [0.30 + 0.30 * (k % 64) / 63 for k in range(cnt)]
+    b = lib.Batch(Ls, betas, seed=seed, start="random", threads=64, groups_per_cu=1,
+                  draws="plane")
+    mom = b.sweep(n)
+    G = min(cnt, torch.cuda.get_device_properties(0).multi_processor_count)
+    # first and second pass of workgroup 0 and of the last workgroup
+    js = sorted({0, 2 * G - 1, 64 * G, 64 * G + 2 * G - 1 if 64 * G + 2 * G - 1 < cnt else cnt - 1,
+                 G - 1, G, cnt - 1, cnt // 2})
+    want, states = [], []
+    for j in js:
+        s = oracle.init(32, oracle.START_RANDOM, seed, j)
+        want.append(oracle.batch_sweep([s], [betas[j]], seed, j, 0, n, nthreads=4, mode=PLANE)[0])
+        states.append(s)
+    _check_moments(mom, want, js)
+    _check_spins(b, states, js)
+    b.check()
+
+
 def test_draw_mode_must_match_setup():
     """A sweep whose draw mode differs from setup's is a device error and
     touches no lattice."""
