@@ -369,20 +369,27 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
         const uint32_t gD = ((((z << lgL) | ((y + 1) & Lm)) << lgnw) | w);
         const uint32_t gB = ((((((z - 1) & Lm) << lgL) | y) << lgnw) | w);
         const uint32_t gF = ((((((z + 1) & Lm) << lgL) | y) << lgnw) | w);
+        // every load of the word first, so that they are in flight together
+        // (the bit operations below are inline assembly, which the compiler
+        // does not move loads across)
         const uint32_t W = Pc[g], O = Po[g];
+        const uint32_t X = Po[p ? wp : wm];
+        const uint32_t jc = J0c[g], jo = J0o[g], jom = J0o[wm];
+        const uint32_t sU = Po[gU], jU = J1o[gU];  // y - 1: J_y at (x, y - 1, z)
+        const uint32_t sD = Po[gD], jD = J1c[g];   // y + 1: J_y at n
+        const uint32_t sB = Po[gB], jB = J2o[gB];  // z - 1: J_z at (x, y, z - 1)
+        const uint32_t sF = Po[gF], jF = J2c[g];   // z + 1: J_z at n
         // p = 0: O is the right neighbour (x + 1), the side word the left one;
         // p = 1: O is the left neighbour, the side word the right one.
-        const uint32_t X = Po[p ? wp : wm];
         const uint32_t S = p ? __builtin_amdgcn_alignbit(X, O, 1) : __builtin_amdgcn_alignbit(O, X, 31);
-        const uint32_t jc = J0c[g], jo = J0o[g];
         const uint32_t bO = p ? jo : jc;  // J_x at the left site (p = 1) or at n (p = 0)
-        const uint32_t bS = p ? jc : __builtin_amdgcn_alignbit(jo, J0o[wm], 31);
+        const uint32_t bS = p ? jc : __builtin_amdgcn_alignbit(jo, jom, 31);
         const uint32_t u0 = bop3<T_X3>(W, O, bO);
         const uint32_t u1 = bop3<T_X3>(W, S, bS);
-        const uint32_t u2 = bop3<T_X3>(W, Po[gU], J1o[gU]);  // y - 1: J_y at (x, y - 1, z)
-        const uint32_t u3 = bop3<T_X3>(W, Po[gD], J1c[g]);   // y + 1: J_y at n
-        const uint32_t u4 = bop3<T_X3>(W, Po[gB], J2o[gB]);  // z - 1: J_z at (x, y, z - 1)
-        const uint32_t u5 = bop3<T_X3>(W, Po[gF], J2c[g]);   // z + 1: J_z at n
+        const uint32_t u2 = bop3<T_X3>(W, sU, jU);
+        const uint32_t u3 = bop3<T_X3>(W, sD, jD);
+        const uint32_t u4 = bop3<T_X3>(W, sB, jB);
+        const uint32_t u5 = bop3<T_X3>(W, sF, jF);
         // n_u = b0 + 2 b1 + 4 b2, bit-sliced
         const uint32_t s1 = bop3<T_X3>(u0, u1, u2), c1 = bop3<T_MAJ3>(u0, u1, u2);
         const uint32_t s2 = bop3<T_X3>(u3, u4, u5), c2 = bop3<T_MAJ3>(u3, u4, u5);
