@@ -22,6 +22,12 @@
  *     p      = ((out[2] << 32 | out[3]) >> 11) 2^-53,
  * the neighbours summed in the order right, left, down, up, every
  * floating-point operation rounded separately (no fused multiply-add).
+ * For L <= 82 the sweep keeps cos and sin of every angle in LDS as well and
+ * forms the sum by the angle-difference identity (sum_delta cos(theta' -
+ * theta_delta) = cos theta' sum cos theta_delta + sin theta' sum sin
+ * theta_delta), with one sincos per trial; it equals the direct sum up to
+ * rounding, so a decision can differ from the direct form's only when p lies
+ * within a few units in the last place of P.
  * Random start: theta_n from out[0], out[1] of counter (n, id, 0, 9).
  * The sweep index t lives in device memory and advances on the device.
  */
