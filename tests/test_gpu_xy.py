@@ -88,6 +88,24 @@ def test_xy_cos_sin_cache_boundary(L):
     _compare(L, 2, BETA_XY, 13, (4, 3), lid0=1)
 
 
+@pytest.mark.parametrize("L", [32, 96])
+def test_xy_trace_does_not_change_the_chain(L):
+    """Sweeping without an energy trace skips all energy work; the angles
+    must equal the traced run's bit for bit, and the trace's last entry the
+    recount (cached form at L = 32, direct form at L = 96)."""
+    say(f"xy no trace L={L}")
+    a = lib.XYLattices(L, 3, seed=17, start="random")
+    b = lib.XYLattices(L, 3, seed=17, start="random")
+    E = _host(a.sweep(BETA_XY, 7))
+    assert b.sweep(BETA_XY, 7, trace=False) is None
+    assert (_host(a.theta) == _host(b.theta)).all()
+    assert np.allclose(E[-1], _host(b.energy()), rtol=0, atol=1e-12 * 2 * L * L)
+    (ta, acc_a), (tb, acc_b) = a.state(), b.state()
+    assert ta == tb == 7 and (acc_a == acc_b).all()
+    a.check()
+    b.check()
+
+
 def test_xy_papers_largest_size():
     """L = 128 (the paper's largest), ten seeds as in its energy study."""
     _compare(128, 10, BETA_XY, 21, (10,))
