@@ -46,13 +46,14 @@ def parse():
                     help="time the one-launch-per-half-sweep kernel instead (same chain)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--workload", choices=("single", "batched", "learned", "ea", "xy"),
+    ap.add_argument("--workload", choices=("single", "batched", "learned", "ea", "xy", "scaling"),
                     default="single",
                     help="single: one L=4096 bit-packed lattice (default); batched: 1024 INT8 "
                          "lattices of sides 32..256 on a 64-point beta grid in one launch; "
                          "learned: independent samples/s of learned-proposal vs plain chains "
                          "at L=32; ea: 3D +-J spin glass L=128, 64 replicas, replica exchange; "
-                         "xy: the paper's XY model at T=0.85, L=8..128, ten seeds")
+                         "xy: the paper's XY model at T=0.85, L=8..128, ten seeds; "
+                         "scaling: time per sweep against L for both layouts")
     ap.add_argument("--beta", type=float, default=BETA, help="learned: inverse temperature")
     ap.add_argument("--epochs", type=int, default=3, help="learned: training epochs")
     ap.add_argument("--no-autotune", action="store_true",
@@ -125,6 +126,14 @@ def cpu_baseline(L: int, seed: int, target_s: float):
     t0 = time.perf_counter()
     oracle.sweep(s, oracle.MODE_PLANE, seed, 0, 1, n, BETA, record=False, nthreads=threads)
     dt = time.perf_counter() - t0
+    # the same oracle on one core, on the sweeps that follow
+    t0 = time.perf_counter()
+    oracle.sweep(s, oracle.MODE_PLANE, seed, 0, 1 + n, 1, BETA, record=False, nthreads=1)
+    one1 = time.perf_counter() - t0
+    n1 = max(1, min(20, int(target_s / 3 / max(one1, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.sweep(s, oracle.MODE_PLANE, seed, 0, 2 + n, n1, BETA, record=False, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {
         "value": L * L * n / (dt * 1e9),
         "unit": "spin-flip attempts/ns",
@@ -132,7 +141,24 @@ def cpu_baseline(L: int, seed: int, target_s: float):
         "kind": "oracle",
         "sample": f"L={L} bit-plane draws, random start seed {seed}, sweeps 1..{n} "
                   f"({dt:.1f} s), OpenMP over rows of one colour",
+        "single_core": {"value": L * L * n1 / (dt1 * 1e9), "cores": 1,
+                        "sample": f"sweeps {n + 2}..{n + 1 + n1} of the same chain ({dt1:.1f} s)"},
+        "host": host_cpu(),
     }
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
 def cpu_baseline_batched(L, beta, seed: int, target_s: float, draws: str = "plane"):
@@ -615,6 +641,60 @@ def bench_xy(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_scaling(args):
+    """Time per sweep against the number of sites N = L^2 for both layouts,
+    the paper's scaling study (L = 8..128) extended to large sides: t = aN + b
+    fitted by least squares on relative residuals, and b/a, the lattice size
+    at which the fixed cost of a sweep equals its cost per site."""
+    import numpy as np
+    import torch
+
+    import paper_2402_06415_amd as lib
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    out = {}
+    for layout, sides in (("int8", [8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]),
+                          ("bit1", [64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384])):
+        rows = []
+        for L in sides:
+            n = int(min(10000, max(200, (1 << 30) // (L * L))))
+            lat = lib.Lattice(L, layout, seed=args.seed, start="random", device=dev)
+            lat.sweep(BETA, min(n, 50), record=False)
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            lat.sweep(BETA, n, record=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / n
+            lat.check()
+            rows.append({"L": L, "sweeps": n, "us_per_sweep": round(us, 4),
+                         "attempts_per_ns": round(L * L / (us * 1e3), 2)})
+            print(f"[scaling] {layout} L={L}: {us:.3f} us per sweep", file=sys.stderr, flush=True)
+            del lat
+        N = np.array([r["L"] ** 2 for r in rows], float)
+        t = np.array([r["us_per_sweep"] for r in rows])
+        a, b = np.polyfit(N, t, 1, w=1.0 / t)
+        out[layout] = {"sides": rows, "a_ns_per_site": round(a * 1e3, 6), "b_us": round(b, 3),
+                       "b_over_a_sites": round(b / a, 1)}
+    rec = {
+        "metric": "time per sweep against lattice size, t = aN + b",
+        "value": out["bit1"]["a_ns_per_site"],
+        "unit": "ns per site (bit-packed)",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8 / u32", "data": "synthetic",
+        "config": {"workload": "one 2D Ising lattice per side, random start seed "
+                               f"{args.seed}, beta=0.4406868, int8 L=8..4096 and bit-packed "
+                               "L=64..16384, sweeps in one call, no observables",
+                   "parallelism": "single GPU"},
+        "layouts": out,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -629,6 +709,8 @@ def main():
         return bench_ea(args)
     if args.workload == "xy":
         return bench_xy(args)
+    if args.workload == "scaling":
+        return bench_scaling(args)
     import torch
 
     import paper_2402_06415_amd as lib
