@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=1000)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--layout", choices=("bit1", "int8"), default="bit1",
+                    help="single: one bit per spin (default) or one byte per spin")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--global-halfsweep", action="store_true",
@@ -112,35 +114,57 @@ def tile_plan_fits(L: int, cus: int) -> bool:
                for t in range(min(cus * tpc, 1024, L), 1, -1))
 
 
-def cpu_baseline(L: int, seed: int, target_s: float):
-    """The oracle (unchanged, plane draws, OpenMP over rows) on a bounded
-    sample: the first sweeps of the same lattice from the same start."""
+def measured_copy_gbs(torch, dev, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Read + write bandwidth of a plain device-to-device copy of 1 GiB on
+    this GPU (best of a few), the practical ceiling beside the 8 TB/s peak."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
+def cpu_baseline(L: int, seed: int, target_s: float, layout: str = "bit1"):
+    """The oracle (unchanged; plane draws for the bit-packed layout, site
+    draws for int8; OpenMP over rows) on a bounded sample: the first sweeps
+    of the same lattice from the same start."""
     import oracle
+
+    mode = oracle.MODE_PLANE if layout == "bit1" else oracle.MODE_SITE
 
     threads = max(1, min(16, os.cpu_count() or 1))
     s = oracle.init(L, oracle.START_RANDOM, seed)
     t0 = time.perf_counter()
-    oracle.sweep(s, oracle.MODE_PLANE, seed, 0, 0, 1, BETA, record=False, nthreads=threads)
+    oracle.sweep(s, mode, seed, 0, 0, 1, BETA, record=False, nthreads=threads)
     one = time.perf_counter() - t0
     n = max(1, min(200, int(target_s / max(one, 1e-6))))
     t0 = time.perf_counter()
-    oracle.sweep(s, oracle.MODE_PLANE, seed, 0, 1, n, BETA, record=False, nthreads=threads)
+    oracle.sweep(s, mode, seed, 0, 1, n, BETA, record=False, nthreads=threads)
     dt = time.perf_counter() - t0
     # the same oracle on one core, on the sweeps that follow
     t0 = time.perf_counter()
-    oracle.sweep(s, oracle.MODE_PLANE, seed, 0, 1 + n, 1, BETA, record=False, nthreads=1)
+    oracle.sweep(s, mode, seed, 0, 1 + n, 1, BETA, record=False, nthreads=1)
     one1 = time.perf_counter() - t0
     n1 = max(1, min(20, int(target_s / 3 / max(one1, 1e-6))))
     t0 = time.perf_counter()
-    oracle.sweep(s, oracle.MODE_PLANE, seed, 0, 2 + n, n1, BETA, record=False, nthreads=1)
+    oracle.sweep(s, mode, seed, 0, 2 + n, n1, BETA, record=False, nthreads=1)
     dt1 = time.perf_counter() - t0
     return {
         "value": L * L * n / (dt * 1e9),
         "unit": "spin-flip attempts/ns",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"L={L} bit-plane draws, random start seed {seed}, sweeps 1..{n} "
-                  f"({dt:.1f} s), OpenMP over rows of one colour",
+        "sample": f"L={L} {'bit-plane' if layout == 'bit1' else 'per-site'} draws, random "
+                  f"start seed {seed}, sweeps 1..{n} ({dt:.1f} s), OpenMP over rows of one colour",
         "single_core": {"value": L * L * n1 / (dt1 * 1e9), "cores": 1,
                         "sample": f"sweeps {n + 2}..{n + 1 + n1} of the same chain ({dt1:.1f} s)"},
         "host": host_cpu(),
@@ -720,7 +744,8 @@ def main():
     torch.cuda.set_device(dev)
     L, nsw = args.L, args.sweeps
     flags = lib.FLAG_GLOBAL_HALFSWEEP if args.global_halfsweep else 0
-    lat = lib.Lattice(L, "bit1", seed=args.seed, start="random", device=dev, flags=flags)
+    layout = args.layout
+    lat = lib.Lattice(L, layout, seed=args.seed, start="random", device=dev, flags=flags)
     stream = torch.cuda.current_stream()
     out = torch.zeros(2, dtype=torch.int64, device=dev)
 
@@ -761,15 +786,24 @@ def main():
     # roofline of the sweep kernel: integer VALU work of the Philox draws the
     # method consumed, against the chip's VALU lane-op peak
     achieved_tops = blocks * PHILOX_OPS_PER_BLOCK / (sweep_ms * 1e-3) / 1e12
-    # effective HBM roofline: 2 bits per attempt (read + write once per sweep)
-    alg_bytes = attempts * 0.25
+    # effective HBM roofline: every spin read and written once per sweep,
+    # 2 bits per attempt bit-packed, 2 bytes as int8
+    per_attempt = 0.25 if layout == "bit1" else 2.0
+    alg_bytes = attempts * per_attempt
     eff_gbs = alg_bytes / (sweep_ms * 1e-3) / 1e9
-    # the library's tile plan keeps the lattice in LDS while its tiles fit
-    # (L <= 16384 on 256 CUs); larger lattices run one launch per half-sweep
-    # from global memory
-    tiles = not args.global_halfsweep and tile_plan_fits(L, torch.cuda.get_device_properties(0).multi_processor_count)
-    kernel_name = "k_sweep_bit1_tiles" if tiles else "k_halfsweep_bit1"
-    prof = profiled_traffic(kernel_name) if (L == 4096 and nsw == 1000) else None
+    if layout == "bit1":
+        # the library's tile plan keeps the lattice in LDS while its tiles fit
+        # (L <= 16384 on 256 CUs); larger lattices run one launch per
+        # half-sweep from global memory
+        tiles = not args.global_halfsweep and tile_plan_fits(
+            L, torch.cuda.get_device_properties(0).multi_processor_count)
+        kernel_name = "k_sweep_bit1_tiles" if tiles else "k_halfsweep_bit1"
+    else:
+        # int8: one resident workgroup up to L = 128, else a launch per half-sweep
+        tiles = not args.global_halfsweep and L <= 128
+        kernel_name = "k_sweep_int8_resident" if tiles else "k_halfsweep_int8"
+    prof = profiled_traffic(kernel_name) if (layout == "bit1" and L == 4096 and nsw == 1000) else None
+    copy_gbs = measured_copy_gbs(torch, dev)
     traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None
     rec = {
         "metric": METRIC,
@@ -782,13 +816,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u32" if layout == "bit1" else "i8",
         "data": "synthetic",
         "config": {
-            "workload": f"2D Ising L={L} one bit per spin, random start seed {args.seed}, "
+            "workload": f"2D Ising L={L} " + ("one bit per spin" if layout == "bit1" else "int8")
+                        + f", random start seed {args.seed}, "
                         f"beta={BETA}, {nsw} checkerboard sweeps + init + recount per step",
             "L": L, "sweeps_per_step": nsw, "beta": BETA, "seed": args.seed,
-            "layout": "bit1", "parallelism": "single GPU",
+            "layout": layout, "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "alu",
@@ -806,8 +841,11 @@ def main():
         "hbm_roofline": {
             "achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(eff_gbs / HBM_PEAK_GBS, 4),
-            "note": "algorithmic 0.25 B/attempt" + ("; the lattice stays in LDS during a call"
-                                                     if tiles else "; lattice in HBM"),
+            "copy_measured": round(copy_gbs, 1),
+            "frac_of_copy": round(eff_gbs / copy_gbs, 4),
+            "note": f"algorithmic {per_attempt:g} B/attempt"
+                    + ("; the lattice stays in LDS during a call" if tiles else "; lattice in HBM")
+                    + "; copy_measured: a 1 GiB device copy on this GPU, read + write bytes",
         },
         "E_final": E, "M_final": M,
     }
@@ -818,7 +856,7 @@ def main():
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(L, args.seed, args.cpu_seconds)
+        rec["cpu_baseline"] = cpu_baseline(L, args.seed, args.cpu_seconds, layout)
     print(json.dumps(rec), flush=True)
 
 
