@@ -99,29 +99,44 @@ __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L,
                                                         Accept acc, long long* dEo,
                                                         long long* dMo,
                                                         unsigned long long* nblk_out) {
+    // a grid-stride loop over the words of colour c, so that the Philox
+    // round keys and threshold masks are set up once per thread; L <= 65536
+    // keeps every word index within 32 bits
     const int nw = L >> 6;
-    const int64_t plane = (int64_t)L * nw;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t plane = (uint32_t)L * (uint32_t)nw;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     int dE = 0, dM = 0;
     unsigned long long nblk = 0;
-    if (idx < plane) {
-        const int y = (int)(idx / nw), w = (int)(idx % nw);
-        uint32_t* P = planes + (int64_t)c * plane;
-        const uint32_t* Q = planes + (int64_t)(1 - c) * plane;
-        const int64_t row = (int64_t)y * nw;
-        const int wm = (w == 0) ? nw - 1 : w - 1;
-        const int wp = (w + 1 == nw) ? 0 : w + 1;
-        const int ym = (y == 0) ? L - 1 : y - 1;
-        const int yp = (y + 1 == L) ? 0 : y + 1;
-        const uint32_t W = P[row + w];
-        const uint32_t O = Q[row + w];
-        const int p = (y + c) & 1;
-        const uint32_t S = side_word(O, Q[row + wm], Q[row + wp], p);
-        const uint32_t U = Q[(int64_t)ym * nw + w];
-        const uint32_t D = Q[(int64_t)yp * nw + w];
+    if (i < plane) {
         const DrawConsts dc = draw_consts(key, acc);
-        P[row + w] = update_word<true>(W, O, S, U, D, (uint32_t)(row + w), h, lid, acc, dc, dE, dM,
-                                       nblk);
+        uint32_t* P = planes + (size_t)c * plane;
+        const uint32_t* Q = planes + (size_t)(1 - c) * plane;
+        int y = (int)(i / (uint32_t)nw), w = (int)(i - (uint32_t)y * (uint32_t)nw);
+        const int sy = (int)(stride / (uint32_t)nw), sx = (int)(stride - (uint32_t)sy * (uint32_t)nw);
+        for (; i < plane; i += stride) {
+            const uint32_t row = (uint32_t)y * (uint32_t)nw;
+            const int wm = (w == 0) ? nw - 1 : w - 1;
+            const int wp = (w + 1 == nw) ? 0 : w + 1;
+            const int ym = (y == 0) ? L - 1 : y - 1;
+            const int yp = (y + 1 == L) ? 0 : y + 1;
+            // the five loads of the word together, one round trip to memory
+            const int p = (y + c) & 1;  // 0: the side word is the left one
+            const uint32_t W = P[row + w];
+            const uint32_t O = Q[row + w];
+            const uint32_t X = Q[row + (p == 0 ? wm : wp)];
+            const uint32_t U = Q[(uint32_t)ym * (uint32_t)nw + w];
+            const uint32_t D = Q[(uint32_t)yp * (uint32_t)nw + w];
+            const uint32_t S = side_word(O, X, X, p);
+            P[row + w] = update_word<true>(W, O, S, U, D, row + (uint32_t)w, h, lid, acc, dc, dE,
+                                           dM, nblk);
+            w += sx;
+            y += sy;
+            if (w >= nw) {
+                w -= nw;
+                ++y;
+            }
+        }
     }
     add_count(nblk, nblk_out);
     if (dEo || dMo)
@@ -448,9 +463,13 @@ hipError_t launch_init_bit1(uint32_t* planes, int L, int start, Key key, uint32_
 hipError_t launch_halfsweep_bit1(uint32_t* planes, int L, int c, uint32_t h, Key key,
                                  uint32_t lid, Accept acc, long long* dE, long long* dM,
                                  unsigned long long* nblk, hipStream_t st) {
+    // at most 4096 workgroups: a thread takes up to 64 words at L = 65536
     int64_t words = (int64_t)L * (L >> 6);
-    hipLaunchKernelGGL(k_halfsweep_bit1, dim3(blocks_for(words, 256)), dim3(256), 0, st, planes, L,
-                       c, h, key, lid, acc, dE, dM, nblk);
+    unsigned blocks = blocks_for(words, 256);
+    if (blocks > 4096)
+        blocks = 4096;
+    hipLaunchKernelGGL(k_halfsweep_bit1, dim3(blocks), dim3(256), 0, st, planes, L, c, h, key, lid,
+                       acc, dE, dM, nblk);
     return hipGetLastError();
 }
 

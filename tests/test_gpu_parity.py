@@ -129,6 +129,13 @@ def test_bit1_global_halfsweep_kernel(L):
     _compare_stepwise(L, "bit1", 9, "random", BC, 8, flags=lib.FLAG_GLOBAL_HALFSWEEP, chunk=3)
 
 
+def test_bit1_global_kernel_several_words_per_thread():
+    """L = 24576 does not fit the tile plan (the whole lattice must sit in
+    LDS), so it runs one launch per half-sweep from global memory, where a
+    thread takes nine words in a grid-stride loop."""
+    _compare_stepwise(24576, "bit1", 5, "random", BC, 2, chunk=2)
+
+
 @pytest.mark.parametrize("beta", [0.0, 1e-12, 0.3, 0.6, 3.0])
 @pytest.mark.parametrize("layout,L", [("int8", 12), ("bit1", 128)])
 def test_beta_edge_cases(layout, L, beta):
