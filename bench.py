@@ -70,7 +70,7 @@ def parse():
 # Sources whose text determines each profiled sweep kernel's code.
 KERNEL_SOURCES = {
     "bit1_kernels.hip": ("bit1_kernels.hip", "common.hpp", "kernels.hpp", "bitslice.hpp"),
-    "batch_kernels.hip": ("batch_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp"),
+    "batch_kernels.hip": ("batch_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp", "quad.hpp"),
     "ea_kernels.hip": ("ea_kernels.hip", "common.hpp", "kernels.hpp", "ea.hpp", "bitslice.hpp"),
     "batch_bit_kernels.hip": ("batch_bit_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp",
                               "bitslice.hpp"),
@@ -801,7 +801,9 @@ def main():
     else:
         # int8: one resident workgroup up to L = 128, else a launch per half-sweep
         tiles = not args.global_halfsweep and L <= 128
-        kernel_name = "k_sweep_int8_resident" if tiles else "k_halfsweep_int8"
+        span = L % 8 == 0 and L * L < (1 << 31)  # the byte-parallel span kernel
+        kernel_name = ("k_sweep_int8_resident" if tiles else
+                       "k_halfsweep_int8_quad" if span else "k_halfsweep_int8")
     prof = profiled_traffic(kernel_name) if (layout == "bit1" and L == 4096 and nsw == 1000) else None
     copy_gbs = measured_copy_gbs(torch, dev)
     traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None

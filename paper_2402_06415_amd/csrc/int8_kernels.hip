@@ -6,6 +6,7 @@
 // four consecutive compact indices q = 4g..4g+3 of the colour, which share
 // one Philox4x32-10 block (counter (g, lattice_id, 2t+c, 0)).
 #include "kernels.hpp"
+#include "quad.hpp"
 
 namespace ising {
 
@@ -217,6 +218,47 @@ __device__ __forceinline__ void block_add_i64(long long a, long long b, long lon
     }
 }
 
+// Half-sweep of colour c from global memory for L % 8 == 0 and L^2 < 2^31:
+// the byte-parallel update of the four colour-c sites of an 8-byte span
+// (quad.hpp), in a grid-stride loop over the spans so that the Philox round
+// keys are set up once per thread.  Span gi = y L/8 + k (columns 8k..8k+7 of
+// row y) is Philox group gi; its row and column advance incrementally.
+__global__ void __launch_bounds__(256) k_halfsweep_int8_quad(int8_t* s, int L, int c, uint32_t h,
+                                                             Key key, uint32_t lid, Accept acc,
+                                                             long long* dEo, long long* dMo,
+                                                             unsigned long long* nblk_out) {
+    const int gpr = L >> 3, N = L * L;
+    const uint32_t ngroups = (uint32_t)L * (uint32_t)gpr;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t gi = blockIdx.x * blockDim.x + threadIdx.x;
+    QuadCounts cnt;
+    unsigned long long nblk = 0;
+    if (gi < ngroups) {
+        const RoundKeys rk = round_keys(key);
+        const QuadAccept qa = quad_accept(acc.T2, acc.T4, acc.always2 != 0, acc.always4 != 0);
+        int y = (int)(gi / (uint32_t)gpr), k = (int)(gi - (uint32_t)y * (uint32_t)gpr);
+        const int dy = (int)(stride / (uint32_t)gpr), dk = (int)(stride - (uint32_t)dy * (uint32_t)gpr);
+        int row = y * L;
+        for (; gi < ngroups; gi += stride) {
+            update_quad(s, L, N, y, row, 8 * k, c, gi, h, rk, lid, qa, cnt, nblk);
+            k += dk;
+            y += dy;
+            row += dy * L;
+            if (k >= gpr) {
+                k -= gpr;
+                ++y;
+                row += L;
+            }
+        }
+    }
+    add_count(nblk, nblk_out);
+    if (dEo || dMo) {
+        const long long dE = 8ll * cnt.nflip - 2ll * cnt.sum_a2;
+        const long long dM = 2ll * (2ll * cnt.ndown - (long long)cnt.nflip);
+        block_add_i64(dE, dM, dEo, dMo);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_halfsweep_int8(int8_t* s, int L, int c, uint32_t h,
                                                         Key key, uint32_t lid, Accept acc,
                                                         long long* dEo, long long* dMo,
@@ -339,6 +381,16 @@ hipError_t launch_halfsweep_int8(int8_t* s, int L, int c, uint32_t h, Key key, u
                                  Accept acc, long long* dE, long long* dM,
                                  unsigned long long* nblk, hipStream_t st) {
     int64_t groups = ((((int64_t)L * L) >> 1) + 3) >> 2;
+    if ((L & 7) == 0 && (int64_t)L * L < (int64_t)1 << 31) {
+        // one 8-byte span per group; at most 4096 workgroups (a thread takes
+        // up to 128 spans at L = 32768)
+        unsigned blocks = blocks_for(groups, 256);
+        if (blocks > 4096)
+            blocks = 4096;
+        hipLaunchKernelGGL(k_halfsweep_int8_quad, dim3(blocks), dim3(256), 0, st, s, L, c, h, key,
+                           lid, acc, dE, dM, nblk);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_halfsweep_int8, dim3(blocks_for(groups, 256)), dim3(256), 0, st, s, L, c,
                        h, key, lid, acc, dE, dM, nblk);
     return hipGetLastError();

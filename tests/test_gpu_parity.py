@@ -111,8 +111,10 @@ def test_int8_resident_kernel(L):
     _compare_stepwise(L, "int8", 3, "random", BC, 40, chunk=7)
 
 
-@pytest.mark.parametrize("L", [4, 6, 16, 130, 256])
+@pytest.mark.parametrize("L", [4, 6, 16, 130, 256, 1024, 2056])
 def test_int8_global_halfsweep_kernel(L):
+    # L % 8 == 0 takes the span kernel (L = 2056: 257 spans per row), others
+    # the per-site one
     _compare_stepwise(L, "int8", 5, "random", BC, 12, flags=lib.FLAG_GLOBAL_HALFSWEEP, chunk=5)
 
 
