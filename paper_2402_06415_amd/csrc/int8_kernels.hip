@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(1024) k_sweep_int8_resident(int8_t* s_glob, in
                                                               Accept acc, int64_t* Etr,
                                                               int64_t* Mtr,
                                                               unsigned long long* nblk_out) {
-    extern __shared__ int8_t sh[];
+    extern __shared__ __align__(16) int8_t sh[];  // 8-byte span loads
     __shared__ long long red[2][16];
     const int N = L * L;
     const int tid = threadIdx.x;
@@ -160,13 +160,37 @@ __global__ void __launch_bounds__(1024) k_sweep_int8_resident(int8_t* s_glob, in
     __syncthreads();
     const int64_t groups = ((N >> 1) + 3) >> 2;  // N/2 sites per colour, 4 per group
     const RoundKeys rk = round_keys(key);
+    // L % 8 == 0: the byte-parallel span update (quad.hpp); span gi = y L/8 + k
+    // is Philox group gi, and a thread's spans advance without divisions
+    const bool span = (L & 7) == 0;
+    const QuadAccept qa = quad_accept(acc.T2, acc.T4, acc.always2 != 0, acc.always4 != 0);
+    const int gpr = L >> 3;
+    const int y0 = span ? tid / gpr : 0, k0 = span ? tid - y0 * gpr : 0;
+    const int dy = span ? (int)blockDim.x / gpr : 0, dk = span ? (int)blockDim.x - dy * gpr : 0;
     unsigned long long nblk = 0;
     for (int64_t j = 0; j < n; ++j) {
         int dE = 0, dM = 0;
         for (int c = 0; c < 2; ++c) {
             uint32_t h = 2u * (t0 + (uint32_t)j) + (uint32_t)c;
-            for (int64_t g = tid; g < groups; g += blockDim.x)
-                update_group(sh, L, c, g, h, rk, lid, acc, dE, dM, nblk);
+            if (span) {
+                QuadCounts cnt;
+                int y = y0, k = k0;
+                for (int gi = tid; gi < (int)groups; gi += blockDim.x) {
+                    update_quad(sh, L, N, y, y * L, 8 * k, c, (uint32_t)gi, h, rk, lid, qa, cnt,
+                                nblk);
+                    k += dk;
+                    y += dy;
+                    if (k >= gpr) {
+                        k -= gpr;
+                        ++y;
+                    }
+                }
+                dE += 8 * (int)cnt.nflip - 2 * (int)cnt.sum_a2;
+                dM += 2 * (2 * (int)cnt.ndown - (int)cnt.nflip);
+            } else {
+                for (int64_t g = tid; g < groups; g += blockDim.x)
+                    update_group(sh, L, c, g, h, rk, lid, acc, dE, dM, nblk);
+            }
             __syncthreads();
         }
         dE = wave_sum_i32(dE);
