@@ -13,8 +13,11 @@
  * iff p < P.
  *
  * Several independent lattices (for example the paper's ten seeds) are
- * swept together, one workgroup per lattice with the angles in LDS for all
- * n sweeps of a call.  Lattice j draws with lattice id lattice_id0 + j:
+ * swept together: up to L = 82 one workgroup per lattice with the angles in
+ * LDS for all n sweeps of a call; above that one launch per half-sweep
+ * spread over many workgroups per lattice, the angles in global memory
+ * (2n launches per call, so a caller of many short calls may capture them
+ * in a HIP graph).  Lattice j draws with lattice id lattice_id0 + j:
  * the trial of the site with compact index q = n >> 1 in half-sweep 2t + c
  * uses out of Philox4x32-10 counter (q, id, 2t + c, 8), key (seed lo,
  * seed hi):
@@ -53,7 +56,8 @@ typedef struct ising_xy {
     void *workspace;      /* device, 256-B aligned, >= ising_xy_workspace_bytes */
 } ising_xy;
 
-/* Workspace: sweep index, accepted-rotation counters, error word. */
+/* Workspace: sweep index, accepted-rotation counters, error word, and the
+ * per-lattice energy sums of the large-lattice sweep. */
 ISING_API size_t ising_xy_workspace_bytes(int32_t count);
 
 /* Random (ISING_START_RANDOM) or aligned (theta = 0, ISING_START_COLD_UP)

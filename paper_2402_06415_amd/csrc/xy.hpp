@@ -9,6 +9,10 @@ constexpr uint32_t kXyMagic = 0x31595849u;   // "IXY1"
 constexpr uint32_t kXyErrNotInit = 1u;
 constexpr uint32_t kXyErrSweepIndex = 4u;
 constexpr size_t kXyAccepted = 256;          // uint64[count]: accepted rotations
+// double[2][count]: per-lattice energy sums of the global-memory sweep
+inline size_t xy_energy_sums_offset(int count) {
+    return kXyAccepted + (((size_t)count * 8 + 255) & ~(size_t)255);
+}
 size_t xy_workspace_bytes(int count);
 hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, int start, Key key,
                           uint32_t lid0, hipStream_t st);

@@ -6,6 +6,13 @@
 // neighbours (the other colour) from LDS and writes its own angle, so the
 // update is in place and race-free.
 //
+// Larger lattices (L > 82) are swept by one launch per half-sweep over many
+// workgroups instead (a lattice on one CU would leave the rest of the GPU
+// idle): the angles stay in global memory, each thread makes one trial, and
+// the energy trace is carried by per-lattice sums in the workspace that
+// alternate between two slots from sweep to sweep, so that each sweep's
+// total is read only after a kernel boundary.
+//
 // Where LDS also holds cos and sin of every angle (24 bytes per site, L <= 82)
 // the energy change of a trial is formed from them by the angle-difference
 // identity, cos(a - b) = cos a cos b + sin a sin b: one sincos of the
@@ -242,9 +249,119 @@ __global__ void k_xy_energy(const double* theta, int L, double* E_out) {
         E_out[blockIdx.x] = E;
 }
 
+// One half-sweep (colour c, sweep sw of the call) of every lattice from
+// global memory, one trial per thread: grid (trials / blockDim, count).
+// The trial is the one of k_xy_sweep's direct form.  Energy sums S (two
+// slots of count doubles): sweep sw adds into slot sw & 1; the colour-0
+// launch of sweep sw >= 1 first carries the previous slot's total in (and
+// writes it to the trace), and the colour-1 launch clears the other slot for
+// the next sweep.
+__global__ void __launch_bounds__(256) k_xy_halfsweep_g(unsigned char* ws, double* theta, int L,
+                                                        int count, int c, int64_t sw, int64_t n,
+                                                        double beta, Key key, uint32_t lid0,
+                                                        double* S, double* E_trace) {
+#pragma clang fp contract(off)
+    __shared__ double red[4];
+    __shared__ unsigned long long racc[4];
+    XyHeader* hd = xy_header(ws);
+    if (hd->ok == 0)
+        return;
+    const int j = blockIdx.y;
+    const uint32_t lid = lid0 + (uint32_t)j;
+    const int N = L * L, half = L >> 1;
+    const uint32_t h = 2u * ((uint32_t)hd->t0 + (uint32_t)sw) + (uint32_t)c;
+    double* th = theta + (int64_t)j * N;
+    double* cur = S + (size_t)(sw & 1) * count;
+    double* other = S + (size_t)((sw + 1) & 1) * count;
+    if (E_trace && blockIdx.x == 0 && threadIdx.x == 0) {
+        if (c == 0 && sw > 0) {
+            E_trace[(sw - 1) * count + j] = other[j];
+            atomicAdd(cur + j, other[j]);
+        }
+        if (c == 1)
+            other[j] = 0.0;  // read by this sweep's colour-0 launch, free now
+    }
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    double dE_acc = 0.0;
+    unsigned long long acc = 0;
+    if (q < (N >> 1)) {
+        const RoundKeys rk = round_keys(key);
+        const int y = q / half, x = 2 * (q - y * half) + ((y + c) & 1);
+        const int row = y * L;
+        const U4 o = philox4x32_10({(uint32_t)q, lid, h, kTagXy}, rk);
+        const double th_new = unit53(o.x, o.y) * kTwoPi;
+        const double p = unit53(o.z, o.w);
+        const int i = row + x;
+        const int nbi[4] = {row + (x + 1 == L ? 0 : x + 1), row + (x == 0 ? L - 1 : x - 1),
+                            (y + 1 == L ? 0 : y + 1) * L + x, (y == 0 ? L - 1 : y - 1) * L + x};
+        const double t = th[i];
+        const double nb[4] = {th[nbi[0]], th[nbi[1]], th[nbi[2]], th[nbi[3]]};
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            d += cos(th_new - nb[k]) - cos(t - nb[k]);
+        const double dE = -d;
+        const double P = exp(-beta * dE);
+        if (p < P) {
+            th[i] = th_new;
+            acc = 1;
+            dE_acc = dE;
+        }
+    }
+    // per-workgroup sums: one atomic each into the lattice's counters
+    const double w = wave_sum_f64(dE_acc);
+    unsigned long long a = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        a += __shfl_xor(a, off, 64);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = w;
+        racc[threadIdx.x >> 6] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        unsigned long long t = 0;
+        for (int v = 0; v < (int)(blockDim.x >> 6); ++v) {
+            e += red[v];
+            t += racc[v];
+        }
+        if (E_trace && e != 0.0)
+            atomicAdd(cur + j, e);
+        if (t)
+            atomicAdd(reinterpret_cast<unsigned long long*>(ws + kXyAccepted) + j, t);
+    }
+}
+
+// Energy sums before the first sweep of a call: slot 0 = H, slot 1 = 0.
+__global__ void k_xy_sums_start(unsigned char* ws, const double* theta, int L, int count,
+                                double* S) {
+    __shared__ double red[16];
+    if (xy_header(ws)->ok == 0)
+        return;
+    const double E = energy_to0(theta + (int64_t)blockIdx.x * L * L, L, red);
+    if (threadIdx.x == 0) {
+        S[blockIdx.x] = E;
+        S[count + blockIdx.x] = 0.0;
+    }
+}
+
+// The last sweep's energies into the trace.
+__global__ void k_xy_sums_finish(unsigned char* ws, int count, int64_t n, const double* S,
+                                 double* E_trace) {
+    if (xy_header(ws)->ok == 0)
+        return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < count)
+        E_trace[(n - 1) * count + j] = S[(size_t)((n - 1) & 1) * count + j];
+}
+
 }  // namespace
 
-size_t xy_workspace_bytes(int count) { return kXyAccepted + (((size_t)count * 8 + 255) & ~(size_t)255); }
+size_t xy_workspace_bytes(int count) {
+    // accepted counters, then the two slots of per-lattice energy sums
+    return xy_energy_sums_offset(count) + (((size_t)count * 16 + 255) & ~(size_t)255);
+}
 
 hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, int start, Key key,
                           uint32_t lid0, hipStream_t st) {
@@ -257,6 +374,25 @@ hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, in
 hipError_t launch_xy_sweep(unsigned char* ws, double* theta, int L, int count, int64_t n,
                            double beta, Key key, uint32_t lid0, double* E_trace, hipStream_t st) {
     hipLaunchKernelGGL(k_xy_prepare, dim3(1), dim3(1), 0, st, ws, count, n);
+    const size_t plane_bytes = (size_t)L * L * sizeof(double);
+    if (3 * plane_bytes > kXyCacheLds) {
+        // one launch per half-sweep over many workgroups
+        double* S = reinterpret_cast<double*>(ws + xy_energy_sums_offset(count));
+        const int trials = L * L / 2;
+        const dim3 grid((unsigned)((trials + 255) / 256), (unsigned)count);
+        if (E_trace)
+            hipLaunchKernelGGL(k_xy_sums_start, dim3(count), dim3(256), 0, st, ws, theta, L, count,
+                               S);
+        for (int64_t sw = 0; sw < n; ++sw)
+            for (int c = 0; c < 2; ++c)
+                hipLaunchKernelGGL(k_xy_halfsweep_g, grid, dim3(256), 0, st, ws, theta, L, count,
+                                   c, sw, n, beta, key, lid0, S, E_trace);
+        if (E_trace && n > 0)
+            hipLaunchKernelGGL(k_xy_sums_finish, dim3((count + 255) / 256), dim3(256), 0, st, ws,
+                               count, n, S, E_trace);
+        hipLaunchKernelGGL(k_xy_advance, dim3(1), dim3(1), 0, st, ws, n);
+        return hipGetLastError();
+    }
     // one trial per thread per half-sweep where the lattice allows (up to 512:
     // the double-precision trial needs more than the 128 registers a lane
     // has at 1024 threads)
