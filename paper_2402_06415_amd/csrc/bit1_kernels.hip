@@ -20,6 +20,11 @@ namespace ising {
 
 namespace {
 
+// Philox blocks drawn straight-line before the conditional tail: three for
+// the single lattice (block 2 is needed by some lane of nearly every wave at
+// the critical point; 3958 against 3759 attempts/ns at L = 4096).
+constexpr int kStraightBlocks = 3;
+
 __global__ void k_init_bit1(uint32_t* planes, int L, int start, Key key, uint32_t lid) {
     const int nw = L >> 6;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -109,7 +114,7 @@ __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L,
     int dE = 0, dM = 0;
     unsigned long long nblk = 0;
     if (i < plane) {
-        const DrawConsts dc = draw_consts(key, acc);
+        const DrawConstsT<kStraightBlocks> dc = draw_consts<kStraightBlocks>(key, acc);
         uint32_t* P = planes + (size_t)c * plane;
         const uint32_t* Q = planes + (size_t)(1 - c) * plane;
         int y = (int)(i / (uint32_t)nw), w = (int)(i - (uint32_t)y * (uint32_t)nw);
@@ -128,8 +133,8 @@ __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L,
             const uint32_t U = Q[(uint32_t)ym * (uint32_t)nw + w];
             const uint32_t D = Q[(uint32_t)yp * (uint32_t)nw + w];
             const uint32_t S = side_word(O, X, X, p);
-            P[row + w] = update_word<true>(W, O, S, U, D, row + (uint32_t)w, h, lid, acc, dc, dE,
-                                           dM, nblk);
+            P[row + w] = update_word<true, kStraightBlocks>(W, O, S, U, D, row + (uint32_t)w, h,
+                                                            lid, acc, dc, dE, dM, nblk);
             w += sx;
             y += sy;
             if (w >= nw) {
@@ -320,7 +325,8 @@ __device__ __forceinline__ void store_tile(uint32_t* planes, const uint32_t* til
 template <bool kObs, bool kLate>
 __device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, int rows, int r,
                                            int64_t hs, uint32_t t0, uint32_t lid,
-                                           const Accept& acc, const DrawConsts& dc,
+                                           const Accept& acc,
+                                           const DrawConstsT<kStraightBlocks>& dc,
                                            unsigned long long* halo, uint32_t* err,
                                            uint32_t spin_limit, int& dE, int& dM,
                                            unsigned long long& nblk) {
@@ -348,7 +354,8 @@ __device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, in
                                ? wait_slot(halo_row(halo, nw, t.down, o, 0) + w, tag_in, spin_limit, err)
                                : To[(r + 2) * nw + w];
         WordState st = classify(W, O, S, U, D, acc);
-        draw_planes(st, (uint32_t)((int64_t)y * nw + w), h, lid, acc, dc, nblk);
+        draw_planes<true, kStraightBlocks>(st, (uint32_t)((int64_t)y * nw + w), h, lid, acc, dc,
+                                           nblk);
         const uint32_t nwd = finalize<kObs>(st, dE, dM);
         Tc[(r + 1) * nw + w] = nwd;
         if (first)
@@ -388,7 +395,7 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
     const TileGeom t = tile_geom(L, rows);
     const int nwaves = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const DrawConsts dc = draw_consts(key, acc);
+    const DrawConstsT<kStraightBlocks> dc = draw_consts<kStraightBlocks>(key, acc);
     load_tile(tile, planes, L, rows, t);
     __syncthreads();
     long long sE = 0, sM = 0;

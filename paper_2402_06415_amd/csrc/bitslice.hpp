@@ -65,16 +65,22 @@ __device__ __forceinline__ WordState classify(uint32_t W, uint32_t O, uint32_t S
 // Per-thread constants of the comparison: the Philox round keys and, for
 // the first eight planes, the threshold bits as all-ones/all-zero masks
 // (t2m[k] for T2, t4m[k] for T4), both in vector registers.
-struct DrawConsts {
+// Per-thread constants of the draws: the Philox round keys and, for the
+// kBlocks blocks drawn unconditionally, the threshold bit of each of their
+// 4 kBlocks planes as a full mask.
+template <int kBlocks>
+struct DrawConstsT {
     RoundKeys rk;
-    uint32_t t2m[8], t4m[8];
+    uint32_t t2m[4 * kBlocks], t4m[4 * kBlocks];
 };
+using DrawConsts = DrawConstsT<2>;
 
-__device__ __forceinline__ DrawConsts draw_consts(Key key, const Accept& acc) {
-    DrawConsts dc;
+template <int kBlocks = 2>
+__device__ __forceinline__ DrawConstsT<kBlocks> draw_consts(Key key, const Accept& acc) {
+    DrawConstsT<kBlocks> dc;
     dc.rk = round_keys(key);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < 4 * kBlocks; ++k) {
         dc.t2m[k] = 0u - ((acc.T2 >> (31 - k)) & 1u);
         dc.t4m[k] = 0u - ((acc.T4 >> (31 - k)) & 1u);
         asm volatile("" : "+v"(dc.t2m[k]), "+v"(dc.t4m[k]));
@@ -105,17 +111,19 @@ __device__ __forceinline__ void compare_plane(WordState& st, uint32_t P, uint32_
 // Draw the Philox blocks of word group g and compare r < T plane by plane.
 // kUniformAccept: the thresholds are the same in every lane of the wave
 // (the tail's threshold bits then go in as scalar operands).
-// Blocks 0 and 1 (planes 0-7) are drawn unconditionally: some lane of a
-// wave needs them almost always.  Further blocks are drawn while the lane
-// still has undecided sites.  nblk counts the blocks the lane needed (those
-// drawn while it still had an undecided site).
-template <bool kUniformAccept = true>
+// The first kBlocks blocks (planes 0 .. 4 kBlocks - 1) are drawn
+// unconditionally, straight-line: some lane of a wave needs them almost
+// always (blocks 0 and 1; block 2 in about 98% of the waves at the critical
+// point).  Further blocks are drawn while the lane still has undecided
+// sites.  nblk counts the blocks the lane needed (those drawn while it still
+// had an undecided site).
+template <bool kUniformAccept = true, int kBlocks = 2>
 __device__ __forceinline__ void draw_planes(WordState& st, uint32_t g, uint32_t h, uint32_t lid,
-                                            const Accept& acc, const DrawConsts& dc,
+                                            const Accept& acc, const DrawConstsT<kBlocks>& dc,
                                             unsigned long long& nblk) {
     const uint32_t m2 = st.m2;
 #pragma unroll
-    for (uint32_t b = 0; b < 2; ++b) {
+    for (uint32_t b = 0; b < (uint32_t)kBlocks; ++b) {
         nblk += st.und ? 1u : 0u;
         const U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, dc.rk);
 #pragma unroll
@@ -124,7 +132,7 @@ __device__ __forceinline__ void draw_planes(WordState& st, uint32_t g, uint32_t 
             compare_plane(st, u4_get(out, kk), bop3<T_BITSEL>(m2, dc.t2m[k], dc.t4m[k]));
         }
     }
-    for (uint32_t b = 2; b < 8u && st.und; ++b) {
+    for (uint32_t b = kBlocks; b < 8u && st.und; ++b) {
         ++nblk;
         const U4 out = philox4x32_10({g, lid, h, kTagPlane | (b << 8)}, dc.rk);
 #pragma unroll
@@ -161,13 +169,13 @@ __device__ __forceinline__ uint32_t finalize(const WordState& st, int& dE, int& 
 }
 
 // Complete Metropolis update of one word (all 32 planes available).
-template <bool kObs>
+template <bool kObs, int kBlocks>
 __device__ __forceinline__ uint32_t update_word(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
                                                 uint32_t D, uint32_t g, uint32_t h, uint32_t lid,
-                                                const Accept& acc, const DrawConsts& dc, int& dE,
-                                                int& dM, unsigned long long& nblk) {
+                                                const Accept& acc, const DrawConstsT<kBlocks>& dc,
+                                                int& dE, int& dM, unsigned long long& nblk) {
     WordState st = classify(W, O, S, U, D, acc);
-    draw_planes(st, g, h, lid, acc, dc, nblk);
+    draw_planes<true, kBlocks>(st, g, h, lid, acc, dc, nblk);
     return finalize<kObs>(st, dE, dM);
 }
 
