@@ -343,11 +343,11 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
     const EaAccept a = reinterpret_cast<const EaAccept*>(ws + lay.thr)[
         reinterpret_cast<const int32_t*>(ws + lay.tidx)[r]];
     const bool al2 = a.M2 == 0, al4 = a.M4 == 0, al6 = a.M6 == 0;  // always flips
-    // per-thread constants: Philox round keys, threshold masks of planes 0-7
+    // per-thread constants: Philox round keys, threshold masks of planes 0-11
     const RoundKeys rk = round_keys(key);
-    uint32_t t2m[8], t4m[8], t6m[8];
+    uint32_t t2m[12], t4m[12], t6m[12];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < 12; ++k) {
         t2m[k] = 0u - ((a.T2 >> (31 - k)) & 1u);
         t4m[k] = 0u - ((a.T4 >> (31 - k)) & 1u);
         t6m[k] = 0u - ((a.T6 >> (31 - k)) & 1u);
@@ -404,9 +404,10 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
         st.W = W;
         st.flip = ge3 | (al2 ? is2 : 0u) | (al4 ? is1 : 0u) | (al6 ? is0 : 0u);
         st.und = (al2 ? 0u : is2) | (al4 ? 0u : is1) | (al6 ? 0u : is0);
-        // blocks 0 and 1 straight-line with the masks in registers
+        // blocks 0 to 2 straight-line with the masks in registers (some lane
+        // of nearly every wave needs block 2)
 #pragma unroll
-        for (uint32_t blk = 0; blk < 2; ++blk) {
+        for (uint32_t blk = 0; blk < 3; ++blk) {
             nblk += st.und ? 1u : 0u;
             const U4 out = philox4x32_10({g, r, h, kTagPlane | (blk << 8)}, rk);
 #pragma unroll
@@ -417,7 +418,7 @@ __global__ void __launch_bounds__(256) k_ea_halfsweep_bit(unsigned char* ws, con
             }
         }
         // further blocks while the lane has undecided sites
-        for (uint32_t blk = 2; blk < 8u && st.und; ++blk) {
+        for (uint32_t blk = 3; blk < 8u && st.und; ++blk) {
             ++nblk;
             const U4 out = philox4x32_10({g, r, h, kTagPlane | (blk << 8)}, rk);
 #pragma unroll
