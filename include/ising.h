@@ -59,7 +59,7 @@
 extern "C" {
 #endif
 
-#define ISING_ABI_VERSION 2
+#define ISING_ABI_VERSION 3
 
 #if defined(__GNUC__) || defined(__clang__)
 #define ISING_API __attribute__((visibility("default")))

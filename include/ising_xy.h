@@ -13,11 +13,11 @@
  * iff p < P.
  *
  * Several independent lattices (for example the paper's ten seeds) are
- * swept together: up to L = 82 one workgroup per lattice with the angles in
+ * swept together: up to L = 80 one workgroup per lattice with the angles in
  * LDS for all n sweeps of a call; above that one launch per half-sweep
- * spread over many workgroups per lattice, the angles in global memory
- * (2n launches per call, so a caller of many short calls may capture them
- * in a HIP graph).  Lattice j draws with lattice id lattice_id0 + j:
+ * spread over many workgroups per lattice, the angles in global memory and
+ * their cosines and sines in the workspace (2n + 1 launches per call, so a
+ * caller of many short calls may capture them in a HIP graph).  Lattice j draws with lattice id lattice_id0 + j:
  * the trial of the site with compact index q = n >> 1 in half-sweep 2t + c
  * uses out of Philox4x32-10 counter (q, id, 2t + c, 8), key (seed lo,
  * seed hi):
@@ -25,12 +25,12 @@
  *     p      = ((out[2] << 32 | out[3]) >> 11) 2^-53,
  * the neighbours summed in the order right, left, down, up, every
  * floating-point operation rounded separately (no fused multiply-add).
- * For L <= 82 the sweep keeps cos and sin of every angle in LDS as well and
- * forms the sum by the angle-difference identity (sum_delta cos(theta' -
- * theta_delta) = cos theta' sum cos theta_delta + sin theta' sum sin
- * theta_delta), with one sincos per trial; it equals the direct sum up to
- * rounding, so a decision can differ from the direct form's only when p lies
- * within a few units in the last place of P.
+ * The sweep keeps cos and sin of every angle (recomputed from the angles
+ * at the start of each call) and forms the sum by the angle-difference
+ * identity (sum_delta cos(theta' - theta_delta) = cos theta' sum cos
+ * theta_delta + sin theta' sum sin theta_delta), with one sincos per trial;
+ * it equals the direct sum up to rounding, so a decision can differ from the
+ * direct sum's only when p lies within a few units in the last place of P.
  * Random start: theta_n from out[0], out[1] of counter (n, id, 0, 9).
  * The sweep index t lives in device memory and advances on the device.
  */
@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define ISING_XY_MAX_L 128 /* the angles of one lattice in LDS: L*L doubles */
+#define ISING_XY_MAX_L 128 /* largest side (the paper's largest lattice) */
 #define ISING_XY_MAX_COUNT 4096
 
 typedef struct ising_xy {
@@ -56,9 +56,12 @@ typedef struct ising_xy {
     void *workspace;      /* device, 256-B aligned, >= ising_xy_workspace_bytes */
 } ising_xy;
 
-/* Workspace: sweep index, accepted-rotation counters, error word, and the
- * per-lattice energy sums of the large-lattice sweep. */
-ISING_API size_t ising_xy_workspace_bytes(int32_t count);
+/* Workspace of count lattices of side L: sweep index, accepted-rotation
+ * counters, error word, the per-lattice energy sums of the large-lattice
+ * sweep and, for L > 80, the cosine and sine of every angle (16 B per site).
+ * 0 for L or count out of range.  The library cannot check the size it is
+ * given: a smaller workspace is undefined behaviour. */
+ISING_API size_t ising_xy_workspace_bytes(int32_t L, int32_t count);
 
 /* Random (ISING_START_RANDOM) or aligned (theta = 0, ISING_START_COLD_UP)
  * start of every lattice; sweep index 0; counters cleared. */

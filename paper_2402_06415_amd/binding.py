@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libising.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 LAYOUT_INT8 = 0
 LAYOUT_BIT1 = 1
 DRAWS_SITE = 0
@@ -217,7 +217,7 @@ def load_library():
                  "ising_ea_state", "ising_ea_check_device_error"):
         getattr(lib, name).restype = ctypes.c_int
     xy_p = P(ising_xy)
-    lib.ising_xy_workspace_bytes.argtypes = [ctypes.c_int32]
+    lib.ising_xy_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.ising_xy_workspace_bytes.restype = ctypes.c_size_t
     lib.ising_xy_init.argtypes = [xy_p, ctypes.c_int32, vp]
     lib.ising_xy_sweep.argtypes = [xy_p, ctypes.c_double, ctypes.c_int64, vp, vp]
@@ -464,8 +464,8 @@ def ising_ea_check_device_error(ea: ising_ea, stream: int = 0):
     _check(load_library().ising_ea_check_device_error(ctypes.byref(ea), stream))
 
 
-def ising_xy_workspace_bytes(count: int) -> int:
-    return int(load_library().ising_xy_workspace_bytes(count))
+def ising_xy_workspace_bytes(L: int, count: int) -> int:
+    return int(load_library().ising_xy_workspace_bytes(L, count))
 
 
 def ising_xy_init(xy: ising_xy, start: int, stream: int = 0):
@@ -843,7 +843,7 @@ class XYLattices:
 
         self.device = torch.device(device or "cuda")
         self.L, self.count = L, count
-        nw = ising_xy_workspace_bytes(count)
+        nw = ising_xy_workspace_bytes(L, count)
         if nw == 0 or L < 2 or L % 2 or L > 128:
             raise IsingError(E_INVALID, f"L={L}, count={count} invalid")
         self._th_raw, th = _aligned_buffer(count * L * L * 8, self.device)

@@ -40,10 +40,10 @@ unsigned char* ws_of(const ising_xy* xy) { return reinterpret_cast<unsigned char
 
 extern "C" {
 
-size_t ising_xy_workspace_bytes(int32_t count) {
-    if (count < 1 || count > ISING_XY_MAX_COUNT)
+size_t ising_xy_workspace_bytes(int32_t L, int32_t count) {
+    if (L < 2 || L > ISING_XY_MAX_L || (L & 1) || count < 1 || count > ISING_XY_MAX_COUNT)
         return 0;
-    return ising::xy_workspace_bytes(count);
+    return ising::xy_workspace_bytes(L, count);
 }
 
 int ising_xy_init(const ising_xy* xy, int32_t start, void* hip_stream) {

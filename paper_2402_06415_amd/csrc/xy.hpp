@@ -13,7 +13,7 @@ constexpr size_t kXyAccepted = 256;          // uint64[count]: accepted rotation
 inline size_t xy_energy_sums_offset(int count) {
     return kXyAccepted + (((size_t)count * 8 + 255) & ~(size_t)255);
 }
-size_t xy_workspace_bytes(int count);
+size_t xy_workspace_bytes(int L, int count);
 hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, int start, Key key,
                           uint32_t lid0, hipStream_t st);
 // prepare (validate, note t), the persistent sweep kernel, advance t

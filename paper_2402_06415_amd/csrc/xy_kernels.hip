@@ -1,26 +1,27 @@
 // Metropolis Monte Carlo of the 2D classical XY model in double precision.
 //
-// One workgroup owns one lattice: its L*L angles sit in LDS for all n
-// sweeps of a call (L <= 128: 128 KiB).  Within a half-sweep the threads
-// take the sites of one colour in turn; a site's trial reads its four
-// neighbours (the other colour) from LDS and writes its own angle, so the
-// update is in place and race-free.
+// Up to L = 80 one workgroup owns one lattice: its L*L angles, with the
+// cosine and sine of each (24 bytes per site), sit in LDS for all n sweeps
+// of a call.  Within a half-sweep the threads take the sites of one colour
+// in turn; a site's trial reads its four neighbours (the other colour) and
+// writes its own angle, so the update is in place and race-free.
 //
-// Larger lattices (L > 82) are swept by one launch per half-sweep over many
+// Larger lattices are swept by one launch per half-sweep over many
 // workgroups instead (a lattice on one CU would leave the rest of the GPU
-// idle): the angles stay in global memory, each thread makes one trial, and
-// the energy trace is carried by per-lattice sums in the workspace that
-// alternate between two slots from sweep to sweep, so that each sweep's
-// total is read only after a kernel boundary.
+// idle): angles, cosines and sines stay in global memory (the latter two in
+// the workspace, filled at the start of each call), each thread makes one
+// trial, and the energy trace is carried by per-lattice sums in the
+// workspace that alternate between two slots from sweep to sweep, so that
+// each sweep's total is read only after a kernel boundary.
 //
-// Where LDS also holds cos and sin of every angle (24 bytes per site, L <= 82)
-// the energy change of a trial is formed from them by the angle-difference
-// identity, cos(a - b) = cos a cos b + sin a sin b: one sincos of the
-// proposed angle per trial instead of eight cosines, and an accepted angle
-// stores the pair just computed.  The result equals the direct sum up to
-// rounding, so the two forms can decide a trial differently only when the
-// uniform draw lies within a few units in the last place of the acceptance
-// probability.  For the energy trace H is summed over
+// Both forms take the energy change of a trial from the cached cosines and
+// sines by the angle-difference identity, cos(a - b) = cos a cos b +
+// sin a sin b: one sincos of the proposed angle per trial instead of eight
+// cosines, and an accepted angle stores the pair just computed.  The result
+// equals the direct sum up to rounding, so a trial can be decided
+// differently from the direct form only when the uniform draw lies within a
+// few units in the last place of the acceptance probability.  For the
+// energy trace H is summed over
 // the lattice once per call and then carried from sweep to sweep by adding
 // the energy changes of the accepted trials (each wave sums its own, and
 // thread 0 adds the per-wave partials in a fixed order behind the next
@@ -127,12 +128,11 @@ __global__ void k_xy_advance(unsigned char* ws, int64_t n) {
         hd->t += (uint64_t)n;
 }
 
-template <bool kCache>
 __global__ void __launch_bounds__(512) k_xy_sweep(unsigned char* ws, double* theta, int L,
                                                   int count, int64_t n, double beta, Key key,
                                                   uint32_t lid0, double* E_trace) {
 #pragma clang fp contract(off)
-    extern __shared__ double th[];  // [N] angles, then with kCache [N] cos and [N] sin
+    extern __shared__ double th[];  // [N] angles, [N] cos, [N] sin
     __shared__ double red[16];
     XyHeader* hd = xy_header(ws);
     if (hd->ok == 0)
@@ -146,8 +146,7 @@ __global__ void __launch_bounds__(512) k_xy_sweep(unsigned char* ws, double* the
     double* const sn = th + 2 * N;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         th[i] = g[i];
-        if (kCache)
-            sincos(th[i], &sn[i], &cs[i]);
+        sincos(th[i], &sn[i], &cs[i]);
     }
     __syncthreads();
     const RoundKeys rk = round_keys(key);
@@ -172,31 +171,22 @@ __global__ void __launch_bounds__(512) k_xy_sweep(unsigned char* ws, double* the
                 const int nbi[4] = {row + (x + 1 == L ? 0 : x + 1), row + (x == 0 ? L - 1 : x - 1),
                                     (y + 1 == L ? 0 : y + 1) * L + x,
                                     (y == 0 ? L - 1 : y - 1) * L + x};
-                double d = 0.0, c_new = 0.0, s_new = 0.0;
-                if (kCache) {
-                    // sum_k cos(a - b_k) = cos a sum_k cos b_k + sin a sum_k sin b_k
-                    sincos(th_new, &s_new, &c_new);
-                    double sc = 0.0, ss = 0.0;
+                // sum_k cos(a - b_k) = cos a sum_k cos b_k + sin a sum_k sin b_k
+                double c_new, s_new;
+                sincos(th_new, &s_new, &c_new);
+                double sc = 0.0, ss = 0.0;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        sc += cs[nbi[k]];
-                        ss += sn[nbi[k]];
-                    }
-                    d = (c_new - cs[i]) * sc + (s_new - sn[i]) * ss;
-                } else {
-                    const double t = th[i];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        d += cos(th_new - th[nbi[k]]) - cos(t - th[nbi[k]]);
+                for (int k = 0; k < 4; ++k) {
+                    sc += cs[nbi[k]];
+                    ss += sn[nbi[k]];
                 }
+                const double d = (c_new - cs[i]) * sc + (s_new - sn[i]) * ss;
                 const double dE = -d;
                 const double P = exp(-beta * dE);
                 if (p < P) {
                     th[i] = th_new;
-                    if (kCache) {
-                        cs[i] = c_new;
-                        sn[i] = s_new;
-                    }
+                    cs[i] = c_new;
+                    sn[i] = s_new;
                     ++acc;
                     dEs += dE;
                 }
@@ -259,7 +249,7 @@ __global__ void k_xy_energy(const double* theta, int L, double* E_out) {
 __global__ void __launch_bounds__(256) k_xy_halfsweep_g(unsigned char* ws, double* theta, int L,
                                                         int count, int c, int64_t sw, int64_t n,
                                                         double beta, Key key, uint32_t lid0,
-                                                        double* S, double* E_trace) {
+                                                        double* S, double* trig, double* E_trace) {
 #pragma clang fp contract(off)
     __shared__ double red[4];
     __shared__ unsigned long long racc[4];
@@ -294,16 +284,25 @@ __global__ void __launch_bounds__(256) k_xy_halfsweep_g(unsigned char* ws, doubl
         const int i = row + x;
         const int nbi[4] = {row + (x + 1 == L ? 0 : x + 1), row + (x == 0 ? L - 1 : x - 1),
                             (y + 1 == L ? 0 : y + 1) * L + x, (y == 0 ? L - 1 : y - 1) * L + x};
-        const double t = th[i];
-        const double nb[4] = {th[nbi[0]], th[nbi[1]], th[nbi[2]], th[nbi[3]]};
-        double d = 0.0;
+        // the angle-difference identity over cached cosines and sines, the
+        // same arithmetic as the workgroup-resident form
+        double* cs = trig + (size_t)j * 2 * N;
+        double* sn = cs + N;
+        double sc = 0.0, ss = 0.0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            d += cos(th_new - nb[k]) - cos(t - nb[k]);
+        for (int k = 0; k < 4; ++k) {
+            sc += cs[nbi[k]];
+            ss += sn[nbi[k]];
+        }
+        double s_new, c_new;
+        sincos(th_new, &s_new, &c_new);
+        const double d = (c_new - cs[i]) * sc + (s_new - sn[i]) * ss;
         const double dE = -d;
         const double P = exp(-beta * dE);
         if (p < P) {
             th[i] = th_new;
+            cs[i] = c_new;
+            sn[i] = s_new;
             acc = 1;
             dE_acc = dE;
         }
@@ -346,6 +345,18 @@ __global__ void k_xy_sums_start(unsigned char* ws, const double* theta, int L, i
     }
 }
 
+// Cosine and sine of every angle, for the global-memory sweep of a call.
+__global__ void k_xy_trig_fill(unsigned char* ws, const double* theta, int N, double* trig) {
+    if (xy_header(ws)->ok == 0)
+        return;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N)
+        return;
+    const int j = blockIdx.y;
+    double* cs = trig + (size_t)j * 2 * N;
+    sincos(theta[(int64_t)j * N + n], &cs[N + n], &cs[n]);
+}
+
 // The last sweep's energies into the trace.
 __global__ void k_xy_sums_finish(unsigned char* ws, int count, int64_t n, const double* S,
                                  double* E_trace) {
@@ -358,9 +369,16 @@ __global__ void k_xy_sums_finish(unsigned char* ws, int count, int64_t n, const 
 
 }  // namespace
 
-size_t xy_workspace_bytes(int count) {
-    // accepted counters, then the two slots of per-lattice energy sums
+bool xy_global_path(int L) { return 3 * (size_t)L * L * sizeof(double) > kXyCacheLds; }
+
+size_t xy_trig_offset(int count) {
     return xy_energy_sums_offset(count) + (((size_t)count * 16 + 255) & ~(size_t)255);
+}
+
+size_t xy_workspace_bytes(int L, int count) {
+    // accepted counters, the two slots of per-lattice energy sums, then for
+    // the global-memory sweep the cosines and sines of every angle
+    return xy_trig_offset(count) + (xy_global_path(L) ? (size_t)count * L * L * 16 : 0);
 }
 
 hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, int start, Key key,
@@ -374,19 +392,21 @@ hipError_t launch_xy_init(unsigned char* ws, double* theta, int L, int count, in
 hipError_t launch_xy_sweep(unsigned char* ws, double* theta, int L, int count, int64_t n,
                            double beta, Key key, uint32_t lid0, double* E_trace, hipStream_t st) {
     hipLaunchKernelGGL(k_xy_prepare, dim3(1), dim3(1), 0, st, ws, count, n);
-    const size_t plane_bytes = (size_t)L * L * sizeof(double);
-    if (3 * plane_bytes > kXyCacheLds) {
+    if (xy_global_path(L)) {
         // one launch per half-sweep over many workgroups
         double* S = reinterpret_cast<double*>(ws + xy_energy_sums_offset(count));
+        double* trig = reinterpret_cast<double*>(ws + xy_trig_offset(count));
         const int trials = L * L / 2;
         const dim3 grid((unsigned)((trials + 255) / 256), (unsigned)count);
+        hipLaunchKernelGGL(k_xy_trig_fill, dim3((unsigned)((L * L + 255) / 256), (unsigned)count),
+                           dim3(256), 0, st, ws, theta, L * L, trig);
         if (E_trace)
             hipLaunchKernelGGL(k_xy_sums_start, dim3(count), dim3(256), 0, st, ws, theta, L, count,
                                S);
         for (int64_t sw = 0; sw < n; ++sw)
             for (int c = 0; c < 2; ++c)
                 hipLaunchKernelGGL(k_xy_halfsweep_g, grid, dim3(256), 0, st, ws, theta, L, count,
-                                   c, sw, n, beta, key, lid0, S, E_trace);
+                                   c, sw, n, beta, key, lid0, S, trig, E_trace);
         if (E_trace && n > 0)
             hipLaunchKernelGGL(k_xy_sums_finish, dim3((count + 255) / 256), dim3(256), 0, st, ws,
                                count, n, S, E_trace);
@@ -399,12 +419,8 @@ hipError_t launch_xy_sweep(unsigned char* ws, double* theta, int L, int count, i
     int threads = ((L * L / 2 + 63) / 64) * 64;
     threads = threads < 64 ? 64 : (threads > 512 ? 512 : threads);
     const size_t plane = (size_t)L * L * sizeof(double);
-    if (3 * plane <= kXyCacheLds)
-        hipLaunchKernelGGL(k_xy_sweep<true>, dim3(count), dim3(threads), 3 * plane, st, ws, theta,
-                           L, count, n, beta, key, lid0, E_trace);
-    else
-        hipLaunchKernelGGL(k_xy_sweep<false>, dim3(count), dim3(threads), plane, st, ws, theta, L,
-                           count, n, beta, key, lid0, E_trace);
+    hipLaunchKernelGGL(k_xy_sweep, dim3(count), dim3(threads), 3 * plane, st, ws, theta, L, count,
+                       n, beta, key, lid0, E_trace);
     hipLaunchKernelGGL(k_xy_advance, dim3(1), dim3(1), 0, st, ws, n);
     return hipGetLastError();
 }

@@ -175,7 +175,7 @@ def _batch(**kw):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(abi_version=3), dict(count=0), dict(count=65537), dict(max_L=12), dict(max_L=264),
+    dict(abi_version=99), dict(count=0), dict(count=65537), dict(max_L=12), dict(max_L=264),
     dict(threads=100), dict(threads=2048), dict(groups_per_cu=17), dict(spins=0),
     dict(spins=0x10010), dict(workspace=0), dict(workspace=0x20004),
     dict(lattice_id0=2 ** 32 - 1), dict(draws=2), dict(draws=-1), dict(reserved=1),
@@ -247,3 +247,16 @@ def test_invalid_spin_glasses_are_rejected_before_any_launch(kw, msg):
         lib.ising_ea_setup(e, [0.4, 0.8])
     assert err.value.code == binding.E_INVALID and msg in lib.ising_last_error()
     assert bytes(e) == before
+
+
+def test_xy_workspace_bytes():
+    """The large-lattice sweep (L > 80) keeps 16 B of cosine and sine per site."""
+    assert lib.ising_xy_workspace_bytes(1, 10) == 0
+    assert lib.ising_xy_workspace_bytes(130, 10) == 0
+    assert lib.ising_xy_workspace_bytes(32, 0) == 0
+    assert lib.ising_xy_workspace_bytes(32, 4097) == 0
+    small = lib.ising_xy_workspace_bytes(80, 10)
+    assert small > 0 and small % 256 == 0
+    assert lib.ising_xy_workspace_bytes(2, 10) == small
+    assert lib.ising_xy_workspace_bytes(82, 10) == small + 10 * 82 * 82 * 16
+    assert lib.ising_xy_workspace_bytes(128, 4096) >= 4096 * 128 * 128 * 16

@@ -2,9 +2,9 @@
 
 Both sides draw the same Philox trials and form the energy change in
 double precision without fused multiply-adds: the oracle as the sum of
-eight cosines of angle differences, the kernel the same way for L > 82 and
-through cached cos/sin of every angle and the angle-difference identity
-below that.  The two agree to a few units in the last place, so the angles
+eight cosines of angle differences, the kernel through cached cos/sin of
+every angle and the angle-difference identity (in LDS up to L = 80, in
+global memory above).  The two agree to a few units in the last place, so the angles
 must agree bit for bit: a decision could only differ where p lies that
 close to the acceptance probability (probability ~1e-15 per trial).  The
 energy trace is a recount at the start of each call plus the accepted
@@ -81,10 +81,12 @@ def test_xy_beta_cases(beta):
     _compare(8, 2, beta, 5, (6,), start="cold" if beta == 20.0 else "random")
 
 
-@pytest.mark.parametrize("L", [64, 80, 84])
+@pytest.mark.parametrize("L", [64, 80, 82, 84])
 def test_xy_cos_sin_cache_boundary(L):
     """L = 80 is the largest side whose angles, cosines and sines fit LDS
-    together (150 KiB); L = 84 takes the direct form."""
+    together (150 KiB); L = 82 and 84 take the global-memory form, whose
+    cosines and sines are refilled from the angles at each of the two
+    calls."""
     _compare(L, 2, BETA_XY, 13, (4, 3), lid0=1)
 
 
@@ -92,7 +94,8 @@ def test_xy_cos_sin_cache_boundary(L):
 def test_xy_trace_does_not_change_the_chain(L):
     """Sweeping without an energy trace skips all energy work; the angles
     must equal the traced run's bit for bit, and the trace's last entry the
-    recount (cached form at L = 32, direct form at L = 96)."""
+    recount (workgroup-resident form at L = 32, global-memory form at
+    L = 96)."""
     say(f"xy no trace L={L}")
     a = lib.XYLattices(L, 3, seed=17, start="random")
     b = lib.XYLattices(L, 3, seed=17, start="random")
@@ -114,7 +117,7 @@ def test_xy_papers_largest_size():
 def test_xy_sweep_before_init_is_a_device_error():
     say("xy no init")
     raw_t, th = lib.binding._aligned_buffer(4 * 4 * 8, "cuda")
-    raw_w, ws = lib.binding._aligned_buffer(lib.ising_xy_workspace_bytes(1), "cuda")
+    raw_w, ws = lib.binding._aligned_buffer(lib.ising_xy_workspace_bytes(4, 1), "cuda")
     th.fill_(0)
     c = lib.ising_xy(lib.binding.ABI_VERSION, 4, 1, 0, 1, th.data_ptr(), ws.data_ptr())
     lib.ising_xy_sweep(c, 1.0, 3)
