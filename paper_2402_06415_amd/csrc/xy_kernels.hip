@@ -241,7 +241,8 @@ __global__ void k_xy_energy(const double* theta, int L, double* E_out) {
 
 // One half-sweep (colour c, sweep sw of the call) of every lattice from
 // global memory, one trial per thread: grid (trials / blockDim, count).
-// The trial is the one of k_xy_sweep's direct form.  Energy sums S (two
+// The trial is k_xy_sweep's, the cached cosines and sines taken from trig
+// (double[count][2][L*L], filled by k_xy_trig_fill).  Energy sums S (two
 // slots of count doubles): sweep sw adds into slot sw & 1; the colour-0
 // launch of sweep sw >= 1 first carries the previous slot's total in (and
 // writes it to the trace), and the colour-1 launch clears the other slot for
