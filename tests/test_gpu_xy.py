@@ -136,3 +136,28 @@ def test_xy_two_by_two_torus_on_the_gpu():
     err = blocks.std(ddof=1) / np.sqrt(40)
     exact = _ring_mean_energy(BETA_XY)
     assert abs(blocks.mean() - exact) < 4 * err, (blocks.mean(), exact, err)
+
+
+def test_xy_largest_batch_at_the_largest_side():
+    """4096 lattices of L = 128, the most the ABI takes, in the global-memory
+    form (1 GiB of cached cosines and sines): three sampled lattices equal
+    the oracle's bit for bit over two calls, and every lattice's carried
+    energy equals its recount."""
+    L, count, seed, lid0 = 128, 4096, 29, 5
+    say(f"xy largest batch L={L} count={count}")
+    g = lib.XYLattices(L, count, seed=seed, lattice_id0=lid0, start="random")
+    picks = (0, 2047, count - 1)
+    th = {j: oracle.xy_init(L, oracle.START_RANDOM, seed, lid0 + j) for j in picks}
+    t = 0
+    for n in (2, 1):
+        E = _host(g.sweep(BETA_XY, n))
+        for j in picks:
+            Eo, _ = oracle.xy_sweep(th[j], seed, lid0 + j, t, n, BETA_XY)
+            assert np.allclose(E[:, j], Eo, rtol=0, atol=1e-12 * 2 * L * L), j
+        t += n
+        got = _host(g.theta[list(picks)])
+        for k, j in enumerate(picks):
+            assert (got[k] == th[j]).all(), f"lattice {j} after sweep {t}"
+    assert np.allclose(E[-1], _host(g.energy()), rtol=0, atol=1e-12 * 2 * L * L)
+    assert g.state()[0] == 3
+    g.check()
