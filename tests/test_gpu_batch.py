@@ -223,3 +223,31 @@ def test_batched_workload_full_size_sampled():
     _check_spins(b, states, js)
     assert b.sweep_index == n
     b.check()
+
+
+@pytest.mark.parametrize("draws", ["site", "plane"])
+def test_largest_batch_count_sampled(draws):
+    """65536 lattices, the most a batch takes, of two alternating sides:
+    five sampled lattices (both ends and the middle) bit for bit against the
+    oracle, and every lattice's last E and M against a recount."""
+    count, n, seed = 65536, 4, 23
+    sides = (16, 32) if draws == "site" else (32, 64)
+    L = np.array([sides[j & 1] for j in range(count)], np.int32)
+    beta = np.array([0.30 + 0.3 * (j % 64) / 63 for j in range(count)])
+    say(f"largest batch {count} draws={draws}")
+    b = lib.Batch(L, beta, seed=seed, start="random", draws=draws)
+    mom = b.sweep(n)
+    E, M = b.measure()
+    momh = _host(mom)
+    assert (momh[:, 0] == _host(E)).all() and (momh[:, 1] == _host(M)).all()
+    mode = oracle.MODE_SITE if draws == "site" else oracle.MODE_PLANE
+    js = [0, 1, count // 2, count - 2, count - 1]
+    states, want = [], []
+    for j in js:
+        s = oracle.init(int(L[j]), oracle.START_RANDOM, seed, j)
+        want.append(oracle.batch_sweep([s], [beta[j]], seed, j, 0, n, mode=mode)[0])
+        states.append(s)
+    _check_moments(mom, want, js)
+    _check_spins(b, states, js)
+    assert b.sweep_index == n
+    b.check()
