@@ -144,3 +144,18 @@ def test_spin_glass_workload_full_size_first_sweeps():
     for r in (0, 21, 42, 63):
         assert (_host(g.replica(r)) == spins[r]).all(), f"replica {r}"
     g.check()
+
+
+def test_most_replicas():
+    """1024 replicas, the most the ABI takes, on an 8^3 glass: every
+    replica's energy trace, the temperature order and every spin, over two
+    calls with an exchange every other sweep.  Adjacent betas are 0.002
+    apart: the swap table of a pair holds 4096 entries, which needs a step
+    of at least 32 ln 2 / 16384."""
+    _compare(8, 1024, np.linspace(0.2, 2.2, 1024), 31, 5, (4, 3), 2, nthreads=16)
+
+
+def test_largest_side():
+    """L = 512, the largest side (2^27 spins per replica), two replicas over
+    two sweeps with an exchange after each."""
+    _compare(512, 2, np.array([0.5, 1.0]), 37, 7, (2,), 1, nthreads=16)

@@ -149,3 +149,15 @@ def test_plane_spin_glass_workload_full_size_first_sweeps():
     for r in (0, 21, 42, 63):
         assert (_host(g.replica(r)) == spins[r]).all(), f"replica {r}"
     g.check()
+
+
+def test_plane_most_replicas():
+    """1024 replicas, the most the ABI takes, at the smallest plane side
+    (L = 64): energies, order and three replicas' spins after two sweeps."""
+    _compare(64, 1024, np.linspace(0.2, 2.2, 1024), 31, 5, (2,), 1, check=(0, 511, 1023))
+
+
+def test_plane_largest_side():
+    """L = 512, the largest side (2^27 spins per replica), two replicas over
+    two sweeps with an exchange after each."""
+    _compare(512, 2, np.array([0.5, 1.0]), 37, 7, (2,), 1)
