@@ -84,7 +84,7 @@ def test_symmetrised_logq_matches_oracle(L, B):
     assert (neg == got).all()
 
 
-@pytest.mark.parametrize("L,B", [(8, 16), (32, 64), (7, 5)])
+@pytest.mark.parametrize("L,B", [(8, 16), (32, 64), (7, 5), (64, 2)])
 def test_gradient_matches_oracle(L, B):
     say(f"grad L={L} B={B}")
     net, p = _net(L, B, 5, scale=1.5)
@@ -130,7 +130,7 @@ def _oracle_uniforms(B, N, seed, chain0, draw):
     return r
 
 
-@pytest.mark.parametrize("L,B,sym", [(6, 16, False), (16, 8, False), (34, 2, False),
+@pytest.mark.parametrize("L,B,sym", [(6, 16, False), (16, 8, False), (34, 2, False), (64, 1, False),
                                      (6, 32, True), (20, 8, True)])
 def test_sampler_matches_oracle(L, B, sym):
     say(f"sample L={L} B={B} symmetric={sym}")
