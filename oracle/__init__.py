@@ -309,6 +309,22 @@ def ea_halfsweep(s: np.ndarray, J: np.ndarray, c: int, seed: int, replica_id: in
     return dE.value
 
 
+def ea_exchange(E: np.ndarray, perm: np.ndarray, beta, m: int, seed: int,
+                accepts: np.ndarray = None):
+    """Exchange number m on the ladder beta [R] (increasing): perm (int32
+    [R], temperature -> replica) is updated in place from the energies E
+    (int64 [R], per replica); accepts (uint64 [R-1]) counts the swaps."""
+    R = len(perm)
+    E = np.ascontiguousarray(E, np.int64)
+    beta = np.ascontiguousarray(beta, np.float64)
+    if accepts is None:
+        accepts = np.zeros(max(R - 1, 1), np.uint64)
+    _load().oracle_ea_exchange(_ptr(E, ctypes.c_int64), _ptr(perm, ctypes.c_int32), R,
+                               _ptr(beta, ctypes.c_double), m, seed,
+                               _ptr(accepts, ctypes.c_uint64))
+    return accepts
+
+
 def ea_run(spins: np.ndarray, J: np.ndarray, beta, seed: int, t0: int, n: int, every: int,
            perm: np.ndarray, E: np.ndarray, accepts: np.ndarray = None, trace: bool = True,
            nthreads: int = 1, mode: int = MODE_SITE):

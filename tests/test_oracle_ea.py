@@ -2,8 +2,10 @@
 against 80-digit arithmetic and printed closed-form values, the energy
 against an independent numpy formula, E(flip) - E = 2u, exact gauge
 invariance of the whole chain, exact detailed balance of each half-sweep
-on the 2^8 states of a 2x2x2 lattice, and replica exchange sampling each
-temperature's exact distribution."""
+on the 2^8 states of a 2x2x2 lattice, replica exchange sampling each
+temperature's exact distribution, and every counter map (per-site draws,
+plane draws, random start, exchange draws) recomputed through PyTorch's
+independent Philox engine."""
 import mpmath as mp
 import numpy as np
 import pytest
@@ -245,3 +247,90 @@ def test_plane_and_site_modes_differ_but_share_everything_else():
         oracle.ea_run(b, J, beta, 3, 0, 4, 0, pb, Eb, trace=False, mode=PLANE)
         assert (a == b).all() == same
         b[:] = a
+
+
+# ---------------------------------------------------------------------------
+# Counter maps of the per-site draws, the random start and the exchange
+# draws, recomputed through PyTorch's own Philox engine (conftest.py): the
+# oracle's decisions must follow from those draws and from the pinned
+# thresholds and local fields alone.
+
+@pytest.mark.parametrize("L,c,t,rid", [(6, 0, 0, 0), (6, 1, 5, 3), (8, 0, 11, 62)])
+def test_site_draw_counter_layout(torch_philox, L, c, t, rid):
+    """Per-site draws: site n of colour c takes r = out[q & 3] of the block
+    (q >> 2, replica, 2t + c, 0), q = n >> 1; it flips iff u <= 0 or
+    r < T(u).  Sites of one colour do not neighbour each other, so every
+    decision is taken on the state before the half-sweep."""
+    seed = (7 << 32) | 4242
+    beta = 0.15
+    J = ea_bonds(L, 17)
+    s0 = oracle.ea_init(L, 1, 19, rid)
+    T, a = oracle.ea_thresholds(beta)
+    sites = [n for n in range(L ** 3)
+             if ((n % L) + (n // L) % L + n // (L * L)) % 2 == c]
+    rows = [[seed & 0xFFFFFFFF, seed >> 32, (n >> 1) >> 2, rid, 2 * t + c, 0] for n in sites]
+    ref = torch_philox(rows)
+    want = s0.copy().reshape(-1)
+    dE_want, drawn_flips, drawn_keeps = 0, 0, 0
+    for n, out in zip(sites, ref):
+        u = oracle.ea_local_u(s0, J, n)
+        if u <= 0 or a[u // 2 - 1]:
+            flip = True
+        else:
+            flip = int(out[(n >> 1) & 3]) < int(T[u // 2 - 1])
+            drawn_flips += flip
+            drawn_keeps += not flip
+        if flip:
+            want[n] = -want[n]
+            dE_want += 2 * u
+    assert drawn_flips > 3 and drawn_keeps > 3  # both outcomes hinge on the draws
+    s = s0.copy()
+    dE = oracle.ea_halfsweep(s, J, c, seed, rid, t, beta, mode=oracle.MODE_SITE)
+    assert (s.reshape(-1) == want).all()
+    assert dE == dE_want
+
+
+def test_random_start_counter_layout(torch_philox):
+    """Random start of replica r: s_n = -1 iff the top bit of out[n & 3] of
+    the block (n >> 2, r, 0, 2) is set."""
+    L, seed, rid = 6, (3 << 32) | 11, 9
+    s = oracle.ea_init(L, 1, seed, rid).reshape(-1)
+    ref = torch_philox([[seed & 0xFFFFFFFF, seed >> 32, n >> 2, rid, 0, 2] for n in range(L ** 3)])
+    want = np.array([-1 if int(ref[n][n & 3]) >> 31 else 1 for n in range(L ** 3)])
+    assert (s == want).all()
+    assert (oracle.ea_init(L, 0, seed, rid) == 1).all()
+
+
+@pytest.mark.parametrize("m", [0, 1, 6, 7])
+def test_exchange_draw_counter_layout(torch_philox, m):
+    """Exchange number m visits the pairs (k, k + 1), k = m & 1, m & 1 + 2,
+    ...; with D = E(at k) - E(at k + 1) > 0 the swap takes r = out[0] of the
+    block (k, m, 0, 5) and is accepted iff r < T(beta_k, beta_k+1, D)."""
+    R, seed = 12, (5 << 32) | 77
+    beta = 0.5 + 0.05 * np.arange(R)
+    rng = np.random.default_rng(m)
+    E = rng.integers(-400, -300, R).astype(np.int64)
+    # energies decreasing along the ladder so that most pairs need a draw,
+    # with steps giving acceptance probabilities between 0.1 and 0.8
+    E = -300 - np.cumsum(rng.integers(1, 12, R) * 4).astype(np.int64)
+    E[R // 2] = E[R // 2 + 1] - 8  # one pair with D < 0: swaps without a draw
+    perm0 = rng.permutation(R).astype(np.int32)
+    Erep = np.empty(R, np.int64)
+    Erep[perm0] = E  # replica perm0[k] sits at temperature k with energy E[k]
+    want = perm0.copy()
+    drawn = {True: 0, False: 0}
+    for k in range(m & 1, R - 1, 2):
+        D = int(Erep[want[k]] - Erep[want[k + 1]])
+        T, always = oracle.ea_swap_threshold(beta[k], beta[k + 1], D)
+        if always:
+            swap = True
+        else:
+            r = int(torch_philox([[seed & 0xFFFFFFFF, seed >> 32, k, m, 0, 5]])[0][0])
+            swap = r < T
+            drawn[swap] += 1
+        if swap:
+            want[k], want[k + 1] = want[k + 1], want[k]
+    perm = perm0.copy()
+    oracle.ea_exchange(Erep, perm, beta, m, seed)
+    assert (perm == want).all()
+    assert drawn[True] + drawn[False] >= 3
