@@ -122,21 +122,59 @@ ISING_API int32_t ising_abi_version(void);
 ISING_API int ising_thresholds(double beta, uint32_t T[5], uint8_t always_flip[5]);
 
 /* Fill the spins: ISING_START_COLD_UP (all +1) or ISING_START_RANDOM
- * (Philox draw per site, see above) and set sweep_index = 0.
- * Errors: invalid lattice description or start -> ISING_E_INVALID. */
+ * (Philox draw per site, see above) and set sweep_index = 0; also clears
+ * the workspace's accumulators, device error word and draw counters.
+ * Paper: the start of a Monte Carlo trajectory, fixed by its random seed
+ * (Supplementary, "Detail of the MC calculation for the XY model": each
+ * simulation runs from its own initial random seed, giving its own
+ * trajectory).  Asynchronous on hip_stream; spins and workspace stay
+ * caller-owned.
+ * Errors: invalid lattice description or start -> ISING_E_INVALID, nothing
+ * enqueued. */
 ISING_API int ising_init(ising_lattice *lat, int32_t start, void *hip_stream);
 
 /* Run n >= 0 sweeps at inverse temperature beta from sweep index
- * lat->sweep_index, then advance it by n.  E_dev / M_dev, when non-NULL,
- * are device int64[n] receiving E and M after each sweep of this call.
- * sweep(b, n1) followed by sweep(b, n2) equals sweep(b, n1 + n2) bit for
- * bit.  Errors: beta negative, NaN or infinite; n < 0;
- * sweep_index + n > 2^31; invalid lattice -> ISING_E_INVALID. */
+ * lat->sweep_index, then advance it by n.  Paper: Results, "Parallel
+ * design of MC simulation for the XY model", Fig. 2a-b (sublattices A and
+ * B updated alternately, each in parallel since no two sites of one
+ * sublattice are neighbours), every site trial following the three steps
+ * of Fig. 2c (draw p, compute dE and P = exp(-beta dE), accept iff p < P)
+ * with the thresholds of ising_thresholds.  One sweep is one MC step.
+ * E_dev / M_dev, when non-NULL, are device int64[n] (caller-owned)
+ * receiving E and M after each sweep of this call (not the state before
+ * it: that is ising_measure's).  sweep(b, n1) followed by sweep(b, n2)
+ * equals sweep(b, n1 + n2) bit for bit, because the draws are keyed by
+ * the sweep index.  Asynchronous on hip_stream.  Errors: beta negative,
+ * NaN or infinite; n < 0; sweep_index + n > 2^31; invalid lattice ->
+ * ISING_E_INVALID, nothing enqueued and sweep_index unchanged;
+ * ISING_E_HIP if a launch fails (spins then undefined). */
 ISING_API int ising_sweep(ising_lattice *lat, double beta, int64_t n, int64_t *E_dev,
                 int64_t *M_dev, void *hip_stream);
 
+/* ising_sweep on a BIT1 lattice with the persistent tile kernel under a
+ * given tile shape instead of the library's choice: the lattice is cut
+ * into L / rows tiles of `rows` full-width rows, one workgroup of `waves`
+ * wavefronts each, resident in LDS for the whole call.  The chain does not
+ * depend on the shape (the same draws, the same decisions): this entry
+ * point exists so that the shapes can be compared, timed and tested.
+ * Paper: as ising_sweep; the tile is the GPU counterpart of the paper's
+ * supercell (Supplementary, "Details and comparisons of parallelization
+ * strategies applied to different lattice configurations").
+ * Errors: not BIT1, rows not dividing L into 2..1024 tiles, waves outside
+ * 1..min(16, rows) -> ISING_E_INVALID; a tile above 64 KiB of LDS or more
+ * tiles than the device holds at once -> ISING_E_UNSUPPORTED; in both
+ * cases nothing is enqueued.  Otherwise as ising_sweep. */
+ISING_API int ising_sweep_tiles(ising_lattice *lat, double beta, int64_t n, int32_t rows,
+                                int32_t waves, int64_t *E_dev, int64_t *M_dev, void *hip_stream);
+
 /* Recount E and M of the current spins from scratch into E_dev[0] and
- * M_dev[0] (device int64; either may be NULL). */
+ * M_dev[0] (device int64, caller-owned; either may be NULL):
+ * E = -sum over right and down bonds of s_i s_j, M = sum s_i.  Paper: the
+ * Hamiltonian of Eq. (1) restricted to theta in {0, pi}, whose per-site
+ * mean is the internal energy U = <H>/L^2 of Supplementary Eq. (S3).
+ * Asynchronous on hip_stream; uses the workspace accumulators, so it must
+ * not overlap another call on the same lattice.  Errors: invalid lattice
+ * -> ISING_E_INVALID. */
 ISING_API int ising_measure(const ising_lattice *lat, int64_t *E_dev, int64_t *M_dev,
                   void *hip_stream);
 

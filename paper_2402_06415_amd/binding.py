@@ -30,7 +30,7 @@ FLAG_GLOBAL_HALFSWEEP = 1
 
 EXPORTED = (
     "ising_spins_bytes", "ising_workspace_bytes", "ising_abi_version", "ising_thresholds",
-    "ising_init", "ising_sweep", "ising_measure", "ising_to_int8", "ising_from_int8",
+    "ising_init", "ising_sweep", "ising_sweep_tiles", "ising_measure", "ising_to_int8", "ising_from_int8",
     "ising_check_device_error", "ising_last_error", "ising_rng_blocks",
     "ising_batch_spins_bytes", "ising_batch_workspace_bytes", "ising_batch_setup",
     "ising_batch_init", "ising_batch_sweep", "ising_batch_measure", "ising_batch_sweep_index",
@@ -153,6 +153,9 @@ def load_library():
     lib.ising_init.restype = ctypes.c_int
     lib.ising_sweep.argtypes = [lat_p, ctypes.c_double, ctypes.c_int64, vp, vp, vp]
     lib.ising_sweep.restype = ctypes.c_int
+    lib.ising_sweep_tiles.argtypes = [lat_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_int32, vp, vp, vp]
+    lib.ising_sweep_tiles.restype = ctypes.c_int
     lib.ising_measure.argtypes = [lat_p, vp, vp, vp]
     lib.ising_measure.restype = ctypes.c_int
     lib.ising_to_int8.argtypes = [lat_p, vp, vp]
@@ -272,6 +275,12 @@ def ising_sweep(lat: ising_lattice, beta: float, n: int, E_dev: int = 0, M_dev: 
                 stream: int = 0):
     _check(load_library().ising_sweep(ctypes.byref(lat), float(beta), int(n), E_dev or None,
                                       M_dev or None, stream))
+
+
+def ising_sweep_tiles(lat: ising_lattice, beta: float, n: int, rows: int, waves: int,
+                      E_dev: int = 0, M_dev: int = 0, stream: int = 0):
+    _check(load_library().ising_sweep_tiles(ctypes.byref(lat), float(beta), int(n), int(rows),
+                                            int(waves), E_dev or None, M_dev or None, stream))
 
 
 def ising_measure(lat: ising_lattice, E_dev: int = 0, M_dev: int = 0, stream: int = 0):
@@ -539,17 +548,27 @@ class Lattice:
     def init(self, start: str = "cold"):
         ising_init(self.c, {"cold": START_COLD_UP, "random": START_RANDOM}[start], self._stream())
 
-    def sweep(self, beta: float, n: int, record: bool = True):
-        """n sweeps; returns device int64 tensors (E, M) after each sweep."""
+    def sweep(self, beta: float, n: int, record: bool = True, tiles=None):
+        """n sweeps; returns device int64 tensors (E, M) after each sweep.
+        tiles = (rows, waves) runs the BIT1 tile kernel under that shape
+        (ising_sweep_tiles) instead of the library's choice."""
         import torch
 
+        E = M = None
         if record:
             E = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
             M = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
-            ising_sweep(self.c, beta, n, E.data_ptr(), M.data_ptr(), self._stream())
-            return E[:n], M[:n]
-        ising_sweep(self.c, beta, n, 0, 0, self._stream())
-        return None, None
+        Ep, Mp = (E.data_ptr(), M.data_ptr()) if record else (0, 0)
+        if tiles is None:
+            ising_sweep(self.c, beta, n, Ep, Mp, self._stream())
+        else:
+            ising_sweep_tiles(self.c, beta, n, tiles[0], tiles[1], Ep, Mp, self._stream())
+        return (E[:n], M[:n]) if record else (None, None)
+
+    def set_sweep_index(self, t: int):
+        """Resume a chain: the next sweep draws as sweep t (with
+        from_int8, a checkpoint of spins and sweep index restores it)."""
+        self.c.sweep_index = int(t)
 
     def measure(self):
         import torch

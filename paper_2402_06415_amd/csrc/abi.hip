@@ -208,8 +208,10 @@ int ising_init(ising_lattice* lat, int32_t start, void* hip_stream) {
     return ISING_OK;
 }
 
-int ising_sweep(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev, int64_t* M_dev,
-                void* hip_stream) {
+// The sweep of ising_sweep and ising_sweep_tiles: `forced` (BIT1 only)
+// replaces the library's tile plan.
+static int sweep_impl(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev, int64_t* M_dev,
+                      void* hip_stream, const ising::Bit1TilePlan* forced) {
     int rc = validate(lat);
     if (rc)
         return rc;
@@ -266,7 +268,14 @@ int ising_sweep(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev, int6
     } else {
         uint32_t* planes = reinterpret_cast<uint32_t*>(lat->spins);
         ising::Bit1TilePlan plan;
-        if (!global_only && ising::plan_bit1_tiles(L, device_cus(), &plan)) {
+        bool tiles = false;
+        if (forced) {
+            plan = *forced;
+            tiles = true;
+        } else if (!global_only) {
+            tiles = ising::plan_bit1_tiles(L, device_cus(), &plan);
+        }
+        if (tiles) {
             HIP_TRY(ising::launch_sweep_bit1_tiles(planes, L, plan, n, t0, key, lat->lattice_id,
                                                    acc, Etr, Mtr, ws_of(lat), kSpinLimit, st),
                     "sweep_bit1_tiles");
@@ -286,6 +295,42 @@ int ising_sweep(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev, int6
         HIP_TRY(ising::launch_prefix_i64(Mtr, n, acc_ws + 3, st), "prefix");
     lat->sweep_index += (uint64_t)n;
     return ISING_OK;
+}
+
+int ising_sweep(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev, int64_t* M_dev,
+                void* hip_stream) {
+    return sweep_impl(lat, beta, n, E_dev, M_dev, hip_stream, nullptr);
+}
+
+int ising_sweep_tiles(ising_lattice* lat, double beta, int64_t n, int32_t rows, int32_t waves,
+                      int64_t* E_dev, int64_t* M_dev, void* hip_stream) {
+    int rc = validate(lat);
+    if (rc)
+        return rc;
+    if (lat->layout != ISING_LAYOUT_BIT1)
+        return set_error(ISING_E_INVALID, "ising_sweep_tiles needs the BIT1 layout");
+    const int L = lat->L;
+    if (rows < 1 || L % rows != 0 || L / rows < 2 || L / rows > ising::WsLayout::kMaxTiles)
+        return set_error(ISING_E_INVALID,
+                         "rows = %d: must divide L = %d into 2..%d tiles", rows, L,
+                         ising::WsLayout::kMaxTiles);
+    if (waves < 1 || waves > 16 || waves > rows)
+        return set_error(ISING_E_INVALID, "waves = %d: must be in 1..min(16, rows = %d)", waves,
+                         rows);
+    ising::Bit1TilePlan plan;
+    plan.ntiles = L / rows;
+    plan.rows = rows;
+    plan.threads = 64 * waves;
+    plan.lds = ising::tile_lds_bytes(L, rows);
+    if (plan.lds > (size_t)64 * 1024)
+        return set_error(ISING_E_UNSUPPORTED, "a tile of %d rows needs %zu bytes of LDS (> 64 KiB)",
+                         rows, plan.lds);
+    const int resident = ising::bit1_tiles_resident(L, plan);
+    if (resident < plan.ntiles)
+        return set_error(ISING_E_UNSUPPORTED,
+                         "%d tiles of %d rows x %d waves: only %d fit the device at once",
+                         plan.ntiles, rows, waves, resident);
+    return sweep_impl(lat, beta, n, E_dev, M_dev, hip_stream, &plan);
 }
 
 int ising_measure(const ising_lattice* lat, int64_t* E_dev, int64_t* M_dev, void* hip_stream) {

@@ -552,6 +552,20 @@ bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
     return true;
 }
 
+int bit1_tiles_resident(int L, const Bit1TilePlan& plan) {
+    (void)L;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    // the variant with traces uses the most registers: it bounds every variant
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(k_sweep_bit1_tiles<true, true>), plan.threads,
+            plan.lds) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
 hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& plan, int64_t n,
                                    uint32_t t0, Key key, uint32_t lid, Accept acc, long long* dE,
                                    long long* dM, unsigned char* ws, uint32_t spin_limit,

@@ -53,6 +53,11 @@ struct Bit1TilePlan {
     size_t lds = 0;     // dynamic LDS bytes
 };
 bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan);
+// LDS bytes of a tile of `rows` rows (both colours, one halo row each side).
+size_t tile_lds_bytes(int L, int rows);
+// How many tiles of this plan the device holds at once (0 if the query
+// fails); every tile must be resident for the inter-tile hand-off.
+int bit1_tiles_resident(int L, const Bit1TilePlan& plan);
 hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& plan,
                                    int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
                                    long long* dE, long long* dM, unsigned char* ws,

@@ -126,6 +126,24 @@ def test_bad_start_and_null_buffers():
         lib.ising_from_int8(lat, 0)
 
 
+@pytest.mark.parametrize("kw,rows,waves", [
+    (dict(), 4, 4),                      # INT8 lattice: the tile kernel is BIT1 only
+    (dict(layout=1, L=128), 3, 1),       # rows must divide L
+    (dict(layout=1, L=128), 128, 4),     # one tile: at least two
+    (dict(layout=1, L=4096), 2, 2),      # 2048 tiles: at most 1024
+    (dict(layout=1, L=128), 8, 0),       # waves in 1..min(16, rows)
+    (dict(layout=1, L=128), 8, 9),
+    (dict(layout=1, L=128, abi_version=1), 8, 8),
+])
+def test_sweep_tiles_rejects_bad_shapes_before_any_launch(kw, rows, waves):
+    lat = _lat(**kw)
+    before = bytes(lat)
+    with pytest.raises(lib.IsingError) as e:
+        lib.ising_sweep_tiles(lat, 0.4, 1, rows, waves)
+    assert e.value.code == binding.E_INVALID
+    assert bytes(lat) == before
+
+
 def test_sweep_of_zero_sweeps_launches_nothing():
     lat = _lat(sweep_index=5)
     lib.ising_sweep(lat, 0.4, 0)  # host-only early return, no device touched

@@ -9,8 +9,10 @@ relative error of order 1e-6 each, so log q (|log q| ~ 10^2..10^3) is held
 to 1e-5 relative plus 1e-3 absolute, gradients to 1e-4 of their largest
 component.  Sampling and acceptance decisions compare the same uint32
 draws against float thresholds: they agree except where a threshold lies
-within float32 error of the draw, so at most a few percent of sampled
-configurations may differ and every acceptance decision must agree."""
+within float32 error of the draw (about 1e-7 per site), so at most one
+sampled configuration in sixteen may differ (none in batches below 16),
+log q is compared on every configuration that agrees, and every acceptance
+decision must agree."""
 import sys
 
 import numpy as np
@@ -130,7 +132,7 @@ def _oracle_uniforms(B, N, seed, chain0, draw):
     return r
 
 
-@pytest.mark.parametrize("L,B,sym", [(6, 16, False), (16, 8, False), (34, 2, False), (64, 1, False),
+@pytest.mark.parametrize("L,B,sym", [(6, 16, False), (16, 8, False), (34, 2, False), (64, 8, False),
                                      (6, 32, True), (20, 8, True)])
 def test_sampler_matches_oracle(L, B, sym):
     say(f"sample L={L} B={B} symmetric={sym}")
@@ -151,7 +153,11 @@ def test_sampler_matches_oracle(L, B, sym):
         so = np.where(flip[:, None, None], -so, so)
         lqo = onn.logq_sym(_bf16(p), so, C)
     same = [(s[b] == so[b]).all() for b in range(B)]
-    assert sum(same) >= B - 1, f"{B - sum(same)} of {B} samples differ"
+    # a sample differs only where a float32 threshold lies within rounding
+    # of its uint32 draw (about 1e-7 per site): one in sixteen at most
+    allowed = B // 16
+    assert B - sum(same) <= allowed, f"{B - sum(same)} of {B} samples differ (allowed {allowed})"
+    assert sum(same) >= 1
     for b in range(B):
         if same[b]:
             assert abs(lq[b] - lqo[b]) <= 1e-5 * abs(lqo[b]) + 1e-3, (b, lq[b], lqo[b])

@@ -54,13 +54,13 @@ def _gpu_lattice(L, layout, seed, start, flags=0, lattice_id=0):
 
 
 def _compare_stepwise(L, layout, seed, start, beta, n, flags=0, chunk=1, lattice_id=0,
-                      record=True):
+                      record=True, tiles=None):
     """Sweep GPU and oracle side by side; compare spins, E, M after each call.
 
     record=False runs the sweeps without per-sweep observables (the kernel
     the benchmark times) and compares a recount instead."""
     say(f"L={L} layout={layout} seed={seed} start={start} beta={beta} n={n} flags={flags} "
-        f"chunk={chunk} record={record}")
+        f"chunk={chunk} record={record} tiles={tiles}")
     g = _gpu_lattice(L, layout, seed, start, flags, lattice_id)
     s = oracle.init(L, oracle.START_COLD_UP if start == "cold" else oracle.START_RANDOM, seed,
                     lattice_id)
@@ -68,8 +68,9 @@ def _compare_stepwise(L, layout, seed, start, beta, n, flags=0, chunk=1, lattice
     done = 0
     while done < n:
         k = min(chunk, n - done)
-        E, M = g.sweep(beta, k, record=record)
-        Eo, Mo = oracle.sweep(s, _mode(layout), seed, lattice_id, done, k, beta, nthreads=8)
+        E, M = g.sweep(beta, k, record=record, tiles=tiles)
+        Eo, Mo = oracle.sweep(s, _mode(layout), seed, lattice_id, done, k, beta,
+                              nthreads=oracle.max_threads())
         if record:
             Eg, Mg = _host(E), _host(M)
             assert (Eg == Eo).all() and (Mg == Mo).all(), f"E/M differ in sweeps {done}..{done + k}"
@@ -238,3 +239,136 @@ def test_throughput_workload_L4096_sampled_over_1000_sweeps():
     assert tuple(_host(full.measure()).tolist()) == (int(_host(Ef)[-1]), int(_host(Mf)[-1]))
     full.check()
     g.check()
+
+
+def test_throughput_workload_L4096_chained_50_sweeps():
+    """L=4096, 1 bit/spin, random start seed 7, beta=0.4406868: 50
+    consecutive sweeps of the kernel the benchmark times (no per-sweep
+    observables), the spins compared with the oracle's after every one."""
+    _compare_stepwise(4096, "bit1", 7, "random", BC, 50, chunk=1, record=False)
+
+
+def test_throughput_workload_L4096_full_1000_sweeps_against_oracle():
+    """The whole throughput workload in one call (10^3 sweeps): E and M
+    after every sweep and the final spins equal the oracle's chain from the
+    same start."""
+    L, seed, n = 4096, 7, 1000
+    say("L=4096 1000 sweeps, full chain against the oracle")
+    g = _gpu_lattice(L, "bit1", seed, "random")
+    E, M = g.sweep(BC, n)
+    s = oracle.init(L, oracle.START_RANDOM, seed)
+    Eo, Mo = oracle.sweep(s, PLANE, seed, 0, 0, n, BC, nthreads=oracle.max_threads())
+    assert (_host(E) == Eo).all() and (_host(M) == Mo).all()
+    assert (_host(g.to_int8()) == s).all()
+    g.check()
+
+
+# (rows per tile, waves per tile): the library's plan at L = 4096 on 256
+# CUs is (4, 4); the others put one, two or four rows on a wave, one to
+# sixteen waves on a tile, and 128 to 1024 tiles on the GPU.
+TILE_SHAPES = [(4, 4), (4, 2), (4, 1), (8, 8), (8, 2), (16, 16), (16, 4), (32, 8)]
+
+
+def test_tile_shapes_give_the_same_chain_L4096():
+    """The throughput lattice under eight tile shapes: every shape gives the
+    same E and M after every sweep and the same spins, equal to the
+    oracle's chain."""
+    L, seed, n = 4096, 7, 20
+    s = oracle.init(L, oracle.START_RANDOM, seed)
+    Eo, Mo = oracle.sweep(s, PLANE, seed, 0, 0, n, BC, nthreads=oracle.max_threads())
+    for rows, waves in TILE_SHAPES:
+        say(f"L=4096 tiles rows={rows} waves={waves} n={n}")
+        g = _gpu_lattice(L, "bit1", seed, "random")
+        E, M = g.sweep(BC, n, tiles=(rows, waves))
+        assert (_host(E) == Eo).all() and (_host(M) == Mo).all(), (rows, waves)
+        assert (_host(g.to_int8()) == s).all(), (rows, waves)
+        g.check()
+
+
+@pytest.mark.parametrize("rows,waves", [(2, 2), (4, 1), (8, 4)])
+def test_tile_shapes_at_a_ragged_side(rows, waves):
+    """L = 320 (five words per row) under shapes other than the library's."""
+    _compare_stepwise(320, "bit1", 8, "random", BC, 9, chunk=4, tiles=(rows, waves))
+
+
+def test_sweep_tiles_reports_shapes_the_device_cannot_hold():
+    """A tile of 512 rows at L = 4096 needs 256 KiB of LDS: refused before
+    any launch, the lattice untouched."""
+    g = _gpu_lattice(4096, "bit1", 7, "random")
+    before = _host(g.to_int8())
+    with pytest.raises(lib.IsingError) as e:
+        g.sweep(BC, 1, tiles=(512, 16))
+    assert e.value.code == lib.binding.E_UNSUPPORTED
+    assert g.sweep_index == 0
+    assert (_host(g.to_int8()) == before).all()
+
+
+@pytest.mark.parametrize("layout,L,flags", [("bit1", 256, 0), ("bit1", 4096, 0),
+                                            ("int8", 64, 0), ("int8", 200, 0),
+                                            ("bit1", 192, lib.FLAG_GLOBAL_HALFSWEEP)])
+def test_checkpoint_and_resume(layout, L, flags):
+    """Checkpoint = the spins in the canonical int8 form plus the sweep
+    index.  Restored into a fresh lattice, the chain continues bit for bit
+    as if it had never stopped: spins, and E and M after every sweep."""
+    say(f"checkpoint {layout} L={L} flags={flags}")
+    seed, n1, n2 = 13, 7, 11
+    a = _gpu_lattice(L, layout, seed, "random", flags)
+    Ea, Ma = a.sweep(BC, n1 + n2)
+    b = _gpu_lattice(L, layout, seed, "random", flags)
+    b.sweep(BC, n1, record=False)
+    ckpt_spins, ckpt_t = b.to_int8().cpu(), b.sweep_index
+    del b
+    c = _gpu_lattice(L, layout, seed, "cold", flags)  # fresh lattice, other start
+    c.from_int8(ckpt_spins)
+    c.set_sweep_index(ckpt_t)
+    Ec, Mc = c.sweep(BC, n2)
+    assert (_host(Ec) == _host(Ea)[n1:]).all() and (_host(Mc) == _host(Ma)[n1:]).all()
+    assert (_host(c.to_int8()) == _host(a.to_int8())).all()
+    assert c.sweep_index == n1 + n2
+    c.check()
+
+
+def _expected_plane_blocks(s, beta, seed, lid, t0, n):
+    """Philox blocks a bit-plane sweep must draw, counted from the oracle's
+    chain: a word (32 sites of one colour) needs blocks until each of its
+    sites with a draw is decided, i.e. ceil(d / 4) for the deepest site,
+    d being the position (from the most significant bit, counted from 1)
+    of the first bit where r and the site's threshold differ (32 if equal).
+    The oracle's own sweep advances the state."""
+    L = s.shape[0]
+    T, a = oracle.thresholds(beta)
+    yy, xx = np.indices((L, L))
+    group = ((yy * L + xx) >> 1) >> 5
+    total = 0
+    for t in range(t0, t0 + n):
+        for c in (0, 1):
+            r = oracle.fill_uniforms(L, PLANE, seed, lid, t, c)
+            h = (np.roll(s, 1, 0) + np.roll(s, -1, 0) + np.roll(s, 1, 1) +
+                 np.roll(s, -1, 1)).astype(np.int64)
+            u = s.astype(np.int64) * h
+            k = (u + 4) // 2
+            need = (((xx + yy) & 1) == c) & (u > 0) & (a[k] == 0)
+            x = (r ^ T[k]).astype(np.uint64)
+            depth = np.where(x == 0, 32,
+                             32 - np.floor(np.log2(np.maximum(x, 1).astype(np.float64))))
+            blocks = np.where(need, (depth.astype(np.int64) + 3) // 4, 0)
+            per_group = np.zeros(group.max() + 1, np.int64)
+            np.maximum.at(per_group, group.ravel(), blocks.ravel())
+            total += int(per_group.sum())
+            oracle.halfsweep(s, c, r, T, a)
+    return total
+
+
+@pytest.mark.parametrize("L,flags", [(256, 0), (4096, 0), (192, lib.FLAG_GLOBAL_HALFSWEEP)])
+def test_rng_block_count_equals_count_from_the_oracle(L, flags):
+    """ising_rng_blocks (the draw count behind the benchmark's ALU work)
+    equals the blocks the oracle's chain needs, word by word."""
+    say(f"rng blocks L={L} flags={flags}")
+    seed, n = 21, 3 if L > 1024 else 6
+    g = _gpu_lattice(L, "bit1", seed, "random", flags)
+    g.sweep(BC, n, record=False)
+    got = g.rng_blocks()
+    s = oracle.init(L, oracle.START_RANDOM, seed)
+    want = _expected_plane_blocks(s, BC, seed, 0, 0, n)
+    assert got == want
+    assert (_host(g.to_int8()) == s).all()
