@@ -151,6 +151,26 @@ ISING_API int ising_init(ising_lattice *lat, int32_t start, void *hip_stream);
 ISING_API int ising_sweep(ising_lattice *lat, double beta, int64_t n, int64_t *E_dev,
                 int64_t *M_dev, void *hip_stream);
 
+/* ising_sweep for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  It is ising_sweep (same kernels, same chain, same E_dev /
+ * M_dev contents) except that the kernels' workspace is a static device
+ * array of the library, 1 KiB + 4 MiB, one copy per GPU, held until the
+ * process ends; lat->workspace is not used and may be NULL.  The call
+ * allocates and frees nothing.  Limit: BIT1 lattices up to L = 8192
+ * (the halo slots of 1024 tiles); INT8 lattices of any valid L.
+ * status_dev (device uint32, may be NULL) receives 0, or the device error
+ * word of this call if an inter-tile wait timed out (spins then undefined).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or host threads) race and must not be made; the
+ * call clears what must start at zero, so successive calls are
+ * independent.  ising_rng_blocks does not count this call's draws.
+ * Errors: as ising_sweep (the workspace is not checked); a BIT1 lattice
+ * above L = 8192 -> ISING_E_UNSUPPORTED; status_dev misaligned ->
+ * ISING_E_INVALID; nothing is enqueued in these cases. */
+ISING_API int ising_sweep_noalloc(ising_lattice *lat, double beta, int64_t n, int64_t *E_dev,
+                                  int64_t *M_dev, uint32_t *status_dev, void *hip_stream);
+
 /* ising_sweep on a BIT1 lattice with the persistent tile kernel under a
  * given tile shape instead of the library's choice: the lattice is cut
  * into L / rows tiles of `rows` full-width rows, one workgroup of `waves`

@@ -18,6 +18,6 @@ from .binding import (  # noqa: F401
     ABI_VERSION, FLAG_GLOBAL_HALFSWEEP, LAYOUT_BIT1, LAYOUT_INT8, START_COLD_UP, START_RANDOM, IsingError, Lattice,
     ising_abi_version, ising_check_device_error, ising_from_int8, ising_init, ising_lattice,
     ising_last_error, ising_measure, ising_rng_blocks, ising_spins_bytes, ising_sweep,
-    ising_sweep_tiles, ising_thresholds,
+    ising_sweep_tiles, ising_sweep_noalloc, ising_thresholds,
     ising_to_int8, ising_workspace_bytes, load_library,
 )

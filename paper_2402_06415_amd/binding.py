@@ -30,7 +30,7 @@ FLAG_GLOBAL_HALFSWEEP = 1
 
 EXPORTED = (
     "ising_spins_bytes", "ising_workspace_bytes", "ising_abi_version", "ising_thresholds",
-    "ising_init", "ising_sweep", "ising_sweep_tiles", "ising_measure", "ising_to_int8", "ising_from_int8",
+    "ising_init", "ising_sweep", "ising_sweep_tiles", "ising_sweep_noalloc", "ising_measure", "ising_to_int8", "ising_from_int8",
     "ising_check_device_error", "ising_last_error", "ising_rng_blocks",
     "ising_batch_spins_bytes", "ising_batch_workspace_bytes", "ising_batch_setup",
     "ising_batch_init", "ising_batch_sweep", "ising_batch_measure", "ising_batch_sweep_index",
@@ -156,6 +156,8 @@ def load_library():
     lib.ising_sweep_tiles.argtypes = [lat_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.c_int32, vp, vp, vp]
     lib.ising_sweep_tiles.restype = ctypes.c_int
+    lib.ising_sweep_noalloc.argtypes = [lat_p, ctypes.c_double, ctypes.c_int64, vp, vp, vp, vp]
+    lib.ising_sweep_noalloc.restype = ctypes.c_int
     lib.ising_measure.argtypes = [lat_p, vp, vp, vp]
     lib.ising_measure.restype = ctypes.c_int
     lib.ising_to_int8.argtypes = [lat_p, vp, vp]
@@ -281,6 +283,13 @@ def ising_sweep_tiles(lat: ising_lattice, beta: float, n: int, rows: int, waves:
                       E_dev: int = 0, M_dev: int = 0, stream: int = 0):
     _check(load_library().ising_sweep_tiles(ctypes.byref(lat), float(beta), int(n), int(rows),
                                             int(waves), E_dev or None, M_dev or None, stream))
+
+
+def ising_sweep_noalloc(lat: ising_lattice, beta: float, n: int, E_dev: int = 0, M_dev: int = 0,
+                        status_dev: int = 0, stream: int = 0):
+    _check(load_library().ising_sweep_noalloc(ctypes.byref(lat), float(beta), int(n),
+                                              E_dev or None, M_dev or None, status_dev or None,
+                                              stream))
 
 
 def ising_measure(lat: ising_lattice, E_dev: int = 0, M_dev: int = 0, stream: int = 0):

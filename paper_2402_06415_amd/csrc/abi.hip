@@ -1,6 +1,8 @@
 // extern "C" entry points of libising.so (declared in include/ising.h):
 // argument validation, the host-side acceptance table, and dispatch of the
-// kernels on the caller's stream.  No device memory is allocated here.
+// kernels on the caller's stream.  No call allocates device memory; the
+// only library-held device memory is the static scratch array of
+// ising_sweep_noalloc.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -69,7 +71,7 @@ bool valid_shape(int32_t dim, int32_t L, int32_t layout) {
     return false;
 }
 
-int validate(const ising_lattice* lat) {
+int validate(const ising_lattice* lat, bool need_workspace = true) {
     if (!lat)
         return set_error(ISING_E_INVALID, "lattice pointer is NULL");
     if (lat->abi_version != ISING_ABI_VERSION)
@@ -88,7 +90,7 @@ int validate(const ising_lattice* lat) {
     if (!lat->spins || !aligned256(lat->spins))
         return set_error(ISING_E_INVALID, "spins must be a non-NULL 256-byte aligned device pointer");
     size_t ws = ising_workspace_bytes(lat->dim, lat->L, lat->layout);
-    if (ws && (!lat->workspace || !aligned256(lat->workspace)))
+    if (need_workspace && ws && (!lat->workspace || !aligned256(lat->workspace)))
         return set_error(ISING_E_INVALID,
                          "workspace must be a non-NULL 256-byte aligned device pointer");
     if (lat->sweep_index > (1ull << 31))
@@ -104,11 +106,46 @@ ising::Key key_of(const ising_lattice* lat) {
 unsigned char* ws_of(const ising_lattice* lat) {
     return reinterpret_cast<unsigned char*>(lat->workspace);
 }
-long long* ws_acc(const ising_lattice* lat) {
-    return reinterpret_cast<long long*>(ws_of(lat) + ising::WsLayout::kAcc);
+long long* ws_acc(unsigned char* ws) {
+    return reinterpret_cast<long long*>(ws + ising::WsLayout::kAcc);
 }
-unsigned long long* ws_blocks(const ising_lattice* lat) {
-    return reinterpret_cast<unsigned long long*>(ws_of(lat) + ising::WsLayout::kRngBlocks);
+unsigned long long* ws_blocks(unsigned char* ws) {
+    return reinterpret_cast<unsigned long long*>(ws + ising::WsLayout::kRngBlocks);
+}
+
+// Scratch of ising_sweep_noalloc: the workspace of one sweep call (the
+// header of accumulators, device error word and draw counters, then the
+// tagged halo slots of the tile kernel) as a static device array, so that
+// the call allocates nothing.  Each GPU the library runs on holds its own
+// copy until the process ends.  Its size bounds BIT1 lattices to
+// L <= kNoAllocMaxL (1024 tiles x 2 colours x 2 edge rows x L/64 words x
+// 8 bytes of halo slots); the other paths need only the header.
+constexpr int kNoAllocMaxL = 8192;
+constexpr size_t kScratchBytes =
+    ising::WsLayout::kHalo + (size_t)ising::WsLayout::kMaxTiles * 2 * 2 * (kNoAllocMaxL / 64) * 8;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the array's name is only a host-side stand-in).
+int scratch_of_current_device(unsigned char** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(ISING_E_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return set_error(ISING_E_HIP, "hipGetSymbolAddress(scratch) gave NULL");
+        g_scratch_dev[dev] = reinterpret_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return ISING_OK;
 }
 
 // Spin limit of the inter-tile waits (each spin sleeps ~64 clocks); a
@@ -117,9 +154,9 @@ constexpr uint32_t kSpinLimit = 1u << 24;
 
 // Zero acc[0..1] and recount E, M of the current spins into acc (raw
 // counts) then finish into E_out/M_out and copies.
-int measure_into(const ising_lattice* lat, long long* E_out, long long* M_out, long long* E_copy,
-                 long long* M_copy, hipStream_t st) {
-    long long* acc = ws_acc(lat);
+int measure_into(const ising_lattice* lat, unsigned char* ws, long long* E_out, long long* M_out,
+                 long long* E_copy, long long* M_copy, hipStream_t st) {
+    long long* acc = ws_acc(ws);
     HIP_TRY(ising::launch_fill_i64(acc, 2, 0, st), "fill");
     const long long N = (long long)lat->L * lat->L;
     if (lat->layout == ISING_LAYOUT_INT8) {
@@ -195,7 +232,8 @@ int ising_init(ising_lattice* lat, int32_t start, void* hip_stream) {
         return set_error(ISING_E_INVALID, "unknown start %d", start);
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     // clear the accumulators, the device error word and the draw counters
-    HIP_TRY(ising::launch_fill_i64(ws_acc(lat), ising::WsLayout::kClearBytes / 8, 0, st), "fill");
+    HIP_TRY(ising::launch_fill_i64(ws_acc(ws_of(lat)), ising::WsLayout::kClearBytes / 8, 0, st),
+            "fill");
     if (lat->layout == ISING_LAYOUT_INT8)
         HIP_TRY(ising::launch_init_int8(reinterpret_cast<int8_t*>(lat->spins), lat->L, start,
                                         key_of(lat), lat->lattice_id, st),
@@ -210,11 +248,16 @@ int ising_init(ising_lattice* lat, int32_t start, void* hip_stream) {
 
 // The sweep of ising_sweep and ising_sweep_tiles: `forced` (BIT1 only)
 // replaces the library's tile plan.
-static int sweep_impl(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev, int64_t* M_dev,
-                      void* hip_stream, const ising::Bit1TilePlan* forced) {
-    int rc = validate(lat);
+// The kernels use the lattice's workspace, or `scratch` when it is given
+// (the library's static scratch of ising_sweep_noalloc; lat->workspace is
+// then not used and may be NULL).
+static int sweep_impl(ising_lattice* lat, unsigned char* scratch, double beta, int64_t n,
+                      int64_t* E_dev, int64_t* M_dev, void* hip_stream,
+                      const ising::Bit1TilePlan* forced) {
+    int rc = validate(lat, scratch == nullptr);
     if (rc)
         return rc;
+    unsigned char* ws = scratch ? scratch : ws_of(lat);
     if (n < 0)
         return set_error(ISING_E_INVALID, "n = %lld < 0", (long long)n);
     if (lat->sweep_index + (uint64_t)n > (1ull << 31))
@@ -234,13 +277,13 @@ static int sweep_impl(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev
     long long* Etr = reinterpret_cast<long long*>(E_dev);
     long long* Mtr = reinterpret_cast<long long*>(M_dev);
     const bool trace = Etr || Mtr;
-    long long* acc_ws = ws_acc(lat);
+    long long* acc_ws = ws_acc(ws);
 
     const bool global_only = (lat->flags & ISING_FLAG_GLOBAL_HALFSWEEP) != 0;
     if (lat->layout == ISING_LAYOUT_INT8 && !global_only && ising::int8_resident_fits(L)) {
         HIP_TRY(ising::launch_sweep_int8_resident(reinterpret_cast<int8_t*>(lat->spins), L, n, t0,
                                                   key, lat->lattice_id, acc, E_dev, M_dev,
-                                                  ws_blocks(lat), st),
+                                                  ws_blocks(ws), st),
                 "sweep_int8_resident");
         lat->sweep_index += (uint64_t)n;
         return ISING_OK;
@@ -248,7 +291,7 @@ static int sweep_impl(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev
     // Multi-workgroup paths: per-sweep changes are accumulated into the
     // traces, then turned into running values from a recount at the start.
     if (trace) {
-        rc = measure_into(lat, nullptr, nullptr, acc_ws + 2, acc_ws + 3, st);
+        rc = measure_into(lat, ws, nullptr, nullptr, acc_ws + 2, acc_ws + 3, st);
         if (rc)
             return rc;
         if (Etr)
@@ -263,7 +306,7 @@ static int sweep_impl(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev
                 HIP_TRY(ising::launch_halfsweep_int8(s, L, c, 2u * (t0 + (uint32_t)j) + (uint32_t)c,
                                                      key, lat->lattice_id, acc,
                                                      Etr ? Etr + j : nullptr,
-                                                     Mtr ? Mtr + j : nullptr, ws_blocks(lat), st),
+                                                     Mtr ? Mtr + j : nullptr, ws_blocks(ws), st),
                         "halfsweep_int8");
     } else {
         uint32_t* planes = reinterpret_cast<uint32_t*>(lat->spins);
@@ -277,7 +320,7 @@ static int sweep_impl(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev
         }
         if (tiles) {
             HIP_TRY(ising::launch_sweep_bit1_tiles(planes, L, plan, n, t0, key, lat->lattice_id,
-                                                   acc, Etr, Mtr, ws_of(lat), kSpinLimit, st),
+                                                   acc, Etr, Mtr, ws, kSpinLimit, st),
                     "sweep_bit1_tiles");
         } else {
             for (int64_t j = 0; j < n; ++j)
@@ -285,7 +328,7 @@ static int sweep_impl(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev
                     HIP_TRY(ising::launch_halfsweep_bit1(
                                 planes, L, c, 2u * (t0 + (uint32_t)j) + (uint32_t)c, key,
                                 lat->lattice_id, acc, Etr ? Etr + j : nullptr,
-                                Mtr ? Mtr + j : nullptr, ws_blocks(lat), st),
+                                Mtr ? Mtr + j : nullptr, ws_blocks(ws), st),
                             "halfsweep_bit1");
         }
     }
@@ -299,7 +342,46 @@ static int sweep_impl(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev
 
 int ising_sweep(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev, int64_t* M_dev,
                 void* hip_stream) {
-    return sweep_impl(lat, beta, n, E_dev, M_dev, hip_stream, nullptr);
+    return sweep_impl(lat, nullptr, beta, n, E_dev, M_dev, hip_stream, nullptr);
+}
+
+int ising_sweep_noalloc(ising_lattice* lat, double beta, int64_t n, int64_t* E_dev,
+                        int64_t* M_dev, uint32_t* status_dev, void* hip_stream) {
+    int rc = validate(lat, false);
+    if (rc)
+        return rc;
+    if (lat->layout == ISING_LAYOUT_BIT1 && lat->L > kNoAllocMaxL)
+        return set_error(ISING_E_UNSUPPORTED,
+                         "ising_sweep_noalloc: BIT1 L = %d exceeds the scratch limit L <= %d "
+                         "(%zu bytes); use ising_sweep with a workspace",
+                         lat->L, kNoAllocMaxL, kScratchBytes);
+    if (status_dev && (reinterpret_cast<uintptr_t>(status_dev) & 3u))
+        return set_error(ISING_E_INVALID, "status_dev must be 4-byte aligned");
+    if (n < 0)
+        return set_error(ISING_E_INVALID, "n = %lld < 0", (long long)n);
+    if (lat->sweep_index + (uint64_t)n > (1ull << 31))
+        return set_error(ISING_E_INVALID, "sweep_index + n exceeds 2^31");
+    uint32_t T[5];
+    uint8_t alw[5];
+    rc = ising_thresholds(beta, T, alw);
+    if (rc)
+        return rc;
+    unsigned char* ws = nullptr;
+    rc = scratch_of_current_device(&ws);
+    if (rc)
+        return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    // the array keeps the last call's contents: clear the accumulators, the
+    // error word and the draw counters (the tile kernel clears its halo)
+    HIP_TRY(ising::launch_fill_i64(ws_acc(ws), ising::WsLayout::kClearBytes / 8, 0, st), "fill");
+    rc = sweep_impl(lat, ws, beta, n, E_dev, M_dev, hip_stream, nullptr);
+    if (rc)
+        return rc;
+    if (status_dev)
+        HIP_TRY(ising::launch_copy_u32(reinterpret_cast<const uint32_t*>(ws + ising::WsLayout::kErr),
+                                       status_dev, st),
+                "copy status");
+    return ISING_OK;
 }
 
 int ising_sweep_tiles(ising_lattice* lat, double beta, int64_t n, int32_t rows, int32_t waves,
@@ -330,14 +412,14 @@ int ising_sweep_tiles(ising_lattice* lat, double beta, int64_t n, int32_t rows, 
         return set_error(ISING_E_UNSUPPORTED,
                          "%d tiles of %d rows x %d waves: only %d fit the device at once",
                          plan.ntiles, rows, waves, resident);
-    return sweep_impl(lat, beta, n, E_dev, M_dev, hip_stream, &plan);
+    return sweep_impl(lat, nullptr, beta, n, E_dev, M_dev, hip_stream, &plan);
 }
 
 int ising_measure(const ising_lattice* lat, int64_t* E_dev, int64_t* M_dev, void* hip_stream) {
     int rc = validate(lat);
     if (rc)
         return rc;
-    return measure_into(lat, reinterpret_cast<long long*>(E_dev),
+    return measure_into(lat, ws_of(lat), reinterpret_cast<long long*>(E_dev),
                         reinterpret_cast<long long*>(M_dev), nullptr, nullptr,
                         reinterpret_cast<hipStream_t>(hip_stream));
 }
@@ -386,7 +468,7 @@ int ising_rng_blocks(const ising_lattice* lat, uint64_t* blocks_host, void* hip_
         return set_error(ISING_E_INVALID, "blocks_host is NULL");
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     uint64_t v[ising::WsLayout::kRngSlots] = {};
-    HIP_TRY(hipMemcpyAsync(v, ws_blocks(lat), sizeof v, hipMemcpyDeviceToHost, st),
+    HIP_TRY(hipMemcpyAsync(v, ws_blocks(ws_of(lat)), sizeof v, hipMemcpyDeviceToHost, st),
             "read block counters");
     HIP_TRY(hipStreamSynchronize(st), "synchronise");
     uint64_t total = 0;

@@ -324,6 +324,11 @@ __global__ void k_fill_i64(long long* p, int64_t n, long long v) {
         p[i] = v;
 }
 
+__global__ void k_copy_u32(const uint32_t* src, uint32_t* dst) {
+    if (threadIdx.x == 0)
+        *dst = *src;
+}
+
 // Single-workgroup inclusive scan: out[j] = base + sum_{i<=j} d[i].
 __global__ void __launch_bounds__(1024) k_prefix_i64(long long* d, int64_t n,
                                                      const long long* base) {
@@ -438,6 +443,11 @@ hipError_t launch_fill_i64(long long* p, int64_t n, long long v, hipStream_t st)
     if (n <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_fill_i64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, st, src, dst);
     return hipGetLastError();
 }
 

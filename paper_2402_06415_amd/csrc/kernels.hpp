@@ -65,6 +65,8 @@ hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& 
 
 // Shared small kernels ------------------------------------------------------
 hipError_t launch_fill_i64(long long* p, int64_t n, long long v, hipStream_t st);
+// *dst = *src (one word, device to device) as a kernel.
+hipError_t launch_copy_u32(const uint32_t* src, uint32_t* dst, hipStream_t st);
 // out[j] = base + sum_{i<=j} d[i] in place (d == out allowed); base read
 // from device memory.
 hipError_t launch_prefix_i64(long long* d, int64_t n, const long long* base, hipStream_t st);
