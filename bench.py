@@ -776,9 +776,16 @@ def main():
     torch.cuda.synchronize()
     total_ms = ev[0].elapsed_time(ev[1])
     sweep_ms = sum(a.elapsed_time(b) for a, b in sw_ev) / args.steps
-    blocks = lat.rng_blocks()      # Philox blocks of the last step (init resets the counter)
     lat.check()
     E, M = (int(v) for v in out.cpu().tolist())
+    # Philox blocks of one step, outside the timed region: the same chain on a
+    # lattice that counts its draws (the timed kernels do not count)
+    counted = lib.Lattice(L, layout, seed=args.seed, start="random", device=dev,
+                          flags=flags | lib.FLAG_COUNT_DRAWS)
+    counted.sweep(BETA, nsw, record=False)
+    blocks = counted.rng_blocks()
+    assert tuple(int(v) for v in counted.measure().cpu().tolist()) == (E, M)
+    del counted
 
     ms_per_step = total_ms / args.steps
     attempts = L * L * nsw

@@ -76,7 +76,11 @@ enum ising_flags {
     /* one launch per half-sweep reading the spins from global memory,
      * instead of the resident single-workgroup (INT8, L <= 128) or the
      * persistent tile-resident (BIT1) kernel */
-    ISING_FLAG_GLOBAL_HALFSWEEP = 1u
+    ISING_FLAG_GLOBAL_HALFSWEEP = 1u,
+    /* BIT1: count the Philox blocks the sweeps draw (ising_rng_blocks), a
+     * diagnostic that costs a few instructions per word; without it the
+     * BIT1 kernels do not count.  The INT8 kernels always count. */
+    ISING_FLAG_COUNT_DRAWS = 2u
 };
 enum ising_status {
     ISING_OK = 0,
@@ -208,7 +212,9 @@ ISING_API int ising_from_int8(ising_lattice *lat, const int8_t *in_dev, void *hi
 /* Read back (synchronising hip_stream) how many Philox4x32-10 blocks
  * (128 random bits each) the sweeps on this lattice have drawn since the
  * last ising_init: the random-number work the method actually consumed,
- * which sets the integer-ALU cost of a sweep.  Diagnostic only. */
+ * which sets the integer-ALU cost of a sweep.  A BIT1 lattice counts only
+ * the sweeps run with ISING_FLAG_COUNT_DRAWS; a block counts when some site
+ * of its 32-site word was still undecided before it.  Diagnostic only. */
 ISING_API int ising_rng_blocks(const ising_lattice *lat, uint64_t *blocks_host,
                                void *hip_stream);
 

@@ -15,7 +15,7 @@ from .binding import (  # noqa: F401
     ising_ea_state, ising_ea_check_device_error, ising_ea_rng_blocks, XYLattices, ising_xy,
     ising_xy_workspace_bytes, ising_xy_init, ising_xy_sweep, ising_xy_energy, ising_xy_state,
     ising_xy_check_device_error,
-    ABI_VERSION, FLAG_GLOBAL_HALFSWEEP, LAYOUT_BIT1, LAYOUT_INT8, START_COLD_UP, START_RANDOM, IsingError, Lattice,
+    ABI_VERSION, FLAG_COUNT_DRAWS, FLAG_GLOBAL_HALFSWEEP, LAYOUT_BIT1, LAYOUT_INT8, START_COLD_UP, START_RANDOM, IsingError, Lattice,
     ising_abi_version, ising_check_device_error, ising_from_int8, ising_init, ising_lattice,
     ising_last_error, ising_measure, ising_rng_blocks, ising_spins_bytes, ising_sweep,
     ising_sweep_tiles, ising_sweep_noalloc, ising_thresholds,

@@ -27,6 +27,7 @@ START_COLD_UP = 0
 START_RANDOM = 1
 OK, E_INVALID, E_UNSUPPORTED, E_HIP, E_STATE = 0, 1, 2, 3, 4
 FLAG_GLOBAL_HALFSWEEP = 1
+FLAG_COUNT_DRAWS = 2
 
 EXPORTED = (
     "ising_spins_bytes", "ising_workspace_bytes", "ising_abi_version", "ising_thresholds",

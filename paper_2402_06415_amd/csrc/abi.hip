@@ -85,7 +85,7 @@ int validate(const ising_lattice* lat, bool need_workspace = true) {
         return set_error(ISING_E_INVALID,
                          "L = %d invalid for layout %d (even, 4..65536; BIT1 needs L %% 64 == 0)",
                          lat->L, lat->layout);
-    if (lat->flags & ~(uint32_t)ISING_FLAG_GLOBAL_HALFSWEEP)
+    if (lat->flags & ~(uint32_t)(ISING_FLAG_GLOBAL_HALFSWEEP | ISING_FLAG_COUNT_DRAWS))
         return set_error(ISING_E_INVALID, "unknown flag bits 0x%x", lat->flags);
     if (!lat->spins || !aligned256(lat->spins))
         return set_error(ISING_E_INVALID, "spins must be a non-NULL 256-byte aligned device pointer");
@@ -280,6 +280,8 @@ static int sweep_impl(ising_lattice* lat, unsigned char* scratch, double beta, i
     long long* acc_ws = ws_acc(ws);
 
     const bool global_only = (lat->flags & ISING_FLAG_GLOBAL_HALFSWEEP) != 0;
+    // the no-alloc scratch's counters are cleared per call: nothing counts there
+    const bool count = (lat->flags & ISING_FLAG_COUNT_DRAWS) != 0 && !scratch;
     if (lat->layout == ISING_LAYOUT_INT8 && !global_only && ising::int8_resident_fits(L)) {
         HIP_TRY(ising::launch_sweep_int8_resident(reinterpret_cast<int8_t*>(lat->spins), L, n, t0,
                                                   key, lat->lattice_id, acc, E_dev, M_dev,
@@ -320,7 +322,7 @@ static int sweep_impl(ising_lattice* lat, unsigned char* scratch, double beta, i
         }
         if (tiles) {
             HIP_TRY(ising::launch_sweep_bit1_tiles(planes, L, plan, n, t0, key, lat->lattice_id,
-                                                   acc, Etr, Mtr, ws, kSpinLimit, st),
+                                                   acc, Etr, Mtr, ws, kSpinLimit, count, st),
                     "sweep_bit1_tiles");
         } else {
             for (int64_t j = 0; j < n; ++j)
@@ -328,7 +330,7 @@ static int sweep_impl(ising_lattice* lat, unsigned char* scratch, double beta, i
                     HIP_TRY(ising::launch_halfsweep_bit1(
                                 planes, L, c, 2u * (t0 + (uint32_t)j) + (uint32_t)c, key,
                                 lat->lattice_id, acc, Etr ? Etr + j : nullptr,
-                                Mtr ? Mtr + j : nullptr, ws_blocks(ws), st),
+                                Mtr ? Mtr + j : nullptr, ws_blocks(ws), count, st),
                             "halfsweep_bit1");
         }
     }
@@ -407,7 +409,13 @@ int ising_sweep_tiles(ising_lattice* lat, double beta, int64_t n, int32_t rows, 
     if (plan.lds > (size_t)64 * 1024)
         return set_error(ISING_E_UNSUPPORTED, "a tile of %d rows needs %zu bytes of LDS (> 64 KiB)",
                          rows, plan.lds);
-    const int resident = ising::bit1_tiles_resident(L, plan);
+    uint32_t T[5];
+    uint8_t alw[5];
+    rc = ising_thresholds(beta, T, alw);
+    if (rc)
+        return rc;
+    const int resident = ising::bit1_tiles_resident(
+        L, plan, E_dev || M_dev, alw[3] || alw[4], (lat->flags & ISING_FLAG_COUNT_DRAWS) != 0);
     if (resident < plan.ntiles)
         return set_error(ISING_E_UNSUPPORTED,
                          "%d tiles of %d rows x %d waves: only %d fit the device at once",

@@ -97,16 +97,18 @@ __device__ __forceinline__ void add_count(unsigned long long v, unsigned long lo
     }
 }
 
-// One half-sweep over the whole lattice, one word per thread, from global
-// memory (any L % 64 == 0).
+// One half-sweep over the whole lattice from global memory (any
+// L % 64 == 0): a grid-stride loop over the words of colour c, so that the
+// Philox round keys and threshold masks are set up once per thread; the
+// five loads of a word are issued together and its straight-line Philox
+// blocks computed while they are in flight.  L <= 65536 keeps every word
+// index within 32 bits.
+template <bool kGeneral, bool kCount>
 __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L, int c,
                                                         uint32_t h, Key key, uint32_t lid,
                                                         Accept acc, long long* dEo,
                                                         long long* dMo,
                                                         unsigned long long* nblk_out) {
-    // a grid-stride loop over the words of colour c, so that the Philox
-    // round keys and threshold masks are set up once per thread; L <= 65536
-    // keeps every word index within 32 bits
     const int nw = L >> 6;
     const uint32_t plane = (uint32_t)L * (uint32_t)nw;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -115,6 +117,11 @@ __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L,
     unsigned long long nblk = 0;
     if (i < plane) {
         const DrawConstsT<kStraightBlocks> dc = draw_consts<kStraightBlocks>(key, acc);
+        uint32_t tag[kStraightBlocks];
+#pragma unroll
+        for (int b = 0; b < kStraightBlocks; ++b)
+            tag[b] = plane_tag((uint32_t)b, dc.rk);
+        const PlaneHalf ph = plane_half(dc.rk, lid, h);
         uint32_t* P = planes + (size_t)c * plane;
         const uint32_t* Q = planes + (size_t)(1 - c) * plane;
         int y = (int)(i / (uint32_t)nw), w = (int)(i - (uint32_t)y * (uint32_t)nw);
@@ -125,16 +132,33 @@ __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L,
             const int wp = (w + 1 == nw) ? 0 : w + 1;
             const int ym = (y == 0) ? L - 1 : y - 1;
             const int yp = (y + 1 == L) ? 0 : y + 1;
-            // the five loads of the word together, one round trip to memory
             const int p = (y + c) & 1;  // 0: the side word is the left one
             const uint32_t W = P[row + w];
             const uint32_t O = Q[row + w];
             const uint32_t X = Q[row + (p == 0 ? wm : wp)];
             const uint32_t U = Q[(uint32_t)ym * (uint32_t)nw + w];
             const uint32_t D = Q[(uint32_t)yp * (uint32_t)nw + w];
-            const uint32_t S = side_word(O, X, X, p);
-            P[row + w] = update_word<true, kStraightBlocks>(W, O, S, U, D, row + (uint32_t)w, h,
-                                                            lid, acc, dc, dE, dM, nblk);
+            const PlaneGroup pg = plane_group(row + (uint32_t)w, ph);
+            U4 blk[kStraightBlocks];
+#pragma unroll
+            for (int b = 0; b < kStraightBlocks; ++b)
+                blk[b] = plane_block(pg, tag[b], ph, dc.rk);
+            const uint32_t S = p ? __builtin_amdgcn_alignbit(X, O, 1)
+                                 : __builtin_amdgcn_alignbit(O, X, 31);
+            WordState st = kGeneral ? classify(W, O, S, U, D, acc) : classify_draw(W, O, S, U, D);
+#pragma unroll
+            for (int b = 0; b < kStraightBlocks; ++b) {
+                if (kCount)
+                    nblk += st.und ? 1u : 0u;
+                compare_block<kStraightBlocks>(st, blk[b], b, dc);
+            }
+            for (uint32_t b = kStraightBlocks; b < 8u && st.und; ++b) {
+                if (kCount)
+                    ++nblk;
+                compare_block_uniform(st, plane_block(pg, plane_tag(b, dc.rk), ph, dc.rk), b,
+                                      acc);
+            }
+            P[row + w] = finalize<true>(st, dE, dM);
             w += sx;
             y += sy;
             if (w >= nw) {
@@ -143,7 +167,8 @@ __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L,
             }
         }
     }
-    add_count(nblk, nblk_out);
+    if (kCount)
+        add_count(nblk, nblk_out);
     if (dEo || dMo)
         block_add_i64(dE, dM, dEo, dMo);
 }
@@ -318,51 +343,141 @@ __device__ __forceinline__ void store_tile(uint32_t* planes, const uint32_t* til
                     tile[(col * t.tr + r + 1) * t.nw + w];
 }
 
-// Update row r of colour c of the tile: one word per lane, 64-word chunks.
-// Rows 0 and rows-1 publish their new words for the neighbouring tiles;
-// with kLate they first take the neighbours' facing rows from the slots
-// (after the first half-sweep), otherwise from the tile's halo rows.
-template <bool kObs, bool kLate>
-__device__ __forceinline__ void update_row(uint32_t* tile, const TileGeom& t, int rows, int r,
-                                           int64_t hs, uint32_t t0, uint32_t lid,
-                                           const Accept& acc,
-                                           const DrawConstsT<kStraightBlocks>& dc,
-                                           unsigned long long* halo, uint32_t* err,
+// The rest of a wait whose first load was issued early: poll the slot until
+// its tag is the one expected (bounded; on time-out the device error word is
+// set and the word read last is used).
+__device__ __forceinline__ uint32_t finish_wait(unsigned long long v,
+                                                const unsigned long long* slot, uint32_t tag,
+                                                uint32_t limit, uint32_t* err) {
+    uint32_t spins = 0;
+    while ((uint32_t)(v >> 32) != tag) {
+        if (++spins > limit) {
+            atomicOr(err, 1u);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return (uint32_t)v;
+}
+
+// Keeps a block's words where they are computed: the compiler may not sink
+// the Philox rounds below this point (towards their first use, past the
+// waits for the loads they are meant to hide).
+__device__ __forceinline__ void pin(U4& v) {
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+}
+
+// Per-thread constants of the tile sweep's draws: round keys and threshold
+// masks of the straight-line blocks, and the tag words of those blocks.
+struct TileDraws {
+    DrawConstsT<kStraightBlocks> dc;
+    uint32_t tag[kStraightBlocks];
+};
+
+// One row of one colour in a half-sweep, as the word loop sees it; every
+// field is uniform in the wave.
+struct RowCtx {
+    uint32_t* Wr;                    // the row being updated (colour c)
+    const uint32_t *Or, *Ur, *Dr;    // colour 1-c: same row, rows above and below
+    const unsigned long long *su, *sd;  // halo slots of the rows above / below
+    unsigned long long *pub_first, *pub_last;  // slots this row publishes (or NULL)
+    uint32_t g0;                     // draw group of word 0: y * nw
+    uint32_t tag_in, tag_out;        // hs (slots written by hs - 1), hs + 1
+    int p;                           // 0: side neighbour left, 1: right
+    bool wait_u, wait_d;             // rows above / below from the slots
+};
+
+// Update the words of one row: one word per lane, 64-word chunks.  The
+// Philox blocks of a word do not depend on the spins, so they are computed
+// between issuing the word's loads and using them: the LDS and halo-slot
+// latencies hide behind them.  kGeneral: the thresholds may have
+// always-flip classes (beta near 0); kCount: count the blocks drawn.
+template <bool kObs, bool kGeneral, bool kCount>
+__device__ __forceinline__ void update_row(const RowCtx& rc, int nw, const PlaneHalf& ph,
+                                           const Accept& acc, const TileDraws& td, uint32_t* err,
                                            uint32_t spin_limit, int& dE, int& dM,
                                            unsigned long long& nblk) {
+    for (int w = (int)(threadIdx.x & 63); w < nw; w += 64) {
+        const int wx = rc.p ? ((w + 1 == nw) ? 0 : w + 1) : ((w == 0) ? nw - 1 : w - 1);
+        const uint32_t W = rc.Wr[w];
+        const uint32_t O = rc.Or[w];
+        const uint32_t X = rc.Or[wx];
+        uint32_t U = 0, D = 0;
+        unsigned long long su = 0, sd = 0;
+        if (rc.wait_u)
+            su = __hip_atomic_load(rc.su + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            U = rc.Ur[w];
+        if (rc.wait_d)
+            sd = __hip_atomic_load(rc.sd + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            D = rc.Dr[w];
+        const PlaneGroup pg = plane_group(rc.g0 + (uint32_t)w, ph);
+        U4 blk[kStraightBlocks];
+#pragma unroll
+        for (int b = 0; b < kStraightBlocks; ++b) {
+            blk[b] = plane_block(pg, td.tag[b], ph, td.dc.rk);
+            pin(blk[b]);
+        }
+        // nothing that waits on the loads moves above the draws
+        __builtin_amdgcn_sched_barrier(0);
+        if (rc.wait_u)
+            U = finish_wait(su, rc.su + w, rc.tag_in, spin_limit, err);
+        if (rc.wait_d)
+            D = finish_wait(sd, rc.sd + w, rc.tag_in, spin_limit, err);
+        // side neighbour: compact column i - 1 (p == 0: the funnel shift
+        // O:X >> 31) or i + 1 (p == 1: X:O >> 1)
+        const uint32_t S = __builtin_amdgcn_alignbit(rc.p ? X : O, rc.p ? O : X, rc.p ? 1u : 31u);
+        WordState st = kGeneral ? classify(W, O, S, U, D, acc) : classify_draw(W, O, S, U, D);
+#pragma unroll
+        for (int b = 0; b < kStraightBlocks; ++b) {
+            if (kCount)
+                nblk += st.und ? 1u : 0u;
+            compare_block<kStraightBlocks>(st, blk[b], b, td.dc);
+        }
+        for (uint32_t b = kStraightBlocks; b < 8u && st.und; ++b) {
+            if (kCount)
+                ++nblk;
+            compare_block_uniform(st, plane_block(pg, plane_tag(b, td.dc.rk), ph, td.dc.rk), b,
+                                  acc);
+        }
+        const uint32_t nwd = finalize<kObs>(st, dE, dM);
+        rc.Wr[w] = nwd;
+        if (rc.pub_first)
+            publish_slot(rc.pub_first + w, rc.tag_out, nwd);
+        if (rc.pub_last)
+            publish_slot(rc.pub_last + w, rc.tag_out, nwd);
+    }
+}
+
+// The context of row r (0 <= r < rows) of the tile in half-sweep hs.  late:
+// the first and last rows take the neighbour rows from the slots (after the
+// first half-sweep) instead of the tile's halo rows.
+__device__ __forceinline__ RowCtx row_ctx(uint32_t* tile, const TileGeom& t, int rows, int r,
+                                          int64_t hs, bool late, unsigned long long* halo) {
     const int c = (int)(hs & 1), o = c ^ 1;
     const int nw = t.nw;
-    const uint32_t h = 2u * t0 + (uint32_t)hs;
-    const uint32_t tag_in = (uint32_t)hs;        // written at half-sweep hs - 1
-    const uint32_t tag_out = (uint32_t)hs + 1u;  // written now
     uint32_t* Tc = tile + c * t.tr * nw;
     const uint32_t* To = tile + o * t.tr * nw;
     const bool first = (r == 0), last = (r == rows - 1);
-    const bool wait = kLate && hs > 0;
     const int y = t.y0 + r;
-    for (int w = (int)(threadIdx.x & 63); w < nw; w += 64) {
-        const int wm = (w == 0) ? nw - 1 : w - 1;
-        const int wp = (w + 1 == nw) ? 0 : w + 1;
-        const uint32_t* Orow = To + (r + 1) * nw;
-        const uint32_t W = Tc[(r + 1) * nw + w];
-        const uint32_t O = Orow[w];
-        const uint32_t S = side_word(O, Orow[wm], Orow[wp], (y + c) & 1);
-        const uint32_t U = (wait && first)
-                               ? wait_slot(halo_row(halo, nw, t.up, o, 1) + w, tag_in, spin_limit, err)
-                               : To[r * nw + w];
-        const uint32_t D = (wait && last)
-                               ? wait_slot(halo_row(halo, nw, t.down, o, 0) + w, tag_in, spin_limit, err)
-                               : To[(r + 2) * nw + w];
-        WordState st = classify(W, O, S, U, D, acc);
-        draw_planes<true, kStraightBlocks>(st, (uint32_t)((int64_t)y * nw + w), h, lid, acc, dc,
-                                           nblk);
-        const uint32_t nwd = finalize<kObs>(st, dE, dM);
-        Tc[(r + 1) * nw + w] = nwd;
-        if (first)
-            publish_slot(halo_row(halo, nw, t.me, c, 0) + w, tag_out, nwd);
-        if (last)
-            publish_slot(halo_row(halo, nw, t.me, c, 1) + w, tag_out, nwd);
-    }
+    RowCtx rc;
+    rc.Wr = Tc + (r + 1) * nw;
+    rc.Or = To + (r + 1) * nw;
+    rc.Ur = To + r * nw;
+    rc.Dr = To + (r + 2) * nw;
+    rc.su = halo_row(halo, nw, t.up, o, 1);
+    rc.sd = halo_row(halo, nw, t.down, o, 0);
+    rc.pub_first = first ? halo_row(halo, nw, t.me, c, 0) : nullptr;
+    rc.pub_last = last ? halo_row(halo, nw, t.me, c, 1) : nullptr;
+    rc.g0 = (uint32_t)y * (uint32_t)nw;
+    rc.tag_in = (uint32_t)hs;
+    rc.tag_out = (uint32_t)hs + 1u;
+    rc.p = (y + c) & 1;
+    rc.wait_u = late && hs > 0 && first;
+    rc.wait_d = late && hs > 0 && last;
+    return rc;
 }
 
 // Receive the facing row of colour c that a neighbouring tile published in
@@ -382,10 +497,87 @@ __device__ __forceinline__ int row_of(int k, int rows) {
     return (rows <= 2 || k == 0) ? k : (k == 1 ? rows - 1 : k - 1);
 }
 
-// All rows of a half-sweep complete before the next starts (one workgroup
-// barrier per half-sweep); with kObs the workgroup also sums the energy and
-// magnetisation changes of each sweep into the traces.
-template <bool kObs, bool kLate>
+// Sums the per-sweep energy and magnetisation changes of the workgroup
+// into the traces; every thread of the workgroup takes part, after the
+// half-sweep's barrier (red is free again by then).
+__device__ __forceinline__ void trace_add(long long sE, long long sM, long long (*red)[16],
+                                          int wave, int lane, int nwaves, int64_t j,
+                                          long long* dEtr, long long* dMtr) {
+    const long long e = wave_sum_i64(sE), m = wave_sum_i64(sM);
+    if (lane == 0) {
+        red[0][wave] = e;
+        red[1][wave] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long E = 0, M = 0;
+        for (int v = 0; v < nwaves; ++v) {
+            E += red[0][v];
+            M += red[1][v];
+        }
+        if (dEtr && E)
+            atomicAdd(reinterpret_cast<unsigned long long*>(dEtr + j), (unsigned long long)E);
+        if (dMtr && M)
+            atomicAdd(reinterpret_cast<unsigned long long*>(dMtr + j), (unsigned long long)M);
+    }
+}
+
+// One wave per row (rows == waves of the workgroup): wave v owns row
+// row_of(v) for the whole call, so the edge rows (waves 0 and 1) keep a
+// raised priority throughout, and the row's geometry is set up once.  The
+// edge waves take the neighbours' facing rows from the slots when they next
+// need them (late receipt), the interior rows proceed meanwhile; one
+// workgroup barrier per half-sweep.
+template <bool kObs, bool kGeneral, bool kCount>
+__global__ void __launch_bounds__(1024) k_sweep_bit1_rows(
+    uint32_t* planes, int L, int rows, int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
+    long long* dEtr, long long* dMtr, unsigned long long* halo, uint32_t* err,
+    unsigned long long* nblk_out, uint32_t spin_limit) {
+    extern __shared__ uint32_t tile[];  // [2][rows + 2][nw]
+    __shared__ long long red[2][16];
+    const TileGeom t = tile_geom(L, rows);
+    const int nwaves = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int r = row_of(wave, rows);
+    TileDraws td;
+    td.dc = draw_consts<kStraightBlocks>(key, acc);
+#pragma unroll
+    for (int b = 0; b < kStraightBlocks; ++b)
+        td.tag[b] = plane_tag((uint32_t)b, td.dc.rk);
+    load_tile(tile, planes, L, rows, t);
+    __syncthreads();
+    if (r == 0 || r == rows - 1)
+        __builtin_amdgcn_s_setprio(3);  // the neighbouring tiles wait for these rows
+    long long sE = 0, sM = 0;
+    unsigned long long nblk = 0;
+    for (int64_t hs = 0; hs < 2 * n; ++hs) {
+        int dE = 0, dM = 0;
+        const PlaneHalf ph = plane_half(td.dc.rk, lid, 2u * t0 + (uint32_t)hs);
+        const RowCtx rc = row_ctx(tile, t, rows, r, hs, true, halo);
+        update_row<kObs, kGeneral, kCount>(rc, t.nw, ph, acc, td, err, spin_limit, dE, dM, nblk);
+        __syncthreads();
+        if (kObs) {
+            sE += dE;
+            sM += dM;
+            if (hs & 1) {
+                trace_add(sE, sM, red, wave, lane, nwaves, hs >> 1, dEtr, dMtr);
+                sE = sM = 0;
+            }
+        }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    if (kCount)
+        add_count(nblk, nblk_out);
+    store_tile(planes, tile, rows, t, wave, nwaves);
+}
+
+// Several rows per wave: all rows of a half-sweep complete before the next
+// starts (one workgroup barrier per half-sweep); the edge rows come first
+// in each half-sweep at raised priority, and the waves holding them take in
+// the neighbours' facing rows into the tile's halo rows before the barrier,
+// behind the interior rows.
+template <bool kObs, bool kGeneral, bool kCount>
 __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
     uint32_t* planes, int L, int rows, int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
     long long* dEtr, long long* dMtr, unsigned long long* halo, uint32_t* err,
@@ -394,28 +586,35 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
     __shared__ long long red[2][16];
     const TileGeom t = tile_geom(L, rows);
     const int nwaves = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const DrawConstsT<kStraightBlocks> dc = draw_consts<kStraightBlocks>(key, acc);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    TileDraws td;
+    td.dc = draw_consts<kStraightBlocks>(key, acc);
+#pragma unroll
+    for (int b = 0; b < kStraightBlocks; ++b)
+        td.tag[b] = plane_tag((uint32_t)b, td.dc.rk);
     load_tile(tile, planes, L, rows, t);
     __syncthreads();
     long long sE = 0, sM = 0;
     unsigned long long nblk = 0;
     for (int64_t hs = 0; hs < 2 * n; ++hs) {
         int dE = 0, dM = 0;
+        const PlaneHalf ph = plane_half(td.dc.rk, lid, 2u * t0 + (uint32_t)hs);
         for (int k = wave; k < rows; k += nwaves) {
             const int r = row_of(k, rows);
             const bool edge = (r == 0) || (r == rows - 1);
             if (edge)
                 __builtin_amdgcn_s_setprio(3);
-            update_row<kObs, kLate>(tile, t, rows, r, hs, t0, lid, acc, dc, halo, err, spin_limit,
-                                    dE, dM, nblk);
+            const RowCtx rc = row_ctx(tile, t, rows, r, hs, false, halo);
+            update_row<kObs, kGeneral, kCount>(rc, t.nw, ph, acc, td, err, spin_limit, dE, dM,
+                                               nblk);
             if (edge)
                 __builtin_amdgcn_s_setprio(0);
         }
-        // with several rows per wave, the waves of the first and last row
-        // take in the neighbours' rows of this colour for the next
-        // half-sweep (row_of: k = 0 is the first row, k = 1 the last)
-        if (!kLate && hs + 1 < 2 * n) {
+        // the waves of the first and last row take in the neighbours' rows
+        // of this colour for the next half-sweep (row_of: k = 0 is the
+        // first row, k = 1 the last)
+        if (hs + 1 < 2 * n) {
             const int c = (int)(hs & 1);
             const uint32_t tag = (uint32_t)hs + 1u;
             if (wave == 0)
@@ -424,32 +623,18 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_tiles(
                 receive_row(tile, t, c, rows + 1, halo_row(halo, t.nw, t.down, c, 0), tag,
                             spin_limit, err);
         }
-        sE += dE;
-        sM += dM;
-        if (kObs && (hs & 1)) {
-            long long e = wave_sum_i64(sE), m = wave_sum_i64(sM);
-            if (lane == 0) {
-                red[0][wave] = e;
-                red[1][wave] = m;
-            }
-            sE = 0;
-            sM = 0;
-        }
         __syncthreads();
-        if (kObs && (hs & 1) && threadIdx.x == 0) {
-            long long e = 0, m = 0;
-            for (int v = 0; v < nwaves; ++v) {
-                e += red[0][v];
-                m += red[1][v];
+        if (kObs) {
+            sE += dE;
+            sM += dM;
+            if (hs & 1) {
+                trace_add(sE, sM, red, wave, lane, nwaves, hs >> 1, dEtr, dMtr);
+                sE = sM = 0;
             }
-            const int64_t j = hs >> 1;
-            if (dEtr && e)
-                atomicAdd(reinterpret_cast<unsigned long long*>(dEtr + j), (unsigned long long)e);
-            if (dMtr && m)
-                atomicAdd(reinterpret_cast<unsigned long long*>(dMtr + j), (unsigned long long)m);
         }
     }
-    add_count(nblk, nblk_out);
+    if (kCount)
+        add_count(nblk, nblk_out);
     store_tile(planes, tile, rows, t, wave, nwaves);
 }
 
@@ -469,14 +654,17 @@ hipError_t launch_init_bit1(uint32_t* planes, int L, int start, Key key, uint32_
 
 hipError_t launch_halfsweep_bit1(uint32_t* planes, int L, int c, uint32_t h, Key key,
                                  uint32_t lid, Accept acc, long long* dE, long long* dM,
-                                 unsigned long long* nblk, hipStream_t st) {
+                                 unsigned long long* nblk, bool count, hipStream_t st) {
     // at most 4096 workgroups: a thread takes up to 64 words at L = 65536
     int64_t words = (int64_t)L * (L >> 6);
     unsigned blocks = blocks_for(words, 256);
     if (blocks > 4096)
         blocks = 4096;
-    hipLaunchKernelGGL(k_halfsweep_bit1, dim3(blocks), dim3(256), 0, st, planes, L, c, h, key, lid,
-                       acc, dE, dM, nblk);
+    const bool general = acc.always2 || acc.always4;
+    auto kern = general ? (count ? k_halfsweep_bit1<true, true> : k_halfsweep_bit1<true, false>)
+                        : (count ? k_halfsweep_bit1<false, true> : k_halfsweep_bit1<false, false>);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), 0, st, planes, L, c, h, key, lid, acc, dE,
+                       dM, nblk);
     return hipGetLastError();
 }
 
@@ -552,16 +740,43 @@ bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
     return true;
 }
 
-int bit1_tiles_resident(int L, const Bit1TilePlan& plan) {
+namespace {
+
+template <bool kObs>
+const void* tiles_kernel_of(bool rows_kernel, bool general, bool count) {
+#define ISING_TK(K, G, C) reinterpret_cast<const void*>(K<kObs, G, C>)
+    if (rows_kernel)
+        return general ? (count ? ISING_TK(k_sweep_bit1_rows, true, true)
+                                : ISING_TK(k_sweep_bit1_rows, true, false))
+                       : (count ? ISING_TK(k_sweep_bit1_rows, false, true)
+                                : ISING_TK(k_sweep_bit1_rows, false, false));
+    return general ? (count ? ISING_TK(k_sweep_bit1_tiles, true, true)
+                            : ISING_TK(k_sweep_bit1_tiles, true, false))
+                   : (count ? ISING_TK(k_sweep_bit1_tiles, false, true)
+                            : ISING_TK(k_sweep_bit1_tiles, false, false));
+#undef ISING_TK
+}
+
+// The tile kernel variant a call launches: one wave per row or several rows
+// per wave; with or without traces; thresholds with or without always-flip
+// classes; counting the draws or not.
+const void* tiles_kernel(const Bit1TilePlan& plan, bool obs, bool general, bool count) {
+    const bool rows_kernel = plan.rows * 64 == plan.threads;
+    return obs ? tiles_kernel_of<true>(rows_kernel, general, count)
+               : tiles_kernel_of<false>(rows_kernel, general, count);
+}
+
+}  // namespace
+
+int bit1_tiles_resident(int L, const Bit1TilePlan& plan, bool obs, bool general, bool count) {
     (void)L;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    // the variant with traces uses the most registers: it bounds every variant
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(k_sweep_bit1_tiles<true, true>), plan.threads,
-            plan.lds) != hipSuccess)
+            &per_cu, tiles_kernel(plan, obs, general, count), plan.threads, plan.lds) !=
+        hipSuccess)
         return 0;
     return per_cu * cus;
 }
@@ -569,7 +784,7 @@ int bit1_tiles_resident(int L, const Bit1TilePlan& plan) {
 hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& plan, int64_t n,
                                    uint32_t t0, Key key, uint32_t lid, Accept acc, long long* dE,
                                    long long* dM, unsigned char* ws, uint32_t spin_limit,
-                                   hipStream_t st) {
+                                   bool count, hipStream_t st) {
     unsigned long long* halo = reinterpret_cast<unsigned long long*>(ws + WsLayout::kHalo);
     uint32_t* err = reinterpret_cast<uint32_t*>(ws + WsLayout::kErr);
     unsigned long long* nblk = reinterpret_cast<unsigned long long*>(ws + WsLayout::kRngBlocks);
@@ -581,17 +796,9 @@ hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& 
     int rows = plan.rows;
     void* args[] = {&planes, (void*)&L, &rows, &n, &t0, &key, &lid, &acc, &dE, &dM,
                     &halo, &err, &nblk, &spin_limit};
-    // one row per wave: the edge waves wait for the neighbours' rows when
-    // they next need them; several: they receive them before the barrier
-    const bool late = plan.rows * 64 <= plan.threads;
-    const bool obs = dE || dM;
-    const void* kern =
-        obs ? (late ? reinterpret_cast<const void*>(k_sweep_bit1_tiles<true, true>)
-                    : reinterpret_cast<const void*>(k_sweep_bit1_tiles<true, false>))
-            : (late ? reinterpret_cast<const void*>(k_sweep_bit1_tiles<false, true>)
-                    : reinterpret_cast<const void*>(k_sweep_bit1_tiles<false, false>));
-    return hipLaunchCooperativeKernel(kern, dim3(plan.ntiles), dim3(plan.threads), args, plan.lds,
-                                      st);
+    const bool general = acc.always2 || acc.always4;
+    return hipLaunchCooperativeKernel(tiles_kernel(plan, dE || dM, general, count),
+                                      dim3(plan.ntiles), dim3(plan.threads), args, plan.lds, st);
 }
 
 }  // namespace ising

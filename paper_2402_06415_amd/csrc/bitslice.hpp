@@ -62,6 +62,97 @@ __device__ __forceinline__ WordState classify(uint32_t W, uint32_t O, uint32_t S
     return st;
 }
 
+// Classification without the always-flip classes: for every beta whose
+// thresholds are both below 2^32 (all beta > 1e-9 or so), u = 2 and u = 4
+// always draw.  Branch-free; the caller picks it only in that case.
+__device__ __forceinline__ WordState classify_draw(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
+                                                   uint32_t D) {
+    const uint32_t a0 = W ^ O, a1 = W ^ S, a2 = W ^ U, a3 = W ^ D;
+    WordState st;
+    st.W = W;
+    st.a3 = a3;
+    st.sm = bop3<T_XOR3>(a0, a1, a2);
+    st.cy = bop3<T_MAJ>(a0, a1, a2);
+    st.flip = bop3<T_OR_AND>(st.cy, st.sm, a3);       // A >= 2: dE <= 0
+    st.m2 = bop3<T_XOR_ANDN>(st.sm, a3, st.cy);       // A == 1: u = 2
+    st.und = bop3<T_NOR3>(st.flip, st.flip, st.flip);  // A <= 1: u = 2 or 4, both draw
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// Plane-draw Philox blocks with the group-independent work hoisted.
+//
+// The blocks of one half-sweep have counters (g, lid, h, 1 | b << 8): only
+// g varies between the lanes and only the tag between the blocks of one
+// group.  Written out, Philox4x32-10's first three rounds then split into a
+// part fixed for the half-sweep (PlaneHalf), a part fixed for the group
+// (PlaneGroup: two products shared by its blocks) and 6 of the 12
+// instructions of those rounds per block; rounds 4-10 are the plain ones.
+// The result is bitwise Philox4x32-10 of that counter.
+// ---------------------------------------------------------------------------
+struct PlaneHalf {
+    uint32_t a;  // lo(M1 h) ^ k0[1]      round 2: x = hi(M1 z1) ^ a
+    uint32_t b;  // hi(M0 x1) ^ k1[1]     round 2: z = lo(M0 g) ^ b
+    uint32_t c;  // lo(M0 x1) ^ k1[2]     round 3: z = hi(M0 x2) ^ c
+};
+
+// x1 = hi(M1 h) ^ lid ^ k0[0] is round 1's x; round keys k0[r] = rk.k[2r],
+// k1[r] = rk.k[2r + 1].
+__device__ __forceinline__ PlaneHalf plane_half(const RoundKeys& rk, uint32_t lid, uint32_t h) {
+    const uint64_t ph = (uint64_t)kPhiloxM1 * h;
+    const uint32_t x1 = xor3((uint32_t)(ph >> 32), lid, rk.k[0]);
+    const uint64_t px = (uint64_t)kPhiloxM0 * x1;
+    PlaneHalf r;
+    r.a = (uint32_t)ph ^ rk.k[2];
+    r.b = (uint32_t)(px >> 32) ^ rk.k[3];
+    r.c = (uint32_t)px ^ rk.k[5];
+    return r;
+}
+
+struct PlaneGroup {
+    uint32_t h0;      // hi(M0 g): round 1's z is h0 ^ tag ^ k1[0]
+    uint32_t hz, lz;  // M1 (lo(M0 g) ^ b): round 3's product of z
+};
+
+__device__ __forceinline__ PlaneGroup plane_group(uint32_t g, const PlaneHalf& ph) {
+    const uint64_t pg = (uint64_t)kPhiloxM0 * g;
+    const uint64_t pz = (uint64_t)kPhiloxM1 * ((uint32_t)pg ^ ph.b);
+    PlaneGroup r;
+    r.h0 = (uint32_t)(pg >> 32);
+    r.hz = (uint32_t)(pz >> 32);
+    r.lz = (uint32_t)pz;
+    return r;
+}
+
+// The tag word of block b folded with round 1's key: (1 | b << 8) ^ k1[0].
+__device__ __forceinline__ uint32_t plane_tag(uint32_t b, const RoundKeys& rk) {
+    return (kTagPlane | (b << 8)) ^ rk.k[1];
+}
+
+__device__ __forceinline__ U4 plane_block(const PlaneGroup& pg, uint32_t tag, const PlaneHalf& ph,
+                                          const RoundKeys& rk) {
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * (pg.h0 ^ tag);  // round 2
+    const uint32_t x2 = (uint32_t)(p1 >> 32) ^ ph.a;
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * x2;             // round 3
+    U4 c;
+    c.x = xor3(pg.hz, (uint32_t)p1, rk.k[4]);
+    c.y = pg.lz;
+    c.z = (uint32_t)(p0 >> 32) ^ ph.c;
+    c.w = (uint32_t)p0;
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        const uint64_t q0 = (uint64_t)kPhiloxM0 * c.x;
+        const uint64_t q1 = (uint64_t)kPhiloxM1 * c.z;
+        U4 n;
+        n.x = xor3((uint32_t)(q1 >> 32), c.y, rk.k[2 * r]);
+        n.y = (uint32_t)q1;
+        n.z = xor3((uint32_t)(q0 >> 32), c.w, rk.k[2 * r + 1]);
+        n.w = (uint32_t)q0;
+        c = n;
+    }
+    return c;
+}
+
 // Per-thread constants of the comparison: the Philox round keys and, for
 // the first eight planes, the threshold bits as all-ones/all-zero masks
 // (t2m[k] for T2, t4m[k] for T4), both in vector registers.
@@ -106,6 +197,30 @@ __device__ __forceinline__ uint32_t bop3_vsv(uint32_t a, uint32_t b, uint32_t c)
 __device__ __forceinline__ void compare_plane(WordState& st, uint32_t P, uint32_t tm) {
     st.flip = bop3<T_OR2>(st.flip, bop3<T_AND_ANDN>(st.und, tm, P), P);
     st.und = bop3<T_AND_XNOR>(st.und, P, tm);
+}
+
+// Compare the four planes of block b (planes 4b..4b+3) of one word, the
+// threshold bits taken from the masks in vector registers (b < kBlocks).
+template <int kBlocks>
+__device__ __forceinline__ void compare_block(WordState& st, const U4& out, int b,
+                                              const DrawConstsT<kBlocks>& dc) {
+    const uint32_t m2 = st.m2;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+        compare_plane(st, u4_get(out, kk), bop3<T_BITSEL>(m2, dc.t2m[4 * b + kk], dc.t4m[4 * b + kk]));
+}
+
+// The same for any block, the threshold bits extracted from the
+// wave-uniform thresholds (scalar work).
+__device__ __forceinline__ void compare_block_uniform(WordState& st, const U4& out, uint32_t b,
+                                                      const Accept& acc) {
+    const uint32_t m2 = st.m2;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const uint32_t sh = 31u - (4u * b + (uint32_t)kk);
+        const uint32_t t2m = 0u - ((acc.T2 >> sh) & 1u), t4m = 0u - ((acc.T4 >> sh) & 1u);
+        compare_plane(st, u4_get(out, kk), bop3_vsv<T_BITSEL>(m2, t2m, t4m));
+    }
 }
 
 // Draw the Philox blocks of word group g and compare r < T plane by plane.

@@ -39,7 +39,7 @@ hipError_t launch_init_bit1(uint32_t* planes, int L, int start, Key key, uint32_
                             hipStream_t st);
 hipError_t launch_halfsweep_bit1(uint32_t* planes, int L, int c, uint32_t h, Key key,
                                  uint32_t lid, Accept acc, long long* dE, long long* dM,
-                                 unsigned long long* nblk, hipStream_t st);
+                                 unsigned long long* nblk, bool count, hipStream_t st);
 hipError_t launch_measure_bit1(const uint32_t* planes, int L, long long* acc, hipStream_t st);
 hipError_t launch_to_int8_bit1(const uint32_t* planes, int L, int8_t* out, hipStream_t st);
 hipError_t launch_from_int8_bit1(uint32_t* planes, int L, const int8_t* in, hipStream_t st);
@@ -56,12 +56,14 @@ bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan);
 // LDS bytes of a tile of `rows` rows (both colours, one halo row each side).
 size_t tile_lds_bytes(int L, int rows);
 // How many tiles of this plan the device holds at once (0 if the query
-// fails); every tile must be resident for the inter-tile hand-off.
-int bit1_tiles_resident(int L, const Bit1TilePlan& plan);
+// fails) in the kernel variant of (traces, always-flip classes, counting);
+// every tile must be resident for the inter-tile hand-off.
+int bit1_tiles_resident(int L, const Bit1TilePlan& plan, bool obs, bool general, bool count);
+// count: add the Philox blocks drawn to the workspace's counters.
 hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& plan,
                                    int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
                                    long long* dE, long long* dM, unsigned char* ws,
-                                   uint32_t spin_limit, hipStream_t st);
+                                   uint32_t spin_limit, bool count, hipStream_t st);
 
 // Shared small kernels ------------------------------------------------------
 hipError_t launch_fill_i64(long long* p, int64_t n, long long v, hipStream_t st);

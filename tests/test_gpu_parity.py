@@ -362,12 +362,17 @@ def _expected_plane_blocks(s, beta, seed, lid, t0, n):
 @pytest.mark.parametrize("L,flags", [(256, 0), (4096, 0), (192, lib.FLAG_GLOBAL_HALFSWEEP)])
 def test_rng_block_count_equals_count_from_the_oracle(L, flags):
     """ising_rng_blocks (the draw count behind the benchmark's ALU work)
-    equals the blocks the oracle's chain needs, word by word."""
+    equals the blocks the oracle's chain needs, word by word; without the
+    counting flag the kernels count nothing and give the same chain."""
     say(f"rng blocks L={L} flags={flags}")
     seed, n = 21, 3 if L > 1024 else 6
-    g = _gpu_lattice(L, "bit1", seed, "random", flags)
+    g = _gpu_lattice(L, "bit1", seed, "random", flags | lib.FLAG_COUNT_DRAWS)
     g.sweep(BC, n, record=False)
     got = g.rng_blocks()
+    plain = _gpu_lattice(L, "bit1", seed, "random", flags)
+    plain.sweep(BC, n, record=False)
+    assert plain.rng_blocks() == 0
+    assert (_host(plain.to_int8()) == _host(g.to_int8())).all()
     s = oracle.init(L, oracle.START_RANDOM, seed)
     want = _expected_plane_blocks(s, BC, seed, 0, 0, n)
     assert got == want
