@@ -400,19 +400,21 @@ __device__ __forceinline__ void update_row(const RowCtx& rc, int nw, const Plane
                                            unsigned long long& nblk) {
     for (int w = (int)(threadIdx.x & 63); w < nw; w += 64) {
         const int wx = rc.p ? ((w + 1 == nw) ? 0 : w + 1) : ((w == 0) ? nw - 1 : w - 1);
+        // the five LDS loads are unconditional (a waiting edge row reads its
+        // stale halo row and replaces it): a load issued on one side of a
+        // branch only would make the compiler wait for every load at the join
         const uint32_t W = rc.Wr[w];
         const uint32_t O = rc.Or[w];
         const uint32_t X = rc.Or[wx];
-        uint32_t U = 0, D = 0;
-        unsigned long long su = 0, sd = 0;
+        uint32_t U = rc.Ur[w];
+        uint32_t D = rc.Dr[w];
+        unsigned long long su, sd;
+        asm("" : "=v"(su));  // defined below when used, no instruction here
+        asm("" : "=v"(sd));
         if (rc.wait_u)
             su = __hip_atomic_load(rc.su + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            U = rc.Ur[w];
         if (rc.wait_d)
             sd = __hip_atomic_load(rc.sd + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else
-            D = rc.Dr[w];
         const PlaneGroup pg = plane_group(rc.g0 + (uint32_t)w, ph);
         U4 blk[kStraightBlocks];
 #pragma unroll
@@ -477,6 +479,10 @@ __device__ __forceinline__ RowCtx row_ctx(uint32_t* tile, const TileGeom& t, int
     rc.p = (y + c) & 1;
     rc.wait_u = late && hs > 0 && first;
     rc.wait_d = late && hs > 0 && last;
+    if (late && hs == 0) {  // the one-row-per-wave kernel masks hs > 0 itself
+        rc.wait_u = first;
+        rc.wait_d = last;
+    }
     return rc;
 }
 
@@ -539,7 +545,9 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_rows(
     const int nwaves = blockDim.x >> 6;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int r = row_of(wave, rows);
+    // rows to waves rotated by the workgroup index, so that the edge rows of
+    // the tiles sharing a compute unit fall on different SIMDs
+    const int r = row_of((wave + (int)blockIdx.x) % rows, rows);
     TileDraws td;
     td.dc = draw_consts<kStraightBlocks>(key, acc);
 #pragma unroll
@@ -551,10 +559,17 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_rows(
         __builtin_amdgcn_s_setprio(3);  // the neighbouring tiles wait for these rows
     long long sE = 0, sM = 0;
     unsigned long long nblk = 0;
+    // the row's context in the two colours, set up once
+    const RowCtx rc0 = row_ctx(tile, t, rows, r, 0, true, halo);
+    const RowCtx rc1 = row_ctx(tile, t, rows, r, 1, true, halo);
     for (int64_t hs = 0; hs < 2 * n; ++hs) {
         int dE = 0, dM = 0;
         const PlaneHalf ph = plane_half(td.dc.rk, lid, 2u * t0 + (uint32_t)hs);
-        const RowCtx rc = row_ctx(tile, t, rows, r, hs, true, halo);
+        RowCtx rc = (hs & 1) ? rc1 : rc0;
+        rc.tag_in = (uint32_t)hs;
+        rc.tag_out = (uint32_t)hs + 1u;
+        rc.wait_u = rc.wait_u && hs > 0;
+        rc.wait_d = rc.wait_d && hs > 0;
         update_row<kObs, kGeneral, kCount>(rc, t.nw, ph, acc, td, err, spin_limit, dE, dM, nblk);
         __syncthreads();
         if (kObs) {
