@@ -388,6 +388,35 @@ struct RowCtx {
     bool wait_u, wait_d;             // rows above / below from the slots
 };
 
+// The decision for one word whose straight-line Philox blocks are drawn:
+// classification from the word and its neighbours (X: the same-row word on
+// the side given by p), the plane-by-plane comparison, further blocks while
+// some site is undecided; returns the new word.
+template <bool kObs, bool kGeneral, bool kCount>
+__device__ __forceinline__ uint32_t decide_word(uint32_t W, uint32_t O, uint32_t X, uint32_t U,
+                                                uint32_t D, int p,
+                                                const U4 (&blk)[kStraightBlocks],
+                                                const PlaneGroup& pg, const PlaneHalf& ph,
+                                                const Accept& acc, const TileDraws& td, int& dE,
+                                                int& dM, unsigned long long& nblk) {
+    // side neighbour: compact column i - 1 (p == 0: the funnel shift
+    // O:X >> 31) or i + 1 (p == 1: X:O >> 1)
+    const uint32_t S = __builtin_amdgcn_alignbit(p ? X : O, p ? O : X, p ? 1u : 31u);
+    WordState st = kGeneral ? classify(W, O, S, U, D, acc) : classify_draw(W, O, S, U, D);
+#pragma unroll
+    for (int b = 0; b < kStraightBlocks; ++b) {
+        if (kCount)
+            nblk += st.und ? 1u : 0u;
+        compare_block<kStraightBlocks>(st, blk[b], b, td.dc);
+    }
+    for (uint32_t b = kStraightBlocks; b < 8u && st.und; ++b) {
+        if (kCount)
+            ++nblk;
+        compare_block_uniform(st, plane_block(pg, plane_tag(b, td.dc.rk), ph, td.dc.rk), b, acc);
+    }
+    return finalize<kObs>(st, dE, dM);
+}
+
 // Update the words of one row: one word per lane, 64-word chunks.  The
 // Philox blocks of a word do not depend on the spins, so they are computed
 // between issuing the word's loads and using them: the LDS and halo-slot
@@ -428,23 +457,8 @@ __device__ __forceinline__ void update_row(const RowCtx& rc, int nw, const Plane
             U = finish_wait(su, rc.su + w, rc.tag_in, spin_limit, err);
         if (rc.wait_d)
             D = finish_wait(sd, rc.sd + w, rc.tag_in, spin_limit, err);
-        // side neighbour: compact column i - 1 (p == 0: the funnel shift
-        // O:X >> 31) or i + 1 (p == 1: X:O >> 1)
-        const uint32_t S = __builtin_amdgcn_alignbit(rc.p ? X : O, rc.p ? O : X, rc.p ? 1u : 31u);
-        WordState st = kGeneral ? classify(W, O, S, U, D, acc) : classify_draw(W, O, S, U, D);
-#pragma unroll
-        for (int b = 0; b < kStraightBlocks; ++b) {
-            if (kCount)
-                nblk += st.und ? 1u : 0u;
-            compare_block<kStraightBlocks>(st, blk[b], b, td.dc);
-        }
-        for (uint32_t b = kStraightBlocks; b < 8u && st.und; ++b) {
-            if (kCount)
-                ++nblk;
-            compare_block_uniform(st, plane_block(pg, plane_tag(b, td.dc.rk), ph, td.dc.rk), b,
-                                  acc);
-        }
-        const uint32_t nwd = finalize<kObs>(st, dE, dM);
+        const uint32_t nwd = decide_word<kObs, kGeneral, kCount>(W, O, X, U, D, rc.p, blk, pg, ph,
+                                                                 acc, td, dE, dM, nblk);
         rc.Wr[w] = nwd;
         if (rc.pub_first)
             publish_slot(rc.pub_first + w, rc.tag_out, nwd);
@@ -571,6 +585,104 @@ __global__ void __launch_bounds__(1024) k_sweep_bit1_rows(
         rc.wait_u = rc.wait_u && hs > 0;
         rc.wait_d = rc.wait_d && hs > 0;
         update_row<kObs, kGeneral, kCount>(rc, t.nw, ph, acc, td, err, spin_limit, dE, dM, nblk);
+        __syncthreads();
+        if (kObs) {
+            sE += dE;
+            sM += dM;
+            if (hs & 1) {
+                trace_add(sE, sM, red, wave, lane, nwaves, hs >> 1, dEtr, dMtr);
+                sE = sM = 0;
+            }
+        }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    if (kCount)
+        add_count(nblk, nblk_out);
+    store_tile(planes, tile, rows, t, wave, nwaves);
+}
+
+// The one-wave-per-row kernel for rows of at most 64 words (one word per
+// lane), with the draws pipelined across half-sweeps: a wave draws the
+// Philox blocks of its word for half-sweep hs + 1 right after publishing
+// its word of half-sweep hs, before the barrier, so that the draws fill the
+// barrier's wait and after the barrier only the loads, the wait for the
+// neighbours' rows, the decision and the publication remain: the chain of
+// hand-offs between neighbouring tiles (each edge row needs the
+// neighbour's edge row of the previous half-sweep) gets that much shorter.
+template <bool kObs, bool kGeneral, bool kCount>
+__global__ void __launch_bounds__(1024) k_sweep_bit1_rows_pipe(
+    uint32_t* planes, int L, int rows, int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
+    long long* dEtr, long long* dMtr, unsigned long long* halo, uint32_t* err,
+    unsigned long long* nblk_out, uint32_t spin_limit) {
+    extern __shared__ uint32_t tile[];  // [2][rows + 2][nw]
+    __shared__ long long red[2][16];
+    const TileGeom t = tile_geom(L, rows);
+    const int nw = t.nw;
+    const int nwaves = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int r = row_of((wave + (int)blockIdx.x) % rows, rows);
+    TileDraws td;
+    td.dc = draw_consts<kStraightBlocks>(key, acc);
+#pragma unroll
+    for (int b = 0; b < kStraightBlocks; ++b)
+        td.tag[b] = plane_tag((uint32_t)b, td.dc.rk);
+    load_tile(tile, planes, L, rows, t);
+    __syncthreads();
+    if (r == 0 || r == rows - 1)
+        __builtin_amdgcn_s_setprio(3);  // the neighbouring tiles wait for these rows
+    const RowCtx rc0 = row_ctx(tile, t, rows, r, 0, true, halo);
+    const RowCtx rc1 = row_ctx(tile, t, rows, r, 1, true, halo);
+    const int w = lane;
+    const bool active = w < nw;
+    // the side-neighbour word for p = 0 (left) and p = 1 (right)
+    const int wl = (w == 0) ? nw - 1 : w - 1, wr = (w + 1 >= nw) ? 0 : w + 1;
+    PlaneHalf ph = plane_half(td.dc.rk, lid, 2u * t0);
+    PlaneGroup pg = plane_group(rc0.g0 + (uint32_t)w, ph);
+    U4 blk[kStraightBlocks];
+#pragma unroll
+    for (int b = 0; b < kStraightBlocks; ++b)
+        blk[b] = plane_block(pg, td.tag[b], ph, td.dc.rk);
+    long long sE = 0, sM = 0;
+    unsigned long long nblk = 0;
+    for (int64_t hs = 0; hs < 2 * n; ++hs) {
+        int dE = 0, dM = 0;
+        RowCtx rc = (hs & 1) ? rc1 : rc0;
+        rc.tag_in = (uint32_t)hs;
+        rc.tag_out = (uint32_t)hs + 1u;
+        rc.wait_u = rc.wait_u && hs > 0;
+        rc.wait_d = rc.wait_d && hs > 0;
+        if (active) {
+            const uint32_t W = rc.Wr[w];
+            const uint32_t O = rc.Or[w];
+            const uint32_t X = rc.Or[rc.p ? wr : wl];
+            uint32_t U = rc.Ur[w];
+            uint32_t D = rc.Dr[w];
+            if (rc.wait_u)
+                U = finish_wait(
+                    __hip_atomic_load(rc.su + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                    rc.su + w, rc.tag_in, spin_limit, err);
+            if (rc.wait_d)
+                D = finish_wait(
+                    __hip_atomic_load(rc.sd + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                    rc.sd + w, rc.tag_in, spin_limit, err);
+            const uint32_t nwd = decide_word<kObs, kGeneral, kCount>(W, O, X, U, D, rc.p, blk, pg,
+                                                                     ph, acc, td, dE, dM, nblk);
+            rc.Wr[w] = nwd;
+            if (rc.pub_first)
+                publish_slot(rc.pub_first + w, rc.tag_out, nwd);
+            if (rc.pub_last)
+                publish_slot(rc.pub_last + w, rc.tag_out, nwd);
+        }
+        // the publication goes out before the next half-sweep's draws
+        __builtin_amdgcn_sched_barrier(0);
+        if (hs + 1 < 2 * n) {
+            ph = plane_half(td.dc.rk, lid, 2u * t0 + (uint32_t)hs + 1u);
+            pg = plane_group(rc0.g0 + (uint32_t)w, ph);
+#pragma unroll
+            for (int b = 0; b < kStraightBlocks; ++b)
+                blk[b] = plane_block(pg, td.tag[b], ph, td.dc.rk);
+        }
         __syncthreads();
         if (kObs) {
             sE += dE;
@@ -719,6 +831,28 @@ bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
     const int nw = L >> 6;
     if (nw < 1 || nw > 0xFFFF || device_cus < 1)
         return false;
+    if (nw <= 64) {
+        // Rows of at most 64 words: one tile per CU and one wave per row, with
+        // the draws pipelined across half-sweeps; the tallest tile (up to
+        // 16 rows, the CU's 16 waves) that still gives every CU a tile, so
+        // that the fewest rows are edge rows.  A multiple of 8 tiles keeps
+        // one band of tiles per XCD.
+        int rows = 0;
+        for (int r = 16; r >= 1 && !rows; --r) {
+            const int t = L / r;
+            if (L % r || t > WsLayout::kMaxTiles || t < 2)
+                continue;
+            if (t >= device_cus || r == 1)
+                rows = r;
+        }
+        if (!rows)
+            return false;
+        plan->ntiles = L / rows;
+        plan->rows = rows;
+        plan->threads = 64 * rows;
+        plan->lds = tile_lds_bytes(L, rows);
+        return true;
+    }
     const int tiles_per_cu = (int64_t)L >= (int64_t)16 * device_cus ? 4 : 1;
     int maxt = device_cus * tiles_per_cu;
     if (maxt > WsLayout::kMaxTiles)
@@ -758,8 +892,13 @@ bool plan_bit1_tiles(int L, int device_cus, Bit1TilePlan* plan) {
 namespace {
 
 template <bool kObs>
-const void* tiles_kernel_of(bool rows_kernel, bool general, bool count) {
+const void* tiles_kernel_of(bool rows_kernel, bool pipe, bool general, bool count) {
 #define ISING_TK(K, G, C) reinterpret_cast<const void*>(K<kObs, G, C>)
+    if (rows_kernel && pipe)
+        return general ? (count ? ISING_TK(k_sweep_bit1_rows_pipe, true, true)
+                                : ISING_TK(k_sweep_bit1_rows_pipe, true, false))
+                       : (count ? ISING_TK(k_sweep_bit1_rows_pipe, false, true)
+                                : ISING_TK(k_sweep_bit1_rows_pipe, false, false));
     if (rows_kernel)
         return general ? (count ? ISING_TK(k_sweep_bit1_rows, true, true)
                                 : ISING_TK(k_sweep_bit1_rows, true, false))
@@ -772,25 +911,26 @@ const void* tiles_kernel_of(bool rows_kernel, bool general, bool count) {
 #undef ISING_TK
 }
 
-// The tile kernel variant a call launches: one wave per row or several rows
-// per wave; with or without traces; thresholds with or without always-flip
-// classes; counting the draws or not.
-const void* tiles_kernel(const Bit1TilePlan& plan, bool obs, bool general, bool count) {
+// The tile kernel variant a call launches: one wave per row (with the
+// draws pipelined when a row is at most 64 words) or several rows per wave;
+// with or without traces; thresholds with or without always-flip classes;
+// counting the draws or not.
+const void* tiles_kernel(int L, const Bit1TilePlan& plan, bool obs, bool general, bool count) {
     const bool rows_kernel = plan.rows * 64 == plan.threads;
-    return obs ? tiles_kernel_of<true>(rows_kernel, general, count)
-               : tiles_kernel_of<false>(rows_kernel, general, count);
+    const bool pipe = (L >> 6) <= 64;
+    return obs ? tiles_kernel_of<true>(rows_kernel, pipe, general, count)
+               : tiles_kernel_of<false>(rows_kernel, pipe, general, count);
 }
 
 }  // namespace
 
 int bit1_tiles_resident(int L, const Bit1TilePlan& plan, bool obs, bool general, bool count) {
-    (void)L;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, tiles_kernel(plan, obs, general, count), plan.threads, plan.lds) !=
+            &per_cu, tiles_kernel(L, plan, obs, general, count), plan.threads, plan.lds) !=
         hipSuccess)
         return 0;
     return per_cu * cus;
@@ -812,7 +952,7 @@ hipError_t launch_sweep_bit1_tiles(uint32_t* planes, int L, const Bit1TilePlan& 
     void* args[] = {&planes, (void*)&L, &rows, &n, &t0, &key, &lid, &acc, &dE, &dM,
                     &halo, &err, &nblk, &spin_limit};
     const bool general = acc.always2 || acc.always4;
-    return hipLaunchCooperativeKernel(tiles_kernel(plan, dE || dM, general, count),
+    return hipLaunchCooperativeKernel(tiles_kernel(L, plan, dE || dM, general, count),
                                       dim3(plan.ntiles), dim3(plan.threads), args, plan.lds, st);
 }
 

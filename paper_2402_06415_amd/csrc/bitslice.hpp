@@ -25,6 +25,7 @@ constexpr uint32_t T_AND_XNOR = tt(kA & ~(kB ^ kC));              // a & (b == c
 constexpr uint32_t T_OR2 = tt(kA | kB);                           // a | b   (c unused)
 constexpr uint32_t T_AND2 = tt(kA & kB);                          // a & b   (c unused)
 constexpr uint32_t T_BITSEL = tt((kA & kB) | (~kA & kC));         // a ? b : c, bitwise
+constexpr uint32_t T_OR3 = tt(kA | kB | kC);                      // a | b | c
 
 // Bit-sliced state of one 32-spin word during its update (steps 2 and 3 of
 // the single-spin-flip trial for 32 sites at once).
@@ -64,18 +65,21 @@ __device__ __forceinline__ WordState classify(uint32_t W, uint32_t O, uint32_t S
 
 // Classification without the always-flip classes: for every beta whose
 // thresholds are both below 2^32 (all beta > 1e-9 or so), u = 2 and u = 4
-// always draw.  Branch-free; the caller picks it only in that case.
+// always draw.  Branch-free; the caller picks it only in that case.  The
+// anti-aligned counts are those of classify, formed with fewer operations:
+// with a_i = W ^ N_i, a0 ^ a1 ^ a2 = W ^ O ^ S ^ U, and the majority of
+// (a0, a1, a2) is W ^ MAJ(O, S, U) (complementing all three inputs of a
+// majority complements it).
 __device__ __forceinline__ WordState classify_draw(uint32_t W, uint32_t O, uint32_t S, uint32_t U,
                                                    uint32_t D) {
-    const uint32_t a0 = W ^ O, a1 = W ^ S, a2 = W ^ U, a3 = W ^ D;
     WordState st;
     st.W = W;
-    st.a3 = a3;
-    st.sm = bop3<T_XOR3>(a0, a1, a2);
-    st.cy = bop3<T_MAJ>(a0, a1, a2);
-    st.flip = bop3<T_OR_AND>(st.cy, st.sm, a3);       // A >= 2: dE <= 0
-    st.m2 = bop3<T_XOR_ANDN>(st.sm, a3, st.cy);       // A == 1: u = 2
-    st.und = bop3<T_NOR3>(st.flip, st.flip, st.flip);  // A <= 1: u = 2 or 4, both draw
+    st.a3 = W ^ D;
+    st.sm = bop3<T_XOR3>(W, O, S) ^ U;
+    st.cy = W ^ bop3<T_MAJ>(O, S, U);
+    st.flip = bop3<T_OR_AND>(st.cy, st.sm, st.a3);     // A >= 2: dE <= 0
+    st.m2 = bop3<T_XOR_ANDN>(st.sm, st.a3, st.cy);     // A == 1: u = 2
+    st.und = ~st.flip;                                  // A <= 1: u = 2 or 4, both draw
     return st;
 }
 
@@ -199,15 +203,27 @@ __device__ __forceinline__ void compare_plane(WordState& st, uint32_t P, uint32_
     st.und = bop3<T_AND_XNOR>(st.und, P, tm);
 }
 
+// One plane of the comparison with the acceptance returned instead of
+// merged into flip (the caller merges two planes' acceptances at once).
+__device__ __forceinline__ uint32_t plane_accept(WordState& st, uint32_t P, uint32_t tm) {
+    const uint32_t a = bop3<T_AND_ANDN>(st.und, tm, P);  // undecided, T bit 1, r bit 0
+    st.und = bop3<T_AND_XNOR>(st.und, P, tm);
+    return a;
+}
+
 // Compare the four planes of block b (planes 4b..4b+3) of one word, the
 // threshold bits taken from the masks in vector registers (b < kBlocks).
 template <int kBlocks>
 __device__ __forceinline__ void compare_block(WordState& st, const U4& out, int b,
                                               const DrawConstsT<kBlocks>& dc) {
     const uint32_t m2 = st.m2;
+    uint32_t a[4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
-        compare_plane(st, u4_get(out, kk), bop3<T_BITSEL>(m2, dc.t2m[4 * b + kk], dc.t4m[4 * b + kk]));
+        a[kk] = plane_accept(st, u4_get(out, kk),
+                             bop3<T_BITSEL>(m2, dc.t2m[4 * b + kk], dc.t4m[4 * b + kk]));
+    st.flip = bop3<T_OR3>(st.flip, a[0], a[1]);
+    st.flip = bop3<T_OR3>(st.flip, a[2], a[3]);
 }
 
 // The same for any block, the threshold bits extracted from the
@@ -215,12 +231,15 @@ __device__ __forceinline__ void compare_block(WordState& st, const U4& out, int 
 __device__ __forceinline__ void compare_block_uniform(WordState& st, const U4& out, uint32_t b,
                                                       const Accept& acc) {
     const uint32_t m2 = st.m2;
+    uint32_t a[4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
         const uint32_t sh = 31u - (4u * b + (uint32_t)kk);
         const uint32_t t2m = 0u - ((acc.T2 >> sh) & 1u), t4m = 0u - ((acc.T4 >> sh) & 1u);
-        compare_plane(st, u4_get(out, kk), bop3_vsv<T_BITSEL>(m2, t2m, t4m));
+        a[kk] = plane_accept(st, u4_get(out, kk), bop3_vsv<T_BITSEL>(m2, t2m, t4m));
     }
+    st.flip = bop3<T_OR3>(st.flip, a[0], a[1]);
+    st.flip = bop3<T_OR3>(st.flip, a[2], a[3]);
 }
 
 // Draw the Philox blocks of word group g and compare r < T plane by plane.
