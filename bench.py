@@ -100,18 +100,42 @@ def profiled_traffic(kernel_name: str, summary: str = "sweep_bit1_L4096",
     return rec
 
 
-def tile_plan_fits(L: int, cus: int) -> bool:
-    """Whether the bit-packed sweep of side L runs as the LDS-resident tile
-    kernel: the host-side rule of the library's tile plan (tiles that divide
-    L, up to four per CU once each keeps four rows, at most 1024, each within
-    its share of the CU's 160 KiB of LDS and 64 KiB)."""
+def bit1_sweep_kernel(L: int, cus: int) -> str:
+    """Name of the kernel the library's bit-packed sweep of side L runs,
+    by the host-side rule of its tile plan: rows of at most 64 words take
+    one tile per CU of up to 16 rows, one wave per row, draws pipelined
+    (k_sweep_bit1_rows_pipe); wider rows up to four tiles per CU that each
+    fit a share of the CU's LDS (one wave per row: k_sweep_bit1_rows,
+    several: k_sweep_bit1_tiles); lattices whose tiles do not fit run one
+    launch per half-sweep (k_halfsweep_bit1)."""
     nw = L >> 6
     if nw < 1 or cus < 1:
-        return False
+        return "k_halfsweep_bit1"
+    if nw <= 64:
+        return "k_sweep_bit1_rows_pipe"
     tpc = 4 if L >= 16 * cus else 1
     cap = min(160 * 1024 // tpc, 64 * 1024)
-    return any(L % t == 0 and 2 * (L // t + 2) * nw * 4 <= cap
-               for t in range(min(cus * tpc, 1024, L), 1, -1))
+    fits = [t for t in range(min(cus * tpc, 1024, L), 1, -1)
+            if L % t == 0 and 2 * (L // t + 2) * nw * 4 <= cap]
+    if not fits:
+        return "k_halfsweep_bit1"
+    best = fits[0]
+    best8 = next((t for t in fits if t % 8 == 0), 0)
+    if best8 and 2 * best8 >= best:
+        best = best8
+    rows = L // best
+    waves = min(rows, max(16 // tpc, 1))
+    return "k_sweep_bit1_rows" if waves == rows else "k_sweep_bit1_tiles"
+
+
+def valu_ceiling(prof, words_per_launch: int):
+    """Attempts/ns the sweep kernel would reach at full VALU issue: the VALU
+    lane-operations it spends per 32-site word (rocprofv3 SQ_INSTS_VALU x 64
+    lanes / words updated) against the chip's 39.3 T lane-ops/s."""
+    if not prof or not prof.get("valu_wave_instructions_per_launch"):
+        return None, None
+    per_word = prof["valu_wave_instructions_per_launch"] * 64 / words_per_launch
+    return per_word, VALU_PEAK_TOPS * 1e12 * 32 / per_word / 1e9
 
 
 def measured_copy_gbs(torch, dev, nbytes: int = 1 << 30, reps: int = 5) -> float:
@@ -300,8 +324,12 @@ def bench_batched(args):
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "kernel": kernel,
             "kernel_ms": round(sweep_ms, 4),
-            "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops per launch",
+            "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops per launch "
+                    "(the blocks the chain needs, counted on a same-chain lattice)",
             "valu_issue_utilisation": round(prof["valu_utilisation"], 3) if prof else None,
+            "valu_per_word": round(valu_per_word, 1) if valu_per_word else None,
+            "valu_ceiling_attempts_per_ns": round(ceiling, 1) if ceiling else None,
+            "frac_of_valu_ceiling": round(value / ceiling, 4) if ceiling else None,
         },
         "hbm_roofline": {
             "achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -802,9 +830,9 @@ def main():
         # the library's tile plan keeps the lattice in LDS while its tiles fit
         # (L <= 16384 on 256 CUs); larger lattices run one launch per
         # half-sweep from global memory
-        tiles = not args.global_halfsweep and tile_plan_fits(
+        kernel_name = "k_halfsweep_bit1" if args.global_halfsweep else bit1_sweep_kernel(
             L, torch.cuda.get_device_properties(0).multi_processor_count)
-        kernel_name = "k_sweep_bit1_tiles" if tiles else "k_halfsweep_bit1"
+        tiles = kernel_name != "k_halfsweep_bit1"
     else:
         # int8: one resident workgroup up to L = 128, else a launch per half-sweep
         tiles = not args.global_halfsweep and L <= 128
@@ -814,6 +842,7 @@ def main():
     prof = profiled_traffic(kernel_name) if (layout == "bit1" and L == 4096 and nsw == 1000) else None
     copy_gbs = measured_copy_gbs(torch, dev)
     traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None
+    valu_per_word, ceiling = valu_ceiling(prof, L * L // 32 * nsw) if layout == "bit1" else (None, None)
     rec = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -844,8 +873,12 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "kernel": kernel_name,
             "kernel_ms": round(sweep_ms, 4),
-            "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops per launch",
+            "work": f"{blocks} Philox4x32-10 blocks x {PHILOX_OPS_PER_BLOCK} int ops per launch "
+                    "(the blocks the chain needs, counted on a same-chain lattice)",
             "valu_issue_utilisation": round(prof["valu_utilisation"], 3) if prof else None,
+            "valu_per_word": round(valu_per_word, 1) if valu_per_word else None,
+            "valu_ceiling_attempts_per_ns": round(ceiling, 1) if ceiling else None,
+            "frac_of_valu_ceiling": round(value / ceiling, 4) if ceiling else None,
         },
         "hbm_roofline": {
             "achieved": round(eff_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
