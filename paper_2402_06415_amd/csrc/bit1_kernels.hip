@@ -112,7 +112,13 @@ __global__ void __launch_bounds__(256) k_halfsweep_bit1(uint32_t* planes, int L,
     const int nw = L >> 6;
     const uint32_t plane = (uint32_t)L * (uint32_t)nw;
     const uint32_t stride = gridDim.x * blockDim.x;
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    // Workgroups are dealt to the 8 XCDs in turn: give each XCD a contiguous
+    // band of the words of every pass, so that the rows above and below a
+    // word, which the neighbouring workgroups also read, are in its own L2.
+    uint32_t wg = blockIdx.x;
+    if ((gridDim.x & 7) == 0)
+        wg = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    uint32_t i = wg * blockDim.x + threadIdx.x;
     int dE = 0, dM = 0;
     unsigned long long nblk = 0;
     if (i < plane) {
