@@ -69,7 +69,8 @@ def parse():
 
 # Sources whose text determines each profiled sweep kernel's code.
 KERNEL_SOURCES = {
-    "bit1_kernels.hip": ("bit1_kernels.hip", "common.hpp", "kernels.hpp", "bitslice.hpp"),
+    "bit1_kernels.hip": ("bit1_kernels.hip", "common.hpp", "kernels.hpp", "bitslice.hpp",
+                         "handoff.hpp"),
     "batch_kernels.hip": ("batch_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp", "quad.hpp"),
     "ea_kernels.hip": ("ea_kernels.hip", "common.hpp", "kernels.hpp", "ea.hpp", "bitslice.hpp"),
     "batch_bit_kernels.hip": ("batch_bit_kernels.hip", "common.hpp", "kernels.hpp", "batch.hpp",
@@ -834,11 +835,18 @@ def main():
             L, torch.cuda.get_device_properties(0).multi_processor_count)
         tiles = kernel_name != "k_halfsweep_bit1"
     else:
-        # int8: one resident workgroup up to L = 128, else a launch per half-sweep
-        tiles = not args.global_halfsweep and L <= 128
+        # int8: one resident workgroup up to L = 128, tiles of rows in LDS
+        # up to L = 4096 (L % 8 == 0), else a launch per half-sweep
         span = L % 8 == 0 and L * L < (1 << 31)  # the byte-parallel span kernel
-        kernel_name = ("k_sweep_int8_resident" if tiles else
-                       "k_halfsweep_int8_quad" if span else "k_halfsweep_int8")
+        if args.global_halfsweep:
+            kernel_name = "k_halfsweep_int8_quad" if span else "k_halfsweep_int8"
+        elif L <= 128:
+            kernel_name = "k_sweep_int8_resident"
+        elif L % 8 == 0 and L <= 4096:
+            kernel_name = "k_sweep_int8_tiles"
+        else:
+            kernel_name = "k_halfsweep_int8_quad" if span else "k_halfsweep_int8"
+        tiles = kernel_name in ("k_sweep_int8_resident", "k_sweep_int8_tiles")
     prof = profiled_traffic(kernel_name) if (layout == "bit1" and L == 4096 and nsw == 1000) else None
     copy_gbs = measured_copy_gbs(torch, dev)
     traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None

@@ -162,7 +162,9 @@ ISING_API int ising_sweep(ising_lattice *lat, double beta, int64_t n, int64_t *E
  * array of the library, 1 KiB + 4 MiB, one copy per GPU, held until the
  * process ends; lat->workspace is not used and may be NULL.  The call
  * allocates and frees nothing.  Limit: BIT1 lattices up to L = 8192
- * (the halo slots of 1024 tiles); INT8 lattices of any valid L.
+ * (the halo slots of 1024 tiles); INT8 lattices of any valid L (above
+ * L = 1024 with one launch per half-sweep when the tile kernel's halo
+ * slots do not fit the scratch; the chain is the same).
  * status_dev (device uint32, may be NULL) receives 0, or the device error
  * word of this call if an inter-tile wait timed out (spins then undefined).
  * Every call on one GPU shares that GPU's array: calls that overlap on one
@@ -175,19 +177,21 @@ ISING_API int ising_sweep(ising_lattice *lat, double beta, int64_t n, int64_t *E
 ISING_API int ising_sweep_noalloc(ising_lattice *lat, double beta, int64_t n, int64_t *E_dev,
                                   int64_t *M_dev, uint32_t *status_dev, void *hip_stream);
 
-/* ising_sweep on a BIT1 lattice with the persistent tile kernel under a
- * given tile shape instead of the library's choice: the lattice is cut
- * into L / rows tiles of `rows` full-width rows, one workgroup of `waves`
- * wavefronts each, resident in LDS for the whole call.  The chain does not
+/* ising_sweep with the persistent tile kernel under a given tile shape
+ * instead of the library's choice: the lattice is cut into L / rows tiles
+ * of `rows` full-width rows, one workgroup of `waves` wavefronts each,
+ * resident in LDS for the whole call (BIT1: colour bit planes, any
+ * L % 64 == 0; INT8: bytes, L % 8 == 0 and L <= 4096).  The chain does not
  * depend on the shape (the same draws, the same decisions): this entry
  * point exists so that the shapes can be compared, timed and tested.
  * Paper: as ising_sweep; the tile is the GPU counterpart of the paper's
  * supercell (Supplementary, "Details and comparisons of parallelization
  * strategies applied to different lattice configurations").
- * Errors: not BIT1, rows not dividing L into 2..1024 tiles, waves outside
- * 1..min(16, rows) -> ISING_E_INVALID; a tile above 64 KiB of LDS or more
- * tiles than the device holds at once -> ISING_E_UNSUPPORTED; in both
- * cases nothing is enqueued.  Otherwise as ising_sweep. */
+ * Errors: an INT8 side not a multiple of 8 or above 4096, rows not dividing
+ * L into 2..1024 tiles, waves outside 1..16 (BIT1: 1..min(16, rows)) ->
+ * ISING_E_INVALID; a tile above the LDS a workgroup may use (BIT1: 64 KiB)
+ * or more tiles than the device holds at once -> ISING_E_UNSUPPORTED; in
+ * both cases nothing is enqueued.  Otherwise as ising_sweep. */
 ISING_API int ising_sweep_tiles(ising_lattice *lat, double beta, int64_t n, int32_t rows,
                                 int32_t waves, int64_t *E_dev, int64_t *M_dev, void *hip_stream);
 

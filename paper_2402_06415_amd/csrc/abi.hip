@@ -46,6 +46,16 @@ int device_cus() {
     return cus;
 }
 
+int device_max_lds() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return lds;
+}
+
 const char* last_error() { return g_last_error.c_str(); }
 
 }  // namespace abi
@@ -55,6 +65,7 @@ namespace {
 
 using ising::abi::aligned256;
 using ising::abi::device_cus;
+using ising::abi::device_max_lds;
 using ising::abi::set_error;
 
 constexpr int kMaxL = 65536;
@@ -198,6 +209,8 @@ size_t ising_workspace_bytes(int32_t dim, int32_t L, int32_t layout) {
     size_t bytes = ising::WsLayout::kHalo;
     if (layout == ISING_LAYOUT_BIT1)
         bytes += ising::WsLayout::halo_bytes(L);
+    else if ((L & 7) == 0 && L <= ising::kInt8TilesMaxL)
+        bytes += ising::int8_halo_bytes(L, ising::WsLayout::kMaxTiles);
     return (bytes + 255) & ~(size_t)255;
 }
 
@@ -253,7 +266,8 @@ int ising_init(ising_lattice* lat, int32_t start, void* hip_stream) {
 // then not used and may be NULL).
 static int sweep_impl(ising_lattice* lat, unsigned char* scratch, double beta, int64_t n,
                       int64_t* E_dev, int64_t* M_dev, void* hip_stream,
-                      const ising::Bit1TilePlan* forced) {
+                      const ising::Bit1TilePlan* forced,
+                      const ising::Int8TilePlan* forced8 = nullptr) {
     int rc = validate(lat, scratch == nullptr);
     if (rc)
         return rc;
@@ -282,7 +296,24 @@ static int sweep_impl(ising_lattice* lat, unsigned char* scratch, double beta, i
     const bool global_only = (lat->flags & ISING_FLAG_GLOBAL_HALFSWEEP) != 0;
     // the no-alloc scratch's counters are cleared per call: nothing counts there
     const bool count = (lat->flags & ISING_FLAG_COUNT_DRAWS) != 0 && !scratch;
-    if (lat->layout == ISING_LAYOUT_INT8 && !global_only && ising::int8_resident_fits(L)) {
+    // INT8 lattices too large for one workgroup run the tile kernel when it
+    // fits the device and the workspace holds its halo slots
+    ising::Int8TilePlan plan8;
+    bool tiles8 = false;
+    if (lat->layout == ISING_LAYOUT_INT8) {
+        if (forced8) {
+            plan8 = *forced8;
+            tiles8 = true;
+        } else if (!global_only && !ising::int8_resident_fits(L) &&
+                   ising::plan_int8_tiles(L, device_cus(), device_max_lds(), &plan8)) {
+            const size_t room = scratch ? kScratchBytes - ising::WsLayout::kHalo
+                                        : ising::int8_halo_bytes(L, ising::WsLayout::kMaxTiles);
+            tiles8 = ising::int8_halo_bytes(L, plan8.ntiles) <= room &&
+                     ising::int8_tiles_resident(plan8, E_dev || M_dev) >= plan8.ntiles;
+        }
+    }
+    if (lat->layout == ISING_LAYOUT_INT8 && !tiles8 && !global_only &&
+        ising::int8_resident_fits(L)) {
         HIP_TRY(ising::launch_sweep_int8_resident(reinterpret_cast<int8_t*>(lat->spins), L, n, t0,
                                                   key, lat->lattice_id, acc, E_dev, M_dev,
                                                   ws_blocks(ws), st),
@@ -301,7 +332,12 @@ static int sweep_impl(ising_lattice* lat, unsigned char* scratch, double beta, i
         if (Mtr)
             HIP_TRY(ising::launch_fill_i64(Mtr, n, 0, st), "fill");
     }
-    if (lat->layout == ISING_LAYOUT_INT8) {
+    if (tiles8) {
+        HIP_TRY(ising::launch_sweep_int8_tiles(reinterpret_cast<int8_t*>(lat->spins), L, plan8, n,
+                                               t0, key, lat->lattice_id, acc, Etr, Mtr, ws,
+                                               kSpinLimit, st),
+                "sweep_int8_tiles");
+    } else if (lat->layout == ISING_LAYOUT_INT8) {
         int8_t* s = reinterpret_cast<int8_t*>(lat->spins);
         for (int64_t j = 0; j < n; ++j)
             for (int c = 0; c < 2; ++c)
@@ -391,9 +427,34 @@ int ising_sweep_tiles(ising_lattice* lat, double beta, int64_t n, int32_t rows, 
     int rc = validate(lat);
     if (rc)
         return rc;
-    if (lat->layout != ISING_LAYOUT_BIT1)
-        return set_error(ISING_E_INVALID, "ising_sweep_tiles needs the BIT1 layout");
     const int L = lat->L;
+    if (lat->layout == ISING_LAYOUT_INT8) {
+        if ((L & 7) != 0 || L > ising::kInt8TilesMaxL)
+            return set_error(ISING_E_INVALID,
+                             "ising_sweep_tiles: INT8 needs L %% 8 == 0 and L <= %d (L = %d)",
+                             ising::kInt8TilesMaxL, L);
+        if (rows < 1 || L % rows != 0 || L / rows < 2 || L / rows > ising::WsLayout::kMaxTiles)
+            return set_error(ISING_E_INVALID, "rows = %d: must divide L = %d into 2..%d tiles",
+                             rows, L, ising::WsLayout::kMaxTiles);
+        if (waves < 1 || waves > 16)
+            return set_error(ISING_E_INVALID, "waves = %d: must be in 1..16", waves);
+        ising::Int8TilePlan p8;
+        p8.ntiles = L / rows;
+        p8.rows = rows;
+        p8.threads = 64 * waves;
+        p8.lds = (size_t)(rows + 2) * (size_t)L;
+        if (p8.lds > (size_t)device_max_lds())
+            return set_error(ISING_E_UNSUPPORTED, "a tile of %d rows needs %zu bytes of LDS",
+                             rows, p8.lds);
+        const int resident = ising::int8_tiles_resident(p8, E_dev || M_dev);
+        if (resident < p8.ntiles)
+            return set_error(ISING_E_UNSUPPORTED,
+                             "%d tiles of %d rows x %d waves: only %d fit the device at once",
+                             p8.ntiles, rows, waves, resident);
+        return sweep_impl(lat, nullptr, beta, n, E_dev, M_dev, hip_stream, nullptr, &p8);
+    }
+    if (lat->layout != ISING_LAYOUT_BIT1)
+        return set_error(ISING_E_INVALID, "unknown layout");
     if (rows < 1 || L % rows != 0 || L / rows < 2 || L / rows > ising::WsLayout::kMaxTiles)
         return set_error(ISING_E_INVALID,
                          "rows = %d: must divide L = %d into 2..%d tiles", rows, L,

@@ -16,6 +16,8 @@ int set_error(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3
 int hip_fail(hipError_t e, const char* what);
 // Compute units of the current device (0 if the query fails).
 int device_cus();
+// LDS bytes one workgroup may use on the current device (0 if the query fails).
+int device_max_lds();
 // Thread-local message of the last failure ("" if none).
 const char* last_error();
 

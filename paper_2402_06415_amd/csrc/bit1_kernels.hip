@@ -14,6 +14,7 @@
 // every lane is decided, which leaves the outcome identical to a full
 // 32-bit comparison.
 #include "bitslice.hpp"
+#include "handoff.hpp"
 #include "kernels.hpp"
 
 namespace ising {
@@ -276,29 +277,6 @@ __global__ void k_from_int8_bit1(uint32_t* planes, int L, const int8_t* in) {
 // time-out the device error word is set and the kernel runs to completion.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint32_t wait_slot(const unsigned long long* slot, uint32_t tag,
-                                              uint32_t limit, uint32_t* err) {
-    uint32_t spins = 0;
-    unsigned long long v;
-    for (;;) {
-        v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)(v >> 32) == tag)
-            break;
-        if (++spins > limit) {
-            atomicOr(err, 1u);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return (uint32_t)v;
-}
-
-__device__ __forceinline__ void publish_slot(unsigned long long* slot, uint32_t tag,
-                                             uint32_t word) {
-    __hip_atomic_store(slot, ((unsigned long long)tag << 32) | word, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Tile geometry shared by the two tile-resident kernels.
 struct TileGeom {
     int nw, tr, ntiles, me, up, down, y0;
@@ -347,24 +325,6 @@ __device__ __forceinline__ void store_tile(uint32_t* planes, const uint32_t* til
             for (int w = (int)(threadIdx.x & 63); w < t.nw; w += 64)
                 planes[(int64_t)col * t.plane + (int64_t)(t.y0 + r) * t.nw + w] =
                     tile[(col * t.tr + r + 1) * t.nw + w];
-}
-
-// The rest of a wait whose first load was issued early: poll the slot until
-// its tag is the one expected (bounded; on time-out the device error word is
-// set and the word read last is used).
-__device__ __forceinline__ uint32_t finish_wait(unsigned long long v,
-                                                const unsigned long long* slot, uint32_t tag,
-                                                uint32_t limit, uint32_t* err) {
-    uint32_t spins = 0;
-    while ((uint32_t)(v >> 32) != tag) {
-        if (++spins > limit) {
-            atomicOr(err, 1u);
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return (uint32_t)v;
 }
 
 // Keeps a block's words where they are computed: the compiler may not sink

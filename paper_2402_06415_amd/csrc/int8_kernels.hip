@@ -5,6 +5,7 @@
 // so all of them are independent and updated in parallel.  Each thread owns
 // four consecutive compact indices q = 4g..4g+3 of the colour, which share
 // one Philox4x32-10 block (counter (g, lattice_id, 2t+c, 0)).
+#include "handoff.hpp"
 #include "kernels.hpp"
 #include "quad.hpp"
 
@@ -283,6 +284,146 @@ __global__ void __launch_bounds__(256) k_halfsweep_int8_quad(int8_t* s, int L, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent tile-resident INT8 sweep (L % 8 == 0).
+//
+// Each workgroup owns `rows` consecutive full-width rows as bytes in LDS for
+// the whole call, with one halo row above and one below: the facing rows of
+// the neighbouring tiles.  A half-sweep updates the colour-c sites of the
+// tile span by span (four sites of an 8-byte span share one Philox block,
+// quad.hpp), the first and last rows first; those rows publish their spans'
+// new colour-c bytes (four bytes, one tagged slot per span) for the
+// neighbouring tiles.  After its spans, every thread takes part in receiving
+// the neighbours' facing rows of this half-sweep into the halo rows, merging
+// their colour-c bytes; then one workgroup barrier.  No reader of this
+// half-sweep is disturbed by that merge: the spans being updated read only
+// the other colour's bytes of the halo rows, and the merge rewrites those
+// with the values they already hold.  Slots come in two sets, by the parity
+// of the half-sweep: a slot is rewritten two half-sweeps later, only after
+// its writer has received the neighbour's next row, which the neighbour
+// publishes only after it has received the slot.
+// ---------------------------------------------------------------------------
+
+// halo[tile][parity of hs][first, last row][L/8 spans] of (tag << 32 | bytes)
+__device__ __forceinline__ unsigned long long* quad_slots(unsigned long long* halo, int gpr, int t,
+                                                          int par, int which) {
+    return halo + (((int64_t)t * 2 + par) * 2 + which) * gpr;
+}
+
+// Row order within a half-sweep: the first and last rows come first.
+__device__ __forceinline__ int int8_row_of(int k, int rows) {
+    return (rows <= 2 || k == 0) ? k : (k == 1 ? rows - 1 : k - 1);
+}
+
+template <bool kObs>
+__global__ void __launch_bounds__(1024) k_sweep_int8_tiles(
+    int8_t* s, int L, int rows, int64_t n, uint32_t t0, Key key, uint32_t lid, Accept acc,
+    long long* dEtr, long long* dMtr, unsigned long long* halo, uint32_t* err,
+    unsigned long long* nblk_out, uint32_t spin_limit) {
+    extern __shared__ uint2 tile8[];  // [rows + 2][L] bytes, 8-byte aligned
+    int8_t* tile = reinterpret_cast<int8_t*>(tile8);
+    __shared__ long long red[2][16];
+    const int gpr = L >> 3;
+    const int ntiles = gridDim.x;
+    // workgroups are dealt to the 8 XCDs in turn: a contiguous band of
+    // tiles per XCD keeps most hand-offs within one XCD
+    int me = blockIdx.x;
+    if ((ntiles & 7) == 0)
+        me = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    const int up = (me == 0) ? ntiles - 1 : me - 1;
+    const int down = (me + 1 == ntiles) ? 0 : me + 1;
+    const int y0 = me * rows;
+    const int yu = (y0 == 0) ? L - 1 : y0 - 1;          // the row above the tile
+    const int yd = (y0 + rows == L) ? 0 : y0 + rows;     // the row below it
+    const int nwaves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < (rows + 2) * gpr; i += blockDim.x) {
+        const int r = i / gpr - 1, k = i - (r + 1) * gpr;
+        const int y = (r < 0) ? yu : (r == rows ? yd : y0 + r);
+        tile8[i] = *reinterpret_cast<const uint2*>(s + (int64_t)y * L + 8 * k);
+    }
+    __syncthreads();
+    const RoundKeys rk = round_keys(key);
+    const QuadAccept qa = quad_accept(acc.T2, acc.T4, acc.always2 != 0, acc.always4 != 0);
+    const int N = (rows + 2) * L;  // the tile's rows: update_quad never wraps inside it
+    const int tasks = rows * gpr;
+    const int k_first = (int)threadIdx.x / gpr, xk_first = (int)threadIdx.x - k_first * gpr;
+    const int dk = (int)blockDim.x / gpr, dxk = (int)blockDim.x - dk * gpr;
+    long long sE = 0, sM = 0;
+    unsigned long long nblk = 0;
+    for (int64_t hs = 0; hs < 2 * n; ++hs) {
+        const int c = (int)(hs & 1), par = (int)(hs & 1);
+        const uint32_t h = 2u * t0 + (uint32_t)hs, tag = (uint32_t)hs + 1u;
+        QuadCounts cnt;
+        // task = k gpr + xk (k-th row in edge-first order, span xk), advanced
+        // incrementally: no division per span
+        int k = k_first, xk = xk_first;
+        for (int task = threadIdx.x; task < tasks; task += blockDim.x) {
+            const int r = int8_row_of(k, rows);
+            const int y = y0 + r;
+            const uint32_t g = (uint32_t)(y * L + 8 * xk) >> 3;  // L^2 < 2^31
+            const uint32_t nb = update_quad(tile, L, N, y, (r + 1) * L, 8 * xk, c, g, h, rk, lid,
+                                            qa, cnt, nblk);
+            if (r == 0)
+                publish_slot(quad_slots(halo, gpr, me, par, 0) + xk, tag, nb);
+            if (r == rows - 1)
+                publish_slot(quad_slots(halo, gpr, me, par, 1) + xk, tag, nb);
+            xk += dxk;
+            k += dk;
+            if (xk >= gpr) {
+                xk -= gpr;
+                ++k;
+            }
+        }
+        // the neighbours' facing rows of this half-sweep: merge their new
+        // colour-c bytes (positions p + 2j of each span, p the row's parity)
+        for (int i = threadIdx.x; i < 2 * gpr; i += blockDim.x) {
+            const int which = i >= gpr, xk = i - which * gpr;
+            const unsigned long long* slot = which ? quad_slots(halo, gpr, down, par, 0) + xk
+                                                   : quad_slots(halo, gpr, up, par, 1) + xk;
+            const uint32_t v = wait_slot(slot, tag, spin_limit, err);
+            const int pn = ((which ? yd : yu) + c) & 1;
+            uint2* dst = tile8 + (which ? (rows + 1) : 0) * gpr + xk;
+            const uint2 old = *dst;
+            uint2 nv;
+            nv.x = __builtin_amdgcn_perm(v, old.x, pn ? 0x05020400u : 0x03050104u);
+            nv.y = __builtin_amdgcn_perm(v, old.y, pn ? 0x07020600u : 0x03070106u);
+            *dst = nv;
+        }
+        __syncthreads();
+        if (kObs) {
+            sE += 8ll * cnt.nflip - 2ll * cnt.sum_a2;
+            sM += 2ll * (2ll * cnt.ndown - (long long)cnt.nflip);
+            if (hs & 1) {
+                const long long e = wave_sum_i64(sE), m = wave_sum_i64(sM);
+                if (lane == 0) {
+                    red[0][wave] = e;
+                    red[1][wave] = m;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    long long E = 0, M = 0;
+                    for (int v = 0; v < nwaves; ++v) {
+                        E += red[0][v];
+                        M += red[1][v];
+                    }
+                    const int64_t j = hs >> 1;
+                    if (dEtr && E)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(dEtr + j),
+                                  (unsigned long long)E);
+                    if (dMtr && M)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(dMtr + j),
+                                  (unsigned long long)M);
+                }
+                sE = sM = 0;
+            }
+        }
+    }
+    add_count(nblk, nblk_out);
+    for (int i = threadIdx.x; i < rows * gpr; i += blockDim.x)
+        *reinterpret_cast<uint2*>(s + (int64_t)(y0 + i / gpr) * L + 8 * (i % gpr)) = tile8[gpr + i];
+}
+
 __global__ void __launch_bounds__(256) k_halfsweep_int8(int8_t* s, int L, int c, uint32_t h,
                                                         Key key, uint32_t lid, Accept acc,
                                                         long long* dEo, long long* dMo,
@@ -423,6 +564,78 @@ hipError_t launch_halfsweep_int8(int8_t* s, int L, int c, uint32_t h, Key key, u
     hipLaunchKernelGGL(k_halfsweep_int8, dim3(blocks_for(groups, 256)), dim3(256), 0, st, s, L, c,
                        h, key, lid, acc, dE, dM, nblk);
     return hipGetLastError();
+}
+
+bool plan_int8_tiles(int L, int device_cus, int max_lds, Int8TilePlan* plan) {
+    if ((L & 7) != 0 || L > kInt8TilesMaxL || device_cus < 1)
+        return false;
+    // the tallest tile (one per CU, at most 16 rows) that still gives every
+    // CU a tile and fits the LDS a workgroup may use
+    int rows = 0;
+    for (int r = 16; r >= 1 && !rows; --r) {
+        const int t = L / r;
+        if (L % r || t > WsLayout::kMaxTiles || t < 2)
+            continue;
+        if ((int64_t)(r + 2) * L > (int64_t)max_lds)
+            continue;
+        if (t >= device_cus || r == 1)
+            rows = r;
+    }
+    if (!rows)
+        return false;
+    const int ntiles = L / rows;
+    // tiles sharing a CU split its 16 waves
+    const int per_cu = (ntiles + device_cus - 1) / device_cus;
+    int waves = 16 / (per_cu > 0 ? per_cu : 1);
+    const int spans = rows * (L >> 3);
+    const int need = (spans + 63) / 64;
+    if (waves > need)
+        waves = need;
+    if (waves < 1)
+        waves = 1;
+    plan->ntiles = ntiles;
+    plan->rows = rows;
+    plan->threads = 64 * waves;
+    plan->lds = (size_t)(rows + 2) * (size_t)L;
+    return true;
+}
+
+size_t int8_halo_bytes(int L, int ntiles) {
+    return (size_t)ntiles * 2 * 2 * (size_t)(L >> 3) * 8;
+}
+
+int int8_tiles_resident(const Int8TilePlan& plan, bool obs) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const void* k = obs ? reinterpret_cast<const void*>(k_sweep_int8_tiles<true>)
+                        : reinterpret_cast<const void*>(k_sweep_int8_tiles<false>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, plan.threads, plan.lds) !=
+        hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_sweep_int8_tiles(int8_t* s, int L, const Int8TilePlan& plan, int64_t n,
+                                   uint32_t t0, Key key, uint32_t lid, Accept acc, long long* dE,
+                                   long long* dM, unsigned char* ws, uint32_t spin_limit,
+                                   hipStream_t st) {
+    unsigned long long* halo = reinterpret_cast<unsigned long long*>(ws + WsLayout::kHalo);
+    uint32_t* err = reinterpret_cast<uint32_t*>(ws + WsLayout::kErr);
+    unsigned long long* nblk = reinterpret_cast<unsigned long long*>(ws + WsLayout::kRngBlocks);
+    // zero every tag so that nothing left by an earlier call can match
+    hipError_t e = launch_fill_i64(reinterpret_cast<long long*>(halo),
+                                   (int64_t)int8_halo_bytes(L, plan.ntiles) / 8, 0, st);
+    if (e != hipSuccess)
+        return e;
+    int rows = plan.rows;
+    void* args[] = {&s, (void*)&L, &rows, &n, &t0, &key, &lid, &acc, &dE, &dM,
+                    &halo, &err, &nblk, &spin_limit};
+    const void* k = (dE || dM) ? reinterpret_cast<const void*>(k_sweep_int8_tiles<true>)
+                               : reinterpret_cast<const void*>(k_sweep_int8_tiles<false>);
+    return hipLaunchCooperativeKernel(k, dim3(plan.ntiles), dim3(plan.threads), args, plan.lds,
+                                      st);
 }
 
 hipError_t launch_measure_int8(const int8_t* s, int L, long long* acc, hipStream_t st) {

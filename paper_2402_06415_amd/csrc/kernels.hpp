@@ -32,6 +32,23 @@ hipError_t launch_halfsweep_int8(int8_t* s, int L, int c, uint32_t h, Key key, u
                                  Accept acc, long long* dE, long long* dM,
                                  unsigned long long* nblk, hipStream_t st);
 hipError_t launch_measure_int8(const int8_t* s, int L, long long* acc, hipStream_t st);
+// Persistent tile-resident INT8 sweep (L % 8 == 0, L <= kInt8TilesMaxL).
+constexpr int kInt8TilesMaxL = 4096;
+struct Int8TilePlan {
+    int ntiles = 0;   // workgroups, one tile of full rows each
+    int rows = 0;     // rows per tile
+    int threads = 0;  // workgroup size
+    size_t lds = 0;   // dynamic LDS bytes: (rows + 2) * L
+};
+// max_lds: LDS bytes one workgroup may use on the device.
+bool plan_int8_tiles(int L, int device_cus, int max_lds, Int8TilePlan* plan);
+// Bytes of tagged halo slots the plan's tiles use (after WsLayout::kHalo).
+size_t int8_halo_bytes(int L, int ntiles);
+int int8_tiles_resident(const Int8TilePlan& plan, bool obs);
+hipError_t launch_sweep_int8_tiles(int8_t* s, int L, const Int8TilePlan& plan, int64_t n,
+                                   uint32_t t0, Key key, uint32_t lid, Accept acc, long long* dE,
+                                   long long* dM, unsigned char* ws, uint32_t spin_limit,
+                                   hipStream_t st);
 hipError_t launch_convert_int8(const int8_t* in, int8_t* out, int64_t N, hipStream_t st);
 
 // BIT1 layout ---------------------------------------------------------------

@@ -59,10 +59,11 @@ struct QuadCounts {
 // Spins are bytes 0x01 (+1) and 0xFF (-1): two spins differ exactly when
 // bit 1 of their XOR is set, and a flip is an XOR with 0xFE.  All four
 // sites are handled byte-parallel in one register, without branches.
-__device__ __forceinline__ void update_quad(int8_t* lat, int L, int N, int y, int row, int x0,
-                                            int c, uint32_t g, uint32_t h, const RoundKeys& rk,
-                                            uint32_t lid, const QuadAccept& qa, QuadCounts& cnt,
-                                            unsigned long long& nblk) {
+// Returns the four sites' new bytes packed (byte j = site j).
+__device__ __forceinline__ uint32_t update_quad(int8_t* lat, int L, int N, int y, int row, int x0,
+                                                int c, uint32_t g, uint32_t h, const RoundKeys& rk,
+                                                uint32_t lid, const QuadAccept& qa,
+                                                QuadCounts& cnt, unsigned long long& nblk) {
     const int p = (y + c) & 1;  // colour-c sites sit at x0 + p + 2j
     // row = y L; the rows above and below, periodic
     const int rup = (row == 0 ? N : row) - L;
@@ -115,6 +116,7 @@ __device__ __forceinline__ void update_quad(int8_t* lat, int L, int N, int y, in
     const uint32_t Fx = perm(F, 0u, p ? 0x05000400u : 0x00050004u);
     const uint32_t Fy = perm(F, 0u, p ? 0x07000600u : 0x00070006u);
     *reinterpret_cast<uint2*>(lat + row + x0) = make_uint2(R.x ^ Fx, R.y ^ Fy);
+    return S ^ F;
 }
 
 }  // namespace ising

@@ -127,7 +127,8 @@ def test_bad_start_and_null_buffers():
 
 
 @pytest.mark.parametrize("kw,rows,waves", [
-    (dict(), 4, 4),                      # INT8 lattice: the tile kernel is BIT1 only
+    (dict(L=12), 4, 4),                  # INT8 tiles need L % 8 == 0
+    (dict(L=16), 5, 4),                  # rows must divide L
     (dict(layout=1, L=128), 3, 1),       # rows must divide L
     (dict(layout=1, L=128), 128, 4),     # one tile: at least two
     (dict(layout=1, L=4096), 2, 2),      # 2048 tiles: at most 1024

@@ -120,6 +120,29 @@ def test_int8_global_halfsweep_kernel(L):
 
 
 @pytest.mark.parametrize("record", [True, False])
+@pytest.mark.parametrize("L", [136, 200, 256, 1024, 4096])
+def test_int8_tile_kernel(L, record):
+    """INT8 lattices above the single-workgroup size with L % 8 == 0 run the
+    persistent tile kernel (tiles of full rows as bytes in LDS, tagged halo
+    hand-off of the edge rows' new bytes): one-row tiles at L = 136 and 200,
+    taller ones from L = 512 on."""
+    _compare_stepwise(L, "int8", 11, "random", BC, 7 if L >= 4096 else 12, chunk=4,
+                      record=record)
+
+
+@pytest.mark.parametrize("L,rows,waves", [(1024, 4, 4), (1024, 2, 1), (1024, 16, 16),
+                                          (256, 1, 1), (256, 8, 2), (4096, 8, 8)])
+def test_int8_tile_shapes(L, rows, waves):
+    """The INT8 tile kernel under tile shapes other than the library's."""
+    _compare_stepwise(L, "int8", 12, "random", BC, 9, chunk=3, tiles=(rows, waves))
+
+
+@pytest.mark.parametrize("beta", [0.0, 3.0])
+def test_int8_tile_kernel_beta_edges(beta):
+    _compare_stepwise(256, "int8", 13, "random", beta, 6, chunk=3)
+
+
+@pytest.mark.parametrize("record", [True, False])
 @pytest.mark.parametrize("L", [64, 128, 192, 320, 1024, 2048])
 def test_bit1_tile_kernel(L, record):
     # record=True and record=False instantiate the tile kernel with and
