@@ -443,6 +443,36 @@ def bench_learned(args):
 
     sp = stats(trp, plain_ms, T)
     sl = stats(trl, learn_ms, cycles * k)
+    # the same chains driven by the untrained network: what training gains
+    net0 = lib.Net(L, max(batch, chains), params=nn_initial_params(7))
+    lc0 = LearnedChains(net0, L, [beta] * chains, seed=301, sweeps_per_proposal=k)
+    for _ in range(100):
+        lc0.cycle()
+    lc0.n_accepted.zero_()
+    tr = torch.empty((cycles * k, chains, 2), dtype=torch.int64, device=dev)
+
+    def run_cycles0():
+        for c in range(cycles):
+            lc0.cycle(trace=tr[c * k:(c + 1) * k])
+
+    _, learn0_ms = timed(run_cycles0)
+    s0 = stats(tr.cpu().numpy(), learn0_ms, cycles * k)
+    rate0 = float(lc0.n_accepted.sum().cpu()) / (cycles * chains)
+    lc0.batch.check()
+    del tr, lc0, net0
+    # cost model: a cycle of k sweeps decorrelates |m| by about k / (2 tau)
+    # independent samples per chain, an accepted proposal by one more; the
+    # learned chain beats the plain one when a > (k / (2 tau)) (T_prop / T_k)
+    t_k = plain_ms / T * k
+    t_prop = learn_ms / cycles - t_k
+    per_cycle = k / (2 * sp["tau_int_absm_sweeps"])
+    cost_model = {
+        "sweeps_ms_per_cycle": round(t_k, 4), "proposal_ms_per_cycle": round(t_prop, 4),
+        "plain_samples_per_cycle": round(per_cycle, 4),
+        "acceptance_needed": round(per_cycle * t_prop / t_k, 3),
+        "proposal_ms_needed_at_this_acceptance": round(rate * t_k / per_cycle, 5),
+        "proposal_ms_needed_at_full_acceptance": round(t_k / per_cycle, 4),
+    }
     train_tflops = steps * batch * N * NN_MAC_PER_SITE_TRAIN * 2 / (train_ms * 1e-3) / 1e12
     rec = {
         "metric": METRIC,
@@ -466,6 +496,12 @@ def bench_learned(args):
             "E": round(sl["samples_per_s_E"] / sp["samples_per_s_E"], 4),
         },
         "acceptance_rate": round(rate, 5),
+        "untrained": dict(s0, acceptance_rate=round(rate0, 5)),
+        "trained_over_untrained": {
+            "acceptance": round(rate / max(rate0, 1e-12), 1) if rate0 > 0 else None,
+            "samples_per_s_absm": round(sl["samples_per_s_absm"] / s0["samples_per_s_absm"], 4),
+        },
+        "cost_model": cost_model,
         "training": {"ms": round(train_ms, 1), "steps": steps, "batch": batch,
                      "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                      "data_generation_ms": round(gen_ms, 1)},

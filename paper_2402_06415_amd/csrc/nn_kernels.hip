@@ -337,18 +337,23 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
 //
 // One wave per configuration and sign.  Lane l = m + 16 kk serves row slot
 // m of each 16-slot tile; each step runs, per tile, the 16 sites as the 16
-// rows of float32 matrix products on the matrix cores
-// (v_mfma_f32_16x16x4_f32): layer 1 is one product over the four mask-A
-// taps, layers 2 and 3 are 20 products over K = 5 taps x 16 channels: the
-// product (tap, q) takes channel 4q + kk in lane kk, and the four chains
-// q = 0..3 (five taps each) accumulate separately and are summed at the
-// end.  Layer 4 (one output) is a per-lane partial over that lane's
-// channels, summed across the four kk lanes.  Activations live in LDS for
-// only four columns (x mod 4): a row reads the row above at x-1..x+1
-// while that row writes x+2.  Channel c is stored at position
-// 4 (c mod 4) + c / 4 so that one 16-byte read gives lane kk its four
-// channels of a tap.  Rows share R = floor((L+1)/2) + 1 ring entries:
-// row y + R starts after row y + 1 has read the last columns of row y.
+// rows of matrix products on the matrix cores.  Layer 1 (four mask-A taps
+// of +-1 spins) is one float32 product v_mfma_f32_16x16x4_f32, exact.
+// Layers 2, 3 and 4 are bfloat16 products v_mfma_f32_16x16x32_bf16 over
+// K = 5 taps x 16 channels (padded to 96: three products of K = 32, the
+// k-th input being channel k mod 16 of tap k / 16), with float32
+// accumulation: the weights are bfloat16 already; each float32 activation
+// a enters as two bfloat16 terms, hi = bf16(a) and lo = bf16(a - hi), each
+// with its own accumulation chain, so that the products see a to within
+// 2^-17 of it (the network's float32 arithmetic to well within the log q
+// tolerance, where bfloat16 activations alone would not be).  Layer 4 (one
+// output) uses the same products with its weights in every column.
+// Activations live in LDS for only four columns (x mod 4): a row reads the
+// row above at x-1..x+1 while that row writes x+2; each site keeps its 16
+// channels as 16 bfloat16 hi terms and 16 lo terms (64 bytes), so that one
+// 16-byte read gives a lane the eight channels of its part of K.  Rows
+// share R = floor((L+1)/2) + 1 ring entries: row y + R starts after row
+// y + 1 has read the last columns of row y.
 //
 // With `symmetric`, a second wave evaluates the negated configuration in
 // step with the first, and the result is log q_sym = log((q(s) + q(-s)) / 2).
@@ -356,6 +361,7 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
 // the same order in every mode, so that sampling and teacher-forced
 // evaluation of the same configuration give the same bits.
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct WaveSlot {
     int y, x;
@@ -375,12 +381,13 @@ __device__ __forceinline__ WaveSlot wave_slot(int s, int t, int L, int S) {
     return r;
 }
 
+constexpr int kSiteBytes = 64;  // 16 channels x (bf16 hi + bf16 lo)
+
+// Byte offset of the activations of site (y, x) of layer `layer` in the ring.
 __device__ __forceinline__ int act_at(int layer, int R, int y, int x) {
     const int ry = y < R ? y : y - R;  // y mod R, as y < L < 2R
-    return ((layer * R + ry) * 4 + (x & 3)) * 16;
+    return ((layer * R + ry) * 4 + (x & 3)) * kSiteBytes;
 }
-
-__device__ __forceinline__ int chan_pos(int c) { return (c & 3) * 4 + (c >> 2); }
 
 // log sigmoid(v) = -(max(-v, 0) + log1p(e^-|v|)), with log1p(e) taken as
 // log(u) - ((u - 1) - e) / u for u = 1 + e (the rounding of u corrected
@@ -391,25 +398,72 @@ __device__ __forceinline__ float log_sigmoid_hw(float v) {
     return -(fmaxf(-v, 0.f) + (__logf(u) - __fdividef((u - 1.f) - e, u)));
 }
 
+__device__ __forceinline__ __bf16 bf16_bits(uint16_t h) {
+    return __builtin_bit_cast(__bf16, h);
+}
+
+// Store the float32 activation a of channel ch at site byte offset o as its
+// two bfloat16 terms.
+__device__ __forceinline__ void store_act(char* act, int o, int ch, float a) {
+    const __bf16 hi = (__bf16)a;
+    const __bf16 lo = (__bf16)(a - (float)hi);  // a - hi is exact in float32
+    *reinterpret_cast<__bf16*>(act + o + 2 * ch) = hi;
+    *reinterpret_cast<__bf16*>(act + o + 32 + 2 * ch) = lo;
+}
+
+// The bfloat16 operand B of layer weights for this lane: product j,
+// elements e = 0..7 are k = 32 j + 8 kk + e, i.e. channel 8 (kk & 1) + e of
+// tap 2 j + (kk >> 1) (zero past the fifth tap), column `col`.
+template <bool kOut1>
+__device__ __forceinline__ bf16x8 weights_b(const float* wexp, int wo, int col, int kk, int j) {
+    bf16x8 b;
+    const int tap = 2 * j + (kk >> 1);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int ci = 8 * (kk & 1) + e;
+        float w = 0.f;
+        if (tap < NTB)
+            w = kOut1 ? wexp[wo + ci * NTB + tap] : wexp[wo + (col * C + ci) * NTB + tap];
+        b[e] = (__bf16)w;  // exact: the values are bfloat16 already
+    }
+    return b;
+}
+
+// One layer's products for the 16 sites of a tile: sum over the three
+// K = 32 chunks of A (the gathered activations, hi and lo terms) times B.
+__device__ __forceinline__ f4 layer_products(const char* act, const int (&src)[3],
+                                             const bf16x8 (&b)[3]) {
+    f4 hi = {0.f, 0.f, 0.f, 0.f}, lo = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(act + src[j]);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(act + src[j] + 32);
+        hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b[j], hi, 0, 0, 0);
+        lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b[j], lo, 0, 0, 0);
+    }
+    return hi + lo;
+}
+
 template <int T>
 __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp, int L, int sample,
                                                  int symmetric, const int8_t* s_in,
                                                  int64_t in_stride, Key key, uint32_t chain0,
                                                  uint32_t draw, int8_t* s_out, int64_t out_stride,
                                                  float* logq_out) {
-    extern __shared__ __align__(16) float sh[];  // 16-byte reads of four channels
+    extern __shared__ __align__(16) float sh[];  // 16-byte reads of eight bfloat16 terms
     __shared__ float red[2];
     constexpr int S = 16 * T;
     const int W2 = L + 2, R = (L + 1) / 2 + 1;
     const int sb_floats = (L * W2 + 3) & ~3;
-    const int layer_floats = R * 4 * C;
+    const int layer_bytes = R * 4 * kSiteBytes;
     float* sb = sh;  // [L][L + 2] spins as +-1.0 (unsigned), zero columns 0 and L + 1
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 15, kk = lane >> 4;
-    // per wave: activations [3][R][4][C], then 16 floats kept zero (read for
-    // taps outside the lattice) and 16 floats that absorb writes of idle rows
-    float* act = sh + sb_floats + w * (3 * layer_floats + 2 * C);
-    const int zero_off = 3 * layer_floats, junk_off = zero_off + C;
+    // per wave: activations [3][R][4] sites of 64 bytes, then one zero site
+    // (read for taps outside the lattice) and one junk site that absorbs
+    // the writes of idle rows
+    char* act = reinterpret_cast<char*>(sh + sb_floats) + w * (3 * layer_bytes + 2 * kSiteBytes);
+    const int zero_off = 3 * layer_bytes, junk_off = zero_off + kSiteBytes;
     const float sigma = w == 0 ? 1.f : -1.f;
     const int b = blockIdx.x;
     for (int i = threadIdx.x; i < sb_floats; i += blockDim.x) {
@@ -419,20 +473,17 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
             v = (float)s_in[(int64_t)b * in_stride + y * L + xc - 1];
         sb[i] = v;
     }
-    if (lane < C)
-        act[zero_off + lane] = 0.f;
-    // matrix-core operands: B[k = kk][j = m] of every product
+    if (lane < kSiteBytes / 4)
+        reinterpret_cast<float*>(act + zero_off)[lane] = 0.f;
+    // matrix-core operands: B[k][j = m] of every product
     const float wb1 = wexp[NNOff::W1 + m * 4 + kk];
-    float wb2[20], wb3[20], w4[20];
+    bf16x8 wb2[3], wb3[3], wb4[3];
 #pragma unroll
-    for (int tap = 0; tap < NTB; ++tap)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int ci = 4 * q + kk;
-            wb2[tap * 4 + q] = wexp[NNOff::W2 + (m * C + ci) * NTB + tap];
-            wb3[tap * 4 + q] = wexp[NNOff::W3 + (m * C + ci) * NTB + tap];
-            w4[tap * 4 + q] = wexp[NNOff::W4 + ci * NTB + tap];
-        }
+    for (int j = 0; j < 3; ++j) {
+        wb2[j] = weights_b<false>(wexp, NNOff::W2, m, kk, j);
+        wb3[j] = weights_b<false>(wexp, NNOff::W3, m, kk, j);
+        wb4[j] = weights_b<true>(wexp, NNOff::W4, m, kk, j);
+    }
     const float bias1 = wexp[NNOff::B1 + m], bias2 = wexp[NNOff::B2 + m];
     const float bias3 = wexp[NNOff::B3 + m], bias4 = wexp[NNOff::B4];
     const RoundKeys rk = round_keys(key);
@@ -448,23 +499,28 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
 #pragma unroll
     for (int u = 0; u < T; ++u)
         lq[u] = 0.f;
+    // the lane holding z of site slot m after the layer-4 products: column
+    // m, rows 4 (m >> 2) .. 4 (m >> 2) + 3 (all columns hold z)
+    const int zsrc = m + 16 * (m >> 2);
     const int steps = 3 * L - 2;
     for (int t = 0; t < steps; ++t) {
-        // Geometry of the step, shared by the layers: for this lane's site of
-        // each tile the LDS offsets of its five taps (the zero block when the
-        // tap is outside the lattice or the slot idle) and of its spin; for
-        // the four product rows this lane receives, where their results go.
+        // Geometry of the step: for this lane's site of each tile, the LDS
+        // byte offsets of the taps its part of K reads (tap 2 j + (kk >> 1)
+        // in product j, channels 8 (kk & 1) ..; -1 for the zero site: tap
+        // outside the lattice, slot idle or past the fifth tap), of its
+        // layer-1 input and of its spin; for the four product rows this
+        // lane receives, where their results go.
         WaveSlot g[T];
-        int toff[T][NTB], doff[T][4], spin_in[T], spin_at[T];
-        bool dok[T][4];
+        int src[T][3], doff[T][4], spin_in[T], spin_at[T];
 #pragma unroll
         for (int u = 0; u < T; ++u) {
             g[u] = wave_slot(16 * u + m, t, L, S);
 #pragma unroll
-            for (int tap = 0; tap < NTB; ++tap) {
+            for (int j = 0; j < 3; ++j) {
+                const int tap = 2 * j + (kk >> 1);
                 const int yy = g[u].y + tap_dy(tap), xx = g[u].x + tap_dx(tap);
-                const bool ok = g[u].on && yy >= 0 && (unsigned)xx < (unsigned)L;
-                toff[u][tap] = ok ? act_at(0, R, yy, xx) + kk * 4 : zero_off;
+                const bool ok = tap < NTB && g[u].on && yy >= 0 && (unsigned)xx < (unsigned)L;
+                src[u][j] = ok ? act_at(0, R, yy, xx) + 16 * (kk & 1) : -1;
             }
             {
                 // layer-1 input of this lane: tap kk (mask A) of its site;
@@ -477,8 +533,7 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const WaveSlot d = wave_slot(16 * u + 4 * kk + v, t, L, S);
-                dok[u][v] = d.on;
-                doff[u][v] = d.on ? act_at(0, R, d.y, d.x) + chan_pos(m) : junk_off;
+                doff[u][v] = d.on ? act_at(0, R, d.y, d.x) : -1;
             }
         }
         // layer 1 (mask A): A[i = m][k = kk] is tap kk of site m
@@ -489,7 +544,8 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wb1, acc, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                act[doff[u][v]] = fmaxf(acc[v] + bias1, 0.f);
+                store_act(act, doff[u][v] < 0 ? junk_off : doff[u][v], m,
+                          fmaxf(acc[v] + bias1, 0.f));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -499,53 +555,34 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
         for (int layer = 1; layer < 3; ++layer) {
 #pragma unroll
             for (int u = 0; u < T; ++u) {
-                f4 in[NTB];
+                int o[3];
 #pragma unroll
-                for (int tap = 0; tap < NTB; ++tap) {
-                    const int o = toff[u][tap] == zero_off
-                                      ? zero_off
-                                      : toff[u][tap] + (layer - 1) * layer_floats;
-                    in[tap] = *reinterpret_cast<const f4*>(act + o);
-                }
-                // four independent accumulation chains (one per q), summed at the end
-                f4 part[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    part[q] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int tap = 0; tap < NTB; ++tap)
-                        part[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            in[tap][q], layer == 1 ? wb2[tap * 4 + q] : wb3[tap * 4 + q], part[q],
-                            0, 0, 0);
-                }
-                const f4 acc = (part[0] + part[1]) + (part[2] + part[3]);
+                for (int j = 0; j < 3; ++j)
+                    o[j] = src[u][j] < 0 ? zero_off : src[u][j] + (layer - 1) * layer_bytes;
+                const f4 acc = layer_products(act, o, layer == 1 ? wb2 : wb3);
                 const float bias = layer == 1 ? bias2 : bias3;
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    act[dok[u][v] ? doff[u][v] + layer * layer_floats : junk_off] =
-                        fmaxf(acc[v] + bias, 0.f);
+                    store_act(act, doff[u][v] < 0 ? junk_off : doff[u][v] + layer * layer_bytes, m,
+                              fmaxf(acc[v] + bias, 0.f));
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        // layer 4: partial over this lane's channels, then across the kk lanes
+        // layer 4: the same products with W4 in every column, then each lane
+        // takes z of its site slot from the lane that holds it
         float z[T];
 #pragma unroll
         for (int u = 0; u < T; ++u) {
-            float part = 0.f;
+            int o[3];
 #pragma unroll
-            for (int tap = 0; tap < NTB; ++tap) {
-                const int o =
-                    toff[u][tap] == zero_off ? zero_off : toff[u][tap] + 2 * layer_floats;
-                const f4 in = *reinterpret_cast<const f4*>(act + o);
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    part = fmaf(w4[tap * 4 + q], in[q], part);
-            }
-            part += __shfl_xor(part, 16, 64);
-            part += __shfl_xor(part, 32, 64);
-            z[u] = part + bias4;
+            for (int j = 0; j < 3; ++j)
+                o[j] = src[u][j] < 0 ? zero_off : src[u][j] + 2 * layer_bytes;
+            const f4 acc = layer_products(act, o, wb4);
+            const int v = lane & 3;
+            const float mine = v == 0 ? acc[0] : v == 1 ? acc[1] : v == 2 ? acc[2] : acc[3];
+            z[u] = __shfl(mine, zsrc, 64) + bias4;
         }
         if (sample && w == 0) {
 #pragma unroll
@@ -771,7 +808,8 @@ hipError_t launch_nn_adam(float* master, float* m, float* v, const float* g, uin
 size_t nn_wave_lds_bytes(int L, int symmetric) {
     const size_t sb = ((size_t)L * (L + 2) + 3) & ~(size_t)3;
     const size_t R = (size_t)(L + 1) / 2 + 1;
-    return (sb + (size_t)(symmetric ? 2 : 1) * (3 * R * 4 * C + 2 * C)) * sizeof(float);
+    return sb * sizeof(float) +
+           (size_t)(symmetric ? 2 : 1) * (3 * R * 4 + 2) * (size_t)kSiteBytes;
 }
 
 hipError_t launch_nn_wave(const float* wexp, int L, int B, int sample, int symmetric,
