@@ -350,12 +350,22 @@ def bench_batched(args):
     print(json.dumps(rec), flush=True)
 
 
-# multiply-adds per site of one training step of the proposal network:
-# forward 64 + 2*1280 + 80, input gradients 80 + 2*1280, weight gradients 64 + 2*1280 + 80
-NN_MAC_PER_SITE = 64 + 2 * 1280 + 80  # layers 1-4 of the masked network, one site
-NN_MAC_PER_SITE_TRAIN = NN_MAC_PER_SITE + (80 + 2 * 1280) + NN_MAC_PER_SITE
-FP32_VECTOR_PEAK_TFLOPS = 157.3
-FP32_MATRIX_PEAK_TFLOPS = 157.3
+# multiply-adds per site of the proposal network (layers 1-4 of the masked
+# network): 64 (mask A, 4 taps x 16) + 2 x 1280 (mask B, 80 x 16) + 80
+NN_MAC_PER_SITE = 64 + 2 * 1280 + 80
+# the wavefront kernel's products per site and sign: layer 1 as 64 float32
+# multiply-adds, layers 2-4 as bfloat16 products with each float32
+# activation entering as two bfloat16 terms
+NN_WAVE_BF16_MAC_PER_SITE = 2 * (2 * 1280 + 80)
+NN_WAVE_F32_MAC_PER_SITE = 64
+BF16_MATRIX_PEAK_TFLOPS = 2500.0
+# HBM bytes per site of one training step, each pass reading its inputs once
+# and writing its outputs once (float32 [B][N][16] activations and gradients,
+# 64 bytes a site; int8 spins; float32 dz): forward 65 + 2 x 128 + 69,
+# layer 4 backward 68 + 132, layers 3 and 2 backward 2 x (128 + 192),
+# layer 1 weight gradient 65
+NN_TRAIN_BYTES_PER_SITE = 65 + 2 * 128 + 69 + 68 + 132 + 2 * (128 + 192) + 65
+HBM_PEAK_GBS = 8000.0
 
 
 def bench_learned(args):
@@ -422,7 +432,8 @@ def bench_learned(args):
     net.logq(lc.batch, out=lq, symmetric=True)
     _, wave_ms = timed(lambda: [net.logq(lc.batch, out=lq, symmetric=True) for _ in range(reps)])
     wave_ms /= reps
-    wave_tflops = chains * 2 * N * NN_MAC_PER_SITE * 2 / (wave_ms * 1e-3) / 1e12
+    wave_tflops = (chains * 2 * N * (NN_WAVE_BF16_MAC_PER_SITE + NN_WAVE_F32_MAC_PER_SITE) * 2
+                   / (wave_ms * 1e-3) / 1e12)
     rate = float(lc.n_accepted.sum().cpu()) / (cycles * chains)
     lc.batch.check()
 
@@ -473,7 +484,7 @@ def bench_learned(args):
         "proposal_ms_needed_at_this_acceptance": round(rate * t_k / per_cycle, 5),
         "proposal_ms_needed_at_full_acceptance": round(t_k / per_cycle, 4),
     }
-    train_tflops = steps * batch * N * NN_MAC_PER_SITE_TRAIN * 2 / (train_ms * 1e-3) / 1e12
+    train_gbs = steps * batch * N * NN_TRAIN_BYTES_PER_SITE / (train_ms * 1e-3) / 1e9
     rec = {
         "metric": METRIC,
         "value": sl["samples_per_s_absm"],
@@ -507,19 +518,22 @@ def bench_learned(args):
                      "data_generation_ms": round(gen_ms, 1)},
         "roofline": {
             "bound": "mfma",
-            "achieved": round(wave_tflops, 3), "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(wave_tflops / FP32_MATRIX_PEAK_TFLOPS, 4), "traffic": None,
+            "achieved": round(wave_tflops, 3), "peak": BF16_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(wave_tflops / BF16_MATRIX_PEAK_TFLOPS, 4), "traffic": None,
             "kernel": "k_nn_wave (log q_sym of the current states: 2 waves per configuration)",
             "kernel_ms": round(wave_ms, 4),
-            "work": f"{chains} configurations x 2 signs x {N} sites x {NN_MAC_PER_SITE} "
-                    "float32 multiply-adds",
+            "work": f"{chains} configurations x 2 signs x {N} sites x "
+                    f"({NN_WAVE_BF16_MAC_PER_SITE} bfloat16 + {NN_WAVE_F32_MAC_PER_SITE} "
+                    "float32 multiply-adds)",
+            "note": f"{3 * L - 2} dependent anti-diagonal steps per configuration: the kernel "
+                    "is bound by the latency of a step, not by the matrix cores' rate",
         },
         "training_roofline": {
-            "bound": "fp32-vector",
-            "achieved": round(train_tflops, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(train_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "kernel": "training step (forward + backward + Adam kernels)",
-            "work": f"{NN_MAC_PER_SITE_TRAIN} multiply-adds per site per configuration",
+            "bound": "hbm",
+            "achieved": round(train_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(train_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "training step (forward, backward, one reduction, Adam)",
+            "work": f"{NN_TRAIN_BYTES_PER_SITE} bytes per site per configuration",
         },
     }
     print(json.dumps(rec), flush=True)

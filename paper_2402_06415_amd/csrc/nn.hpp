@@ -7,21 +7,24 @@
 namespace ising {
 
 constexpr int kNNChannels = 16;
-constexpr int kNNWgradPerBlock = 4096;  // (b, p) pairs per weight-gradient block
+constexpr int kNNGradBlocks = 1024;  // most workgroups of a weight-gradient pass
 // Byte offsets of the network workspace of max_batch configurations.
 struct NNWs {
     size_t wexp = 0;          // float[P]: the bfloat16 weights as float
-    size_t h[3] = {0, 0, 0};  // float[B][C][N]: post-ReLU outputs of layers 1-3
-    size_t g[2] = {0, 0};     // float[B][C][N]: gradients, ping-pong
+    size_t h[3] = {0, 0, 0};  // float[B][N][C]: post-ReLU outputs of layers 1-3
+    size_t g[2] = {0, 0};     // float[B][N][C]: gradients, ping-pong
     size_t dz = 0;            // float[B][N]: gradient of the loss at the logits
     size_t logq = 0;          // float[B]
-    size_t partial = 0;       // float[chunks][C][C*5+1]: weight-gradient partial sums
-    int chunks = 0;
+    size_t zero = 0;          // float[C]: zeros, read for taps outside the lattice
+    size_t partial = 0;       // float[rows][P]: weight-gradient partial sums per workgroup
+    int rows = 0;
     size_t bytes = 0;
 };
 NNWs nn_ws_layout(int L, int max_batch);
 int nn_param_count();
-int nn_wgrad_chunks(int L, int B);
+// Workgroups (rows of partial) of the weight-gradient passes over B
+// configurations: one per four 16-site tiles, at most kNNGradBlocks.
+int nn_grad_rows(int L, int B);
 hipError_t launch_nn_round(const float* master, uint16_t* w, float* wexp, hipStream_t st);
 // Forward pass of B configurations; logq[b] = log q(s_b); with_dz also
 // writes the loss gradient at the logits (for launch_nn_backward).

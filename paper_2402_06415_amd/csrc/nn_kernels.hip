@@ -2,11 +2,9 @@
 // autoregressive network (forward, backward, Adam, incremental sampling)
 // and the Metropolis-Hastings acceptance of whole-lattice proposals.
 //
-// Tensors of a batch live in the workspace as float32 [B][C][N] with
-// N = L*L sites in raster order.  The network's parameters are bfloat16;
-// the kernels read the float32 expansion of those bfloat16 values (`wexp`,
-// exactly the same numbers), because uniform float loads become scalar
-// operands of the FMAs, and accumulate in float32.
+// The network's parameters are bfloat16; the kernels read the float32
+// expansion of those bfloat16 values (`wexp`, exactly the same numbers) and
+// accumulate in float32.
 #include "nn.hpp"
 
 namespace ising {
@@ -27,6 +25,9 @@ struct NNOff {
     static constexpr int P = B4 + 1;
 };
 static_assert(NNOff::P == 2753, "parameter layout");
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -51,260 +52,6 @@ __global__ void k_nn_round(const float* master, uint16_t* w, float* wexp, int P)
         w[i] = h;
         wexp[i] = bf16_to_f32(h);
     }
-}
-
-// Site p of a batch element: (y, x), and whether (y + dy, x + dx) is inside.
-struct Site {
-    int y, x;
-};
-__device__ __forceinline__ bool inside(const Site& q, int L, int dy, int dx) {
-    return (unsigned)(q.y + dy) < (unsigned)L && (unsigned)(q.x + dx) < (unsigned)L;
-}
-
-// Layer 1 (mask A, 1 -> C, ReLU) from the int8 spins.
-__global__ void k_nn_fwd1(const int8_t* s, int64_t stride, int B, int L, float sign,
-                          const float* __restrict__ w, float* h1) {
-    const int N = L * L;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)B * N)
-        return;
-    const int b = (int)(e / N), p = (int)(e - (int64_t)b * N);
-    const Site q{p / L, p % L};
-    const int8_t* sb = s + (int64_t)b * stride;
-    float in[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-        in[t] = inside(q, L, tap_dy(t), tap_dx(t)) ? sign * (float)sb[p + tap_dy(t) * L + tap_dx(t)]
-                                                   : 0.f;
-    float* out = h1 + (int64_t)b * C * N + p;
-#pragma unroll
-    for (int co = 0; co < C; ++co) {
-        float a = w[NNOff::B1 + co];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            a = fmaf(w[NNOff::W1 + co * 4 + t], in[t], a);
-        out[(int64_t)co * N] = fmaxf(a, 0.f);
-    }
-}
-
-// Layers 2 and 3 (mask B, C -> C, ReLU).
-__global__ void k_nn_fwd_mid(const float* hin, int B, int L, const float* __restrict__ w, int wo,
-                             int bo, float* hout) {
-    const int N = L * L;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)B * N)
-        return;
-    const int b = (int)(e / N), p = (int)(e - (int64_t)b * N);
-    const Site q{p / L, p % L};
-    const float* xb = hin + (int64_t)b * C * N;
-    float in[C][NTB];
-#pragma unroll
-    for (int ci = 0; ci < C; ++ci)
-#pragma unroll
-        for (int t = 0; t < NTB; ++t)
-            in[ci][t] = inside(q, L, tap_dy(t), tap_dx(t))
-                            ? xb[(int64_t)ci * N + p + tap_dy(t) * L + tap_dx(t)]
-                            : 0.f;
-    float* out = hout + (int64_t)b * C * N + p;
-#pragma unroll
-    for (int co = 0; co < C; ++co) {
-        float a = w[bo + co];
-#pragma unroll
-        for (int ci = 0; ci < C; ++ci)
-#pragma unroll
-            for (int t = 0; t < NTB; ++t)
-                a = fmaf(w[wo + (co * C + ci) * NTB + t], in[ci][t], a);
-        out[(int64_t)co * N] = fmaxf(a, 0.f);
-    }
-}
-
-// Layer 4 (mask B, C -> 1) and the likelihood: one workgroup per batch
-// element.  logq[b] = sum_p log sigmoid(s_p z_p); with dz, also
-// dz[b][p] = d(-mean_b log q)/dz_p = -s_p sigmoid(-s_p z_p) / B.  The
-// configuration is sign * s (sign = -1 evaluates the negated lattice).
-__global__ void k_nn_out(const float* h3, const int8_t* s, int64_t stride, int B, int L, float sign,
-                         const float* __restrict__ w, float* logq, float* dz) {
-    __shared__ float red[16];
-    const int N = L * L, b = blockIdx.x;
-    const float* xb = h3 + (int64_t)b * C * N;
-    const int8_t* sb = s + (int64_t)b * stride;
-    float lq = 0.f;
-    for (int p = threadIdx.x; p < N; p += blockDim.x) {
-        const Site q{p / L, p % L};
-        float z = w[NNOff::B4];
-#pragma unroll
-        for (int ci = 0; ci < C; ++ci)
-#pragma unroll
-            for (int t = 0; t < NTB; ++t)
-                if (inside(q, L, tap_dy(t), tap_dx(t)))
-                    z = fmaf(w[NNOff::W4 + ci * NTB + t],
-                             xb[(int64_t)ci * N + p + tap_dy(t) * L + tap_dx(t)], z);
-        const float sp = sign * (float)sb[p];
-        lq += log_sigmoid(sp * z);
-        if (dz)
-            dz[(int64_t)b * N + p] = -sp / (1.f + expf(sp * z)) / (float)B;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        lq += __shfl_xor(lq, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = lq;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float t = 0.f;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
-            t += red[i];
-        logq[b] = t;
-    }
-}
-
-// Mean negative log-likelihood from logq[0..B-1] in a fixed order.
-__global__ void k_nn_loss(const float* logq, int B, float* loss) {
-    __shared__ float red[4];
-    float t = 0.f;
-    for (int b = threadIdx.x; b < B; b += blockDim.x)
-        t += logq[b];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        t += __shfl_xor(t, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = t;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        *loss = -(red[0] + red[1] + red[2] + red[3]) / (float)B;
-}
-
-// Gradient into the input of layer 4: g3[ci][p] = [h3 > 0] sum_t W4[ci][t] dz[p - d_t].
-__global__ void k_nn_bwd_out(const float* dz, const float* h3, int B, int L,
-                             const float* __restrict__ w, float* g3) {
-    const int N = L * L;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)B * N)
-        return;
-    const int b = (int)(e / N), p = (int)(e - (int64_t)b * N);
-    const Site q{p / L, p % L};
-    float g[NTB];
-#pragma unroll
-    for (int t = 0; t < NTB; ++t)
-        g[t] = inside(q, L, -tap_dy(t), -tap_dx(t))
-                   ? dz[(int64_t)b * N + p - tap_dy(t) * L - tap_dx(t)]
-                   : 0.f;
-    const float* hb = h3 + (int64_t)b * C * N + p;
-    float* ob = g3 + (int64_t)b * C * N + p;
-#pragma unroll
-    for (int ci = 0; ci < C; ++ci) {
-        float a = 0.f;
-#pragma unroll
-        for (int t = 0; t < NTB; ++t)
-            a = fmaf(w[NNOff::W4 + ci * NTB + t], g[t], a);
-        ob[(int64_t)ci * N] = hb[(int64_t)ci * N] > 0.f ? a : 0.f;
-    }
-}
-
-// Gradient into the input of layer 3 or 2:
-// gprev[ci][p] = [hprev > 0] sum_co sum_t W[co][ci][t] gout[co][p - d_t].
-__global__ void k_nn_bwd_mid(const float* gout, const float* hprev, int B, int L,
-                             const float* __restrict__ w, int wo, float* gprev) {
-    const int N = L * L;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)B * N)
-        return;
-    const int b = (int)(e / N), p = (int)(e - (int64_t)b * N);
-    const Site q{p / L, p % L};
-    const float* gb = gout + (int64_t)b * C * N;
-    float g[C][NTB];
-#pragma unroll
-    for (int co = 0; co < C; ++co)
-#pragma unroll
-        for (int t = 0; t < NTB; ++t)
-            g[co][t] = inside(q, L, -tap_dy(t), -tap_dx(t))
-                           ? gb[(int64_t)co * N + p - tap_dy(t) * L - tap_dx(t)]
-                           : 0.f;
-    const float* hb = hprev + (int64_t)b * C * N + p;
-    float* ob = gprev + (int64_t)b * C * N + p;
-#pragma unroll
-    for (int ci = 0; ci < C; ++ci) {
-        float a = 0.f;
-#pragma unroll
-        for (int co = 0; co < C; ++co)
-#pragma unroll
-            for (int t = 0; t < NTB; ++t)
-                a = fmaf(w[wo + (co * C + ci) * NTB + t], g[co][t], a);
-        ob[(int64_t)ci * N] = hb[(int64_t)ci * N] > 0.f ? a : 0.f;
-    }
-}
-
-// Weight gradient of one layer, partial sums: block (chunk, co) sums
-// gout[co][p] x[ci][p + d_t] (and gout for the bias) over its chunk of
-// (b, p) and writes partial[chunk][co][ci * NT + t], bias last.
-// kIn: 1 (int8 spins, layer 1) or C; kNT: 4 or 5.
-template <int kIn, int kNT>
-__global__ void k_nn_wgrad(const float* gout, int cout, const float* xin, const int8_t* s,
-                           int64_t stride, int B, int L, int per_thread, float* partial) {
-    constexpr int K = kIn * kNT + 1;
-    __shared__ float red[16][K];
-    const int N = L * L, co = blockIdx.y;
-    float acc[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        acc[k] = 0.f;
-    const int64_t total = (int64_t)B * N;
-    const int64_t base = (int64_t)blockIdx.x * blockDim.x * per_thread;
-    for (int r = 0; r < per_thread; ++r) {
-        const int64_t e = base + (int64_t)r * blockDim.x + threadIdx.x;
-        if (e >= total)
-            break;
-        const int b = (int)(e / N), p = (int)(e - (int64_t)b * N);
-        const Site q{p / L, p % L};
-        const float g = gout[((int64_t)b * cout + co) * N + p];
-#pragma unroll
-        for (int ci = 0; ci < kIn; ++ci)
-#pragma unroll
-            for (int t = 0; t < kNT; ++t) {
-                float x = 0.f;
-                if (inside(q, L, tap_dy(t), tap_dx(t))) {
-                    const int pp = p + tap_dy(t) * L + tap_dx(t);
-                    x = kIn == 1 ? (float)s[(int64_t)b * stride + pp]
-                                 : xin[((int64_t)b * kIn + ci) * N + pp];
-                }
-                acc[ci * kNT + t] = fmaf(g, x, acc[ci * kNT + t]);
-            }
-        acc[K - 1] += g;
-    }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        float v = acc[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            v += __shfl_xor(v, off, 64);
-        if (lane == 0)
-            red[wave][k] = v;
-    }
-    __syncthreads();
-    const int nw = blockDim.x >> 6;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        float t = 0.f;
-        for (int i = 0; i < nw; ++i)
-            t += red[i][k];
-        partial[((int64_t)blockIdx.x * cout + co) * K + k] = t;
-    }
-}
-
-// grad[W(co, k)] and grad[b(co)] = sum over chunks of partial[chunk][co][k].
-__global__ void k_nn_reduce(const float* partial, int chunks, int cout, int K, float* grad,
-                            int wo, int bo) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cout * K)
-        return;
-    const int co = i / K, k = i - co * K;
-    float t = 0.f;
-    for (int c = 0; c < chunks; ++c)
-        t += partial[((int64_t)c * cout + co) * K + k];
-    if (k == K - 1)
-        grad[bo + co] = t;
-    else
-        grad[wo + co * (K - 1) + k] = t;
 }
 
 __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uint16_t* w,
@@ -335,23 +82,29 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
 // 3L - 2 steps instead of L^2, and the draws and results are those of the
 // site-by-site order.
 //
-// One wave per configuration and sign.  Lane l = m + 16 kk serves row slot
-// m of each 16-slot tile; each step runs, per tile, the 16 sites as the 16
-// rows of matrix products on the matrix cores.  Layer 1 (four mask-A taps
-// of +-1 spins) is one float32 product v_mfma_f32_16x16x4_f32, exact.
-// Layers 2, 3 and 4 are bfloat16 products v_mfma_f32_16x16x32_bf16 over
-// K = 5 taps x 16 channels (padded to 96: three products of K = 32, the
-// k-th input being channel k mod 16 of tap k / 16), with float32
+// One wave per configuration and sign.  Lane l = m + 16 kk serves site
+// slot m of each 16-slot tile and, of that site, channels 4 kk .. 4 kk + 3.
+// Each layer is a set of products D[out channel][site] = sum_k A[out
+// channel][k] B[k][site] on the matrix cores, with the sites of a tile as
+// the 16 columns.  Layer 1 (four mask-A taps of +-1 spins) is one float32
+// product v_mfma_f32_16x16x4_f32, exact.  Layers 2, 3 and 4 take one
+// bfloat16 product v_mfma_f32_16x16x32_bf16 per mask-B tap, with float32
 // accumulation: the weights are bfloat16 already; each float32 activation
-// a enters as two bfloat16 terms, hi = bf16(a) and lo = bf16(a - hi), each
-// with its own accumulation chain, so that the products see a to within
-// 2^-17 of it (the network's float32 arithmetic to well within the log q
-// tolerance, where bfloat16 activations alone would not be).  Layer 4 (one
-// output) uses the same products with its weights in every column.
+// a enters as two bfloat16 terms, hi = bf16(a) and lo = bf16(a - hi), both
+// against the same weight, so that the products see a to within 2^-17 of
+// it (the network's float32 arithmetic to well within the log q tolerance,
+// where bfloat16 activations alone would not be).  The K = 32 of a tap are
+// its 16 channels x the two terms, ordered so that lane (m, kk) supplies
+// the hi and lo terms of channels 4 kk .. 4 kk + 3: exactly what the lane
+// holds of its own site after the previous layer.  The centre tap thus
+// passes from layer to layer in registers, and only the four taps on
+// earlier anti-diagonals read LDS, all at the start of a step.  Layer 4 (one
+// output) has its weights in every row, so that every lane of a site
+// receives its z.
 // Activations live in LDS for only four columns (x mod 4): a row reads the
-// row above at x-1..x+1 while that row writes x+2; each site keeps its 16
-// channels as 16 bfloat16 hi terms and 16 lo terms (64 bytes), so that one
-// 16-byte read gives a lane the eight channels of its part of K.  Rows
+// row above at x-1..x+1 while that row writes x+2.  A site keeps 64 bytes,
+// [hi of channels 4c..4c+3, lo of the same] for c = 0..3, which its four
+// lanes write with one 16-byte store each at the end of the step.  Rows
 // share R = floor((L+1)/2) + 1 ring entries: row y + R starts after row
 // y + 1 has read the last columns of row y.
 //
@@ -360,8 +113,6 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
 // Each wave adds its log-likelihood terms after the per-step barrier, in
 // the same order in every mode, so that sampling and teacher-forced
 // evaluation of the same configuration give the same bits.
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct WaveSlot {
     int y, x;
@@ -398,50 +149,31 @@ __device__ __forceinline__ float log_sigmoid_hw(float v) {
     return -(fmaxf(-v, 0.f) + (__logf(u) - __fdividef((u - 1.f) - e, u)));
 }
 
-__device__ __forceinline__ __bf16 bf16_bits(uint16_t h) {
-    return __builtin_bit_cast(__bf16, h);
+// The four float32 activations of this lane's channels as the operand of
+// the next layer's centre tap: their hi terms, then their lo terms.
+__device__ __forceinline__ bf16x8 act_terms(const f4& a) {
+    bf16x8 r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        r[v] = (__bf16)a[v];
+        r[4 + v] = (__bf16)(a[v] - (float)r[v]);  // a - hi is exact in float32
+    }
+    return r;
 }
 
-// Store the float32 activation a of channel ch at site byte offset o as its
-// two bfloat16 terms.
-__device__ __forceinline__ void store_act(char* act, int o, int ch, float a) {
-    const __bf16 hi = (__bf16)a;
-    const __bf16 lo = (__bf16)(a - (float)hi);  // a - hi is exact in float32
-    *reinterpret_cast<__bf16*>(act + o + 2 * ch) = hi;
-    *reinterpret_cast<__bf16*>(act + o + 32 + 2 * ch) = lo;
-}
-
-// The bfloat16 operand B of layer weights for this lane: product j,
-// elements e = 0..7 are k = 32 j + 8 kk + e, i.e. channel 8 (kk & 1) + e of
-// tap 2 j + (kk >> 1) (zero past the fifth tap), column `col`.
+// Operand A of tap t of a mask-B layer (weights at wo) for lane (m, kk):
+// row co = m (every row the single output with kOut1), elements e = 0..7
+// the weight of channel 4 kk + (e & 3), once for the hi and once for the
+// lo term.
 template <bool kOut1>
-__device__ __forceinline__ bf16x8 weights_b(const float* wexp, int wo, int col, int kk, int j) {
-    bf16x8 b;
-    const int tap = 2 * j + (kk >> 1);
+__device__ __forceinline__ bf16x8 weights_tap(const float* wexp, int wo, int m, int kk, int t) {
+    bf16x8 a;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        const int ci = 8 * (kk & 1) + e;
-        float w = 0.f;
-        if (tap < NTB)
-            w = kOut1 ? wexp[wo + ci * NTB + tap] : wexp[wo + (col * C + ci) * NTB + tap];
-        b[e] = (__bf16)w;  // exact: the values are bfloat16 already
+        const int ci = 4 * kk + (e & 3);
+        a[e] = (__bf16)(kOut1 ? wexp[wo + ci * NTB + t] : wexp[wo + (m * C + ci) * NTB + t]);
     }
-    return b;
-}
-
-// One layer's products for the 16 sites of a tile: sum over the three
-// K = 32 chunks of A (the gathered activations, hi and lo terms) times B.
-__device__ __forceinline__ f4 layer_products(const char* act, const int (&src)[3],
-                                             const bf16x8 (&b)[3]) {
-    f4 hi = {0.f, 0.f, 0.f, 0.f}, lo = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(act + src[j]);
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(act + src[j] + 32);
-        hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, b[j], hi, 0, 0, 0);
-        lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b[j], lo, 0, 0, 0);
-    }
-    return hi + lo;
+    return a;
 }
 
 template <int T>
@@ -450,18 +182,18 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
                                                  int64_t in_stride, Key key, uint32_t chain0,
                                                  uint32_t draw, int8_t* s_out, int64_t out_stride,
                                                  float* logq_out) {
-    extern __shared__ __align__(16) float sh[];  // 16-byte reads of eight bfloat16 terms
+    extern __shared__ __align__(16) float sh[];  // 16-byte accesses of eight bfloat16 terms
     __shared__ float red[2];
     constexpr int S = 16 * T;
     const int W2 = L + 2, R = (L + 1) / 2 + 1;
     const int sb_floats = (L * W2 + 3) & ~3;
     const int layer_bytes = R * 4 * kSiteBytes;
     float* sb = sh;  // [L][L + 2] spins as +-1.0 (unsigned), zero columns 0 and L + 1
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int m = lane & 15, kk = lane >> 4;
     // per wave: activations [3][R][4] sites of 64 bytes, then one zero site
     // (read for taps outside the lattice) and one junk site that absorbs
-    // the writes of idle rows
+    // the writes of idle slots
     char* act = reinterpret_cast<char*>(sh + sb_floats) + w * (3 * layer_bytes + 2 * kSiteBytes);
     const int zero_off = 3 * layer_bytes, junk_off = zero_off + kSiteBytes;
     const float sigma = w == 0 ? 1.f : -1.f;
@@ -475,17 +207,23 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
     }
     if (lane < kSiteBytes / 4)
         reinterpret_cast<float*>(act + zero_off)[lane] = 0.f;
-    // matrix-core operands: B[k][j = m] of every product
-    const float wb1 = wexp[NNOff::W1 + m * 4 + kk];
-    bf16x8 wb2[3], wb3[3], wb4[3];
+    // matrix-core operands A: row co = m of every product
+    const float wa1 = wexp[NNOff::W1 + m * 4 + kk];
+    bf16x8 wa2[NTB], wa3[NTB], wa4[NTB];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        wb2[j] = weights_b<false>(wexp, NNOff::W2, m, kk, j);
-        wb3[j] = weights_b<false>(wexp, NNOff::W3, m, kk, j);
-        wb4[j] = weights_b<true>(wexp, NNOff::W4, m, kk, j);
+    for (int t = 0; t < NTB; ++t) {
+        wa2[t] = weights_tap<false>(wexp, NNOff::W2, m, kk, t);
+        wa3[t] = weights_tap<false>(wexp, NNOff::W3, m, kk, t);
+        wa4[t] = weights_tap<true>(wexp, NNOff::W4, m, kk, t);
     }
-    const float bias1 = wexp[NNOff::B1 + m], bias2 = wexp[NNOff::B2 + m];
-    const float bias3 = wexp[NNOff::B3 + m], bias4 = wexp[NNOff::B4];
+    f4 bias1, bias2, bias3;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        bias1[v] = wexp[NNOff::B1 + 4 * kk + v];
+        bias2[v] = wexp[NNOff::B2 + 4 * kk + v];
+        bias3[v] = wexp[NNOff::B3 + 4 * kk + v];
+    }
+    const float bias4 = wexp[NNOff::B4];
     const RoundKeys rk = round_keys(key);
     const uint32_t chain = chain0 + (uint32_t)b;
     // symmetric sampling writes the configuration negated with probability 1/2
@@ -499,108 +237,125 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
 #pragma unroll
     for (int u = 0; u < T; ++u)
         lq[u] = 0.f;
-    // the lane holding z of site slot m after the layer-4 products: column
-    // m, rows 4 (m >> 2) .. 4 (m >> 2) + 3 (all columns hold z)
-    const int zsrc = m + 16 * (m >> 2);
+    const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
     const int steps = 3 * L - 2;
     for (int t = 0; t < steps; ++t) {
-        // Geometry of the step: for this lane's site of each tile, the LDS
-        // byte offsets of the taps its part of K reads (tap 2 j + (kk >> 1)
-        // in product j, channels 8 (kk & 1) ..; -1 for the zero site: tap
-        // outside the lattice, slot idle or past the fifth tap), of its
-        // layer-1 input and of its spin; for the four product rows this
-        // lane receives, where their results go.
+        // Geometry of the step, per tile: this lane's site, the LDS byte
+        // offsets of its part of the four earlier taps (zero site outside
+        // the lattice or for an idle slot) and of its own part, its layer-1
+        // input (tap kk of mask A) and its spin.
         WaveSlot g[T];
-        int src[T][3], doff[T][4], spin_in[T], spin_at[T];
+        int nb[T][4], own[T], spin_in[T], spin_at[T];
 #pragma unroll
         for (int u = 0; u < T; ++u) {
             g[u] = wave_slot(16 * u + m, t, L, S);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int tap = 2 * j + (kk >> 1);
-                const int yy = g[u].y + tap_dy(tap), xx = g[u].x + tap_dx(tap);
-                const bool ok = tap < NTB && g[u].on && yy >= 0 && (unsigned)xx < (unsigned)L;
-                src[u][j] = ok ? act_at(0, R, yy, xx) + 16 * (kk & 1) : -1;
+            for (int tp = 0; tp < 4; ++tp) {
+                const int yy = g[u].y + tap_dy(tp), xx = g[u].x + tap_dx(tp);
+                const bool ok = g[u].on && yy >= 0 && (unsigned)xx < (unsigned)L;
+                nb[u][tp] = ok ? act_at(0, R, yy, xx) + 16 * kk : zero_off;
             }
-            {
-                // layer-1 input of this lane: tap kk (mask A) of its site;
-                // index 0 is the zero column of row 0
-                const int dy = kk < 3 ? -1 : 0, dx = kk < 3 ? kk - 1 : -1;
-                const bool ok = g[u].on && g[u].y + dy >= 0;
-                spin_in[u] = ok ? (g[u].y + dy) * W2 + g[u].x + dx + 1 : 0;
-                spin_at[u] = g[u].on ? g[u].y * W2 + g[u].x + 1 : 0;
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const WaveSlot d = wave_slot(16 * u + 4 * kk + v, t, L, S);
-                doff[u][v] = d.on ? act_at(0, R, d.y, d.x) : -1;
-            }
+            own[u] = g[u].on ? act_at(0, R, g[u].y, g[u].x) + 16 * kk : junk_off;
+            // index 0 is the zero column of row 0
+            const int dy = kk < 3 ? -1 : 0, dx = kk < 3 ? kk - 1 : -1;
+            const bool ok = g[u].on && g[u].y + dy >= 0;
+            spin_in[u] = ok ? (g[u].y + dy) * W2 + g[u].x + dx + 1 : 0;
+            spin_at[u] = g[u].on ? g[u].y * W2 + g[u].x + 1 : 0;
         }
-        // layer 1 (mask A): A[i = m][k = kk] is tap kk of site m
-#pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const float a = sigma * sb[spin_in[u]];
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, wb1, acc, 0, 0, 0);
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                store_act(act, doff[u][v] < 0 ? junk_off : doff[u][v], m,
-                          fmaxf(acc[v] + bias1, 0.f));
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // layers 2 and 3 (mask B)
-#pragma unroll
-        for (int layer = 1; layer < 3; ++layer) {
+        // the sampling draws of the step do not depend on z: taken first,
+        // they overlap the products' latency
+        uint32_t r[T];
+        if (sample && w == 0) {
 #pragma unroll
             for (int u = 0; u < T; ++u) {
-                int o[3];
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    o[j] = src[u][j] < 0 ? zero_off : src[u][j] + (layer - 1) * layer_bytes;
-                const f4 acc = layer_products(act, o, layer == 1 ? wb2 : wb3);
-                const float bias = layer == 1 ? bias2 : bias3;
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    store_act(act, doff[u][v] < 0 ? junk_off : doff[u][v] + layer * layer_bytes, m,
-                              fmaxf(acc[v] + bias, 0.f));
+                const int i = g[u].y * L + g[u].x;
+                const U4 o = philox4x32_10({(uint32_t)(i >> 2), chain, draw, kTagNNSample}, rk);
+                r[u] = u4_get(o, i & 3);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        // layer 4: the same products with W4 in every column, then each lane
-        // takes z of its site slot from the lane that holds it
+        // every LDS read of the step, before any of its writes: layer-1
+        // inputs and the earlier taps of layers 2, 3 and 4
+        float sp_in[T];
+        bf16x8 ta[T][3][4];
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            sp_in[u] = sb[spin_in[u]];
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+#pragma unroll
+                for (int tp = 0; tp < 4; ++tp) {
+                    const int o = nb[u][tp] == zero_off ? zero_off : nb[u][tp] + l * layer_bytes;
+                    ta[u][l][tp] = *reinterpret_cast<const bf16x8*>(act + o);
+                }
+        }
+        bf16x8 outs[T][3];
         float z[T];
 #pragma unroll
         for (int u = 0; u < T; ++u) {
-            int o[3];
+            // layer 1 (mask A): B[k = kk][site m] is tap kk of site m
+            f4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa1, sigma * sp_in[u], zero4, 0, 0, 0);
+            f4 a;
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
-                o[j] = src[u][j] < 0 ? zero_off : src[u][j] + 2 * layer_bytes;
-            const f4 acc = layer_products(act, o, wb4);
-            const int v = lane & 3;
-            const float mine = v == 0 ? acc[0] : v == 1 ? acc[1] : v == 2 ? acc[2] : acc[3];
-            z[u] = __shfl(mine, zsrc, 64) + bias4;
+            for (int v = 0; v < 4; ++v)
+                a[v] = fmaxf(acc[v] + bias1[v], 0.f);
+            outs[u][0] = act_terms(a);
+            // layers 2 and 3: the earlier taps first, the centre tap (this
+            // lane's own output of the layer below) last
+#pragma unroll
+            for (int l = 1; l < 3; ++l) {
+                const bf16x8* wl = l == 1 ? wa2 : wa3;
+                acc = zero4;
+#pragma unroll
+                for (int tp = 0; tp < 4; ++tp)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl[tp], ta[u][l - 1][tp], acc, 0,
+                                                                  0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl[4], outs[u][l - 1], acc, 0, 0, 0);
+                const f4 bl = l == 1 ? bias2 : bias3;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    a[v] = fmaxf(acc[v] + bl[v], 0.f);
+                outs[u][l] = act_terms(a);
+            }
+            // layer 4: every row holds z of the column's site
+            acc = zero4;
+#pragma unroll
+            for (int tp = 0; tp < 4; ++tp)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa4[tp], ta[u][2][tp], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa4[4], outs[u][2], acc, 0, 0, 0);
+            z[u] = acc[0] + bias4;
         }
         if (sample && w == 0) {
 #pragma unroll
             for (int u = 0; u < T; ++u) {
                 if (g[u].on) {
-                    const int i = g[u].y * L + g[u].x;
-                    const U4 o = philox4x32_10({(uint32_t)(i >> 2), chain, draw, kTagNNSample}, rk);
-                    const uint32_t r = u4_get(o, i & 3);
                     const float pplus = 1.f / (1.f + expf(-z[u]));
-                    const float sp = ((double)r < (double)pplus * 4294967296.0) ? 1.f : -1.f;
+                    const float sp = ((double)r[u] < (double)pplus * 4294967296.0) ? 1.f : -1.f;
                     if (kk == 0) {
                         sb[spin_at[u]] = sp;
-                        s_out[(int64_t)b * out_stride + i] = (int8_t)(out_sign * sp);
+                        s_out[(int64_t)b * out_stride + g[u].y * L + g[u].x] =
+                            (int8_t)(out_sign * sp);
                     }
                 }
             }
         }
-        __syncthreads();
+        // this step's activations, for the taps of later steps
+#pragma unroll
+        for (int u = 0; u < T; ++u)
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                *reinterpret_cast<bf16x8*>(act + (own[u] == junk_off ? junk_off
+                                                                      : own[u] + l * layer_bytes)) =
+                    outs[u][l];
+        if (sample) {
+            // the second wave reads the spins the first one drew
+            __syncthreads();
+        } else {
+            // the spins are inputs and each wave has its own ring: the
+            // waves need not wait for each other
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
 #pragma unroll
         for (int u = 0; u < T; ++u) {
             const float term = log_sigmoid_hw(sigma * sb[spin_at[u]] * z[u]);
@@ -624,6 +379,482 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
             r = fmaxf(x, y) + log1pf(expf(-fabsf(x - y))) - 0.69314718055994531f;
         }
         logq_out[b] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training: forward and backward passes over a batch of B configurations.
+//
+// Activations and their gradients live in the workspace as float32
+// [B][N][C]: the 16 channels of a site are 64 contiguous bytes, and the
+// flattened site index e = b N + p runs over the whole batch.  The
+// convolutions of layers 2 and 3 and their transposes run on the matrix
+// cores as in the sampler, with 16 consecutive sites as the columns of a
+// tile: D[out channel][site] = sum_k A[out channel][k] B[k][site] over
+// k = (tap, in channel), A the bfloat16 weights and B the three bfloat16
+// terms that sum exactly to each float32 activation or gradient.  The weight gradients
+// contract over sites, where neither operand is bfloat16: they use the
+// float32 product v_mfma_f32_16x16x4_f32 (four sites per product, exact
+// products, float32 accumulation).
+// ---------------------------------------------------------------------------
+
+constexpr int kTile = 16;  // sites per matrix-core tile
+
+// Operand A of the products of a mask-B layer (weights at wo) for lane
+// (m, kk): row = output channel m; product j, elements e = 0..7 are
+// k = 32 j + 8 kk + e, i.e. channel 8 (kk & 1) + e of tap 2 j + (kk >> 1)
+// (zero past the fifth tap).
+__device__ __forceinline__ bf16x8 weights_b(const float* wexp, int wo, int m, int kk, int j) {
+    bf16x8 b;
+    const int tap = 2 * j + (kk >> 1);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int ci = 8 * (kk & 1) + e;
+        // exact: the values are bfloat16 already
+        b[e] = (__bf16)(tap < NTB ? wexp[wo + (m * C + ci) * NTB + tap] : 0.f);
+    }
+    return b;
+}
+
+struct TSite {
+    int y, x;
+};
+// Row and column of flattened site e.
+__device__ __forceinline__ TSite tsite(int e, int N, int L) {
+    const int p = e % N;
+    const int y = p / L;
+    return {y, p - y * L};
+}
+__device__ __forceinline__ bool tinside(const TSite& q, int L, int dy, int dx) {
+    return (unsigned)(q.y + dy) < (unsigned)L && (unsigned)(q.x + dx) < (unsigned)L;
+}
+
+// A lane's site in a contiguous run of sites: flattened index e = b N + p,
+// row y and column x of p.  Divides once, at the start of the run.
+struct RunSite {
+    int e, b, p, y, x;
+    __device__ __forceinline__ void start(int e0, int N, int L) {
+        e = e0;
+        b = e0 / N;
+        p = e0 - b * N;
+        y = p / L;
+        x = p - y * L;
+    }
+    __device__ __forceinline__ void advance(int k, int N, int L) {
+        e += k;
+        p += k;
+        x += k;
+        while (x >= L) {
+            x -= L;
+            if (++y == L) {
+                y = 0;
+                p -= N;
+                ++b;
+            }
+        }
+    }
+    // Whether the neighbour (y + dy, x + dx) of tap t of mask B exists,
+    // from the three edge flags; tap 5 (padding) never does.
+    __device__ __forceinline__ bool tap_ok(int t, int L) const {
+        const bool up = y > 0, left = x > 0, right = x < L - 1;
+        return t == 0 ? up && left : t == 1 ? up : t == 2 ? up && right : t == 3 ? left : t == 4;
+    }
+    // The same for the neighbour (y - dy, x - dx) that tap t reads from.
+    __device__ __forceinline__ bool tap_ok_rev(int t, int L) const {
+        const bool down = y < L - 1, left = x > 0, right = x < L - 1;
+        return t == 0 ? down && right : t == 1 ? down : t == 2 ? down && left : t == 3 ? right : t == 4;
+    }
+};
+
+// Contiguous run of tiles [t0, t1) of wave `wave` of `waves`.
+__device__ __forceinline__ void tile_run(int tiles, int wave, int waves, int& t0, int& t1) {
+    const int per = (tiles + waves - 1) / waves;
+    t0 = wave * per;
+    t1 = t0 + per < tiles ? t0 + per : tiles;
+}
+
+// Eight float32 values v as three bfloat16 vectors with hi + mid + lo = v
+// exactly: hi keeps the leading 8 significant bits of v (truncated), mid
+// the leading 8 of the remainder v - hi (exact in float32), and lo the
+// rest, at most 8 significant bits and so a bfloat16 itself.  The products
+// on the matrix cores then see the float32 operand unchanged.
+__device__ __forceinline__ void split3_bf16(const f4& a, const f4& b, bf16x8& hi, bf16x8& mid,
+                                            bf16x8& lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float v = e < 4 ? a[e] : b[e - 4];
+        const uint32_t uh = __float_as_uint(v) & 0xFFFF0000u;
+        const float r = v - __uint_as_float(uh);
+        const uint32_t um = __float_as_uint(r) & 0xFFFF0000u;
+        const uint32_t ul = __float_as_uint(r - __uint_as_float(um));
+        hi[e] = __builtin_bit_cast(__bf16, (uint16_t)(uh >> 16));
+        mid[e] = __builtin_bit_cast(__bf16, (uint16_t)(um >> 16));
+        lo[e] = __builtin_bit_cast(__bf16, (uint16_t)(ul >> 16));
+    }
+}
+
+// Operand A of the transposed convolution by the layer weights at wo, for
+// this lane: row ci = m; elements e = 0..7 are k = 32 j + 8 kk + e, i.e.
+// output channel 8 (kk & 1) + e of tap 2 j + (kk >> 1) (zero past the fifth).
+__device__ __forceinline__ bf16x8 weights_t(const float* wexp, int wo, int m, int kk, int j) {
+    bf16x8 a;
+    const int tap = 2 * j + (kk >> 1);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int co = 8 * (kk & 1) + e;
+        a[e] = (__bf16)(tap < NTB ? wexp[wo + (co * C + m) * NTB + tap] : 0.f);
+    }
+    return a;
+}
+
+// Layer 1 (mask A, 1 -> C, ReLU) from the int8 spins times sign: thread i
+// computes channels 4 (i & 3) .. + 3 of site i >> 2.  Also clears the 64
+// zero bytes that the later passes read for taps outside the lattice.
+__global__ void k_nn_fwd1(const int8_t* s, int64_t stride, int total, int N, int L, float sign,
+                          const float* __restrict__ w, float* __restrict__ h1,
+                          float* __restrict__ zero) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C)
+        zero[i] = 0.f;
+    if (i >= (int64_t)total * 4)
+        return;
+    const int e = (int)(i >> 2), c0 = 4 * (int)(i & 3);
+    const int b = e / N, p = e - b * N;
+    const TSite q{p / L, p % L};
+    const int8_t* sb = s + (int64_t)b * stride;
+    float in[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        in[t] = tinside(q, L, tap_dy(t), tap_dx(t))
+                    ? sign * (float)sb[p + tap_dy(t) * L + tap_dx(t)]
+                    : 0.f;
+    f4 out;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float a = w[NNOff::B1 + c0 + c];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            a = fmaf(w[NNOff::W1 + (c0 + c) * 4 + t], in[t], a);
+        out[c] = fmaxf(a, 0.f);
+    }
+    *reinterpret_cast<f4*>(h1 + (size_t)e * C + c0) = out;
+}
+
+// Layers 2 and 3 (mask B, C -> C, ReLU): each wave takes a contiguous run
+// of 16-site tiles.  Lane (m, kk) gathers the eight input channels
+// 8 (kk & 1) .. of tap 2 j + (kk >> 1) of site m for product j, and
+// receives output channels 4 kk .. 4 kk + 3 of site m.  Loads are
+// unconditional (a tap outside the lattice reads `zero`, 64 zero bytes),
+// so that the loads of a tile are in flight together.
+__global__ void __launch_bounds__(256) k_nn_fwd_mid(const float* __restrict__ hin,
+                                                    const float* __restrict__ zero, int total,
+                                                    int N, int L, const float* __restrict__ wexp,
+                                                    int wo, int bo, float* __restrict__ hout) {
+    const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    bf16x8 wa[3];
+    int off[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        wa[j] = weights_b(wexp, wo, m, kk, j);
+        const int tap = 2 * j + (kk >> 1);
+        off[j] = tap < NTB ? tap_dy(tap) * L + tap_dx(tap) : 0;
+    }
+    f4 bias;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        bias[v] = wexp[bo + 4 * kk + v];
+    int t0, t1;
+    tile_run((total + kTile - 1) / kTile, blockIdx.x * (blockDim.x >> 6) + w,
+             gridDim.x * (blockDim.x >> 6), t0, t1);
+    if (t0 >= t1)
+        return;
+    RunSite q;
+    q.start(t0 * kTile + m, N, L);
+    for (int tile = t0; tile < t1; ++tile) {
+        const bool on = q.e < total;
+        f4 hi = {0.f, 0.f, 0.f, 0.f}, mid = hi, lo = hi;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const bool ok = on && q.tap_ok(2 * j + (kk >> 1), L);
+            const f4* src = reinterpret_cast<const f4*>(
+                (ok ? hin + (size_t)(q.e + off[j]) * C : zero) + 8 * (kk & 1));
+            const f4 v0 = src[0], v1 = src[1];
+            bf16x8 bh, bm, bl;
+            split3_bf16(v0, v1, bh, bm, bl);
+            hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bh, hi, 0, 0, 0);
+            mid = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bm, mid, 0, 0, 0);
+            lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bl, lo, 0, 0, 0);
+        }
+        f4 d = hi + (mid + lo) + bias;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            d[v] = fmaxf(d[v], 0.f);
+        if (on)
+            *reinterpret_cast<f4*>(hout + (size_t)q.e * C + 4 * kk) = d;
+        q.advance(kTile, N, L);
+    }
+}
+
+// Layer 4 (mask B, C -> 1) and the likelihood: one workgroup per batch
+// element.  logq[b] = sum_p log sigmoid(s_p z_p); with dz, also
+// dz[b][p] = d(-mean_b log q)/dz_p = -s_p sigmoid(-s_p z_p) / B.  The
+// configuration is sign * s (sign = -1 evaluates the negated lattice).
+__global__ void k_nn_out(const float* __restrict__ h3, const int8_t* s, int64_t stride, int B, int L,
+                         float sign, const float* __restrict__ w, float* logq, float* dz) {
+    __shared__ float red[16];
+    const int N = L * L, b = blockIdx.x;
+    const float* xb = h3 + (size_t)b * N * C;
+    const int8_t* sb = s + (int64_t)b * stride;
+    float lq = 0.f;
+    for (int p = threadIdx.x; p < N; p += blockDim.x) {
+        const TSite q{p / L, p % L};
+        float z = w[NNOff::B4];
+#pragma unroll
+        for (int t = 0; t < NTB; ++t) {
+            if (!tinside(q, L, tap_dy(t), tap_dx(t)))
+                continue;
+            const f4* src =
+                reinterpret_cast<const f4*>(xb + (size_t)(p + tap_dy(t) * L + tap_dx(t)) * C);
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) {
+                const f4 a = src[c4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    z = fmaf(w[NNOff::W4 + (4 * c4 + c) * NTB + t], a[c], z);
+            }
+        }
+        const float sp = sign * (float)sb[p];
+        lq += log_sigmoid(sp * z);
+        if (dz)
+            dz[(size_t)b * N + p] = -sp / (1.f + expf(sp * z)) / (float)B;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        lq += __shfl_xor(lq, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = lq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i)
+            t += red[i];
+        logq[b] = t;
+    }
+}
+
+// Mean negative log-likelihood from logq[0..B-1] in a fixed order.
+__global__ void k_nn_loss(const float* logq, int B, float* loss) {
+    __shared__ float red[4];
+    float t = 0.f;
+    for (int b = threadIdx.x; b < B; b += blockDim.x)
+        t += logq[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        t += __shfl_xor(t, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *loss = -(red[0] + red[1] + red[2] + red[3]) / (float)B;
+}
+
+// Gradient into the input of layer 4: g3[e][ci] = [h3 > 0] sum_t W4[ci][t]
+// dz[e - d_t]; thread i computes channels 4 (i & 3) .. + 3 of site i >> 2.
+__global__ void k_nn_bwd_out(const float* __restrict__ dz, const float* __restrict__ h3, int total,
+                             int N, int L, const float* __restrict__ w, float* __restrict__ g3) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)total * 4)
+        return;
+    const int e = (int)(i >> 2), c0 = 4 * (int)(i & 3);
+    const TSite q = tsite(e, N, L);
+    float g[NTB];
+#pragma unroll
+    for (int t = 0; t < NTB; ++t)
+        g[t] = tinside(q, L, -tap_dy(t), -tap_dx(t)) ? dz[e - tap_dy(t) * L - tap_dx(t)] : 0.f;
+    const f4 h = *reinterpret_cast<const f4*>(h3 + (size_t)e * C + c0);
+    f4 o;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float a = 0.f;
+#pragma unroll
+        for (int t = 0; t < NTB; ++t)
+            a = fmaf(w[NNOff::W4 + (c0 + c) * NTB + t], g[t], a);
+        o[c] = h[c] > 0.f ? a : 0.f;
+    }
+    *reinterpret_cast<f4*>(g3 + (size_t)e * C + c0) = o;
+}
+
+// Gradient into the input of layer 3 or 2 (the transposed convolution):
+// gprev[e][ci] = [hprev > 0] sum_{t, co} W[co][ci][t] gout[e - d_t][co],
+// organised as k_nn_fwd_mid.
+__global__ void __launch_bounds__(256) k_nn_bwd_mid(const float* __restrict__ gout,
+                                                    const float* __restrict__ zero,
+                                                    const float* __restrict__ hprev, int total,
+                                                    int N, int L, const float* __restrict__ wexp,
+                                                    int wo, float* __restrict__ gprev) {
+    const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    bf16x8 wa[3];
+    int off[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        wa[j] = weights_t(wexp, wo, m, kk, j);
+        const int tap = 2 * j + (kk >> 1);
+        off[j] = tap < NTB ? -(tap_dy(tap) * L + tap_dx(tap)) : 0;
+    }
+    int t0, t1;
+    tile_run((total + kTile - 1) / kTile, blockIdx.x * (blockDim.x >> 6) + w,
+             gridDim.x * (blockDim.x >> 6), t0, t1);
+    if (t0 >= t1)
+        return;
+    RunSite q;
+    q.start(t0 * kTile + m, N, L);
+    for (int tile = t0; tile < t1; ++tile) {
+        const bool on = q.e < total;
+        f4 hi = {0.f, 0.f, 0.f, 0.f}, mid = hi, lo = hi;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const bool ok = on && q.tap_ok_rev(2 * j + (kk >> 1), L);
+            const f4* src = reinterpret_cast<const f4*>(
+                (ok ? gout + (size_t)(q.e + off[j]) * C : zero) + 8 * (kk & 1));
+            const f4 v0 = src[0], v1 = src[1];
+            bf16x8 bh, bm, bl;
+            split3_bf16(v0, v1, bh, bm, bl);
+            hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bh, hi, 0, 0, 0);
+            mid = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bm, mid, 0, 0, 0);
+            lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bl, lo, 0, 0, 0);
+        }
+        if (on) {
+            f4 d = hi + (mid + lo);
+            const f4 h = *reinterpret_cast<const f4*>(hprev + (size_t)q.e * C + 4 * kk);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                d[v] = h[v] > 0.f ? d[v] : 0.f;
+            *reinterpret_cast<f4*>(gprev + (size_t)q.e * C + 4 * kk) = d;
+        }
+        q.advance(kTile, N, L);
+    }
+}
+
+// Weight gradient of one layer, partial sums per workgroup: dW[co][ci][t] =
+// sum_e g[e][co] x[e + d_t][ci] and db[co] = sum_e g[e][co] over the
+// workgroup's sites, written into row blockIdx.x of partial[rows][P] at
+// the layer's parameter offsets wo and bo.  Each product takes four sites
+// k: A[co][k] = g of site k, B[k][ci] = x at tap t of site k; lane (m, kk)
+// loads channel m of site kk of both and receives D[4 kk + v][m].  Each
+// wave takes a contiguous run of 16-site tiles; loads are unconditional as
+// in k_nn_fwd_mid (lanes without a value read `zero`).
+// kCout = C: g is [B][N][C]; kCout = 1 (layer 4): g is dz, [B][N].
+// kIn = C: x is [B][N][C], one product per tap; kIn = 1 (layer 1): x is the
+// int8 spins, the four taps of mask A in the columns of one product.
+template <int kCout, int kIn>
+__global__ void __launch_bounds__(256) k_nn_wgrad(const float* __restrict__ g,
+                                                  const float* __restrict__ zero,
+                                                  const float* __restrict__ x,
+                                                  const int8_t* __restrict__ s, int64_t stride,
+                                                  int total, int N, int L, int wo, int bo, int P,
+                                                  float* __restrict__ partial) {
+    constexpr int kT = kIn == 1 ? 1 : NTB;
+    __shared__ float red[4][4 * kT + 1][64];
+    const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    f4 acc[kT];
+#pragma unroll
+    for (int t = 0; t < kT; ++t)
+        acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    float accb = 0.f;
+    int off[NTB];
+#pragma unroll
+    for (int t = 0; t < NTB; ++t)
+        off[t] = tap_dy(t) * L + tap_dx(t);
+    // layer 1: column m holds tap m of mask A
+    const int off1 = m < 4 ? tap_dy(m) * L + tap_dx(m) : 0;
+    int t0, t1;
+    tile_run((total + kTile - 1) / kTile, blockIdx.x * 4 + w, gridDim.x * 4, t0, t1);
+    if (t0 < t1) {
+        RunSite q;
+        q.start(t0 * kTile + kk, N, L);
+        for (int k4 = 4 * t0; k4 < 4 * t1; ++k4) {
+            const bool on = q.e < total;
+            const float a = kCout == 1 ? *(on && m == 0 ? g + q.e : zero)
+                                       : *(on ? g + (size_t)q.e * C + m : zero);
+            accb += a;
+            if constexpr (kIn == 1) {
+                const bool ok = on && m < 4 && q.tap_ok(m, L);
+                const float bv = (float)*(ok ? s + (int64_t)q.b * stride + q.p + off1
+                                             : reinterpret_cast<const int8_t*>(zero));
+                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[0], 0, 0, 0);
+            } else {
+                float bv[NTB];
+#pragma unroll
+                for (int t = 0; t < NTB; ++t) {
+                    const bool ok = on && q.tap_ok(t, L);
+                    bv[t] = *(ok ? x + (size_t)(q.e + off[t]) * C + m : zero);
+                }
+#pragma unroll
+                for (int t = 0; t < NTB; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[t], acc[t], 0, 0, 0);
+            }
+            q.advance(4, N, L);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            red[w][4 * t + v][lane] = acc[t][v];
+    red[w][4 * kT][lane] = accb;
+    __syncthreads();
+    if (w != 0)
+        return;
+    float* out = partial + (size_t)blockIdx.x * P;
+#pragma unroll
+    for (int t = 0; t < kT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 4 * t + v, co = 4 * kk + v;
+            const float d = ((red[0][r][lane] + red[1][r][lane]) + red[2][r][lane]) + red[3][r][lane];
+            if (kIn == 1) {
+                if (m < 4)
+                    out[wo + co * 4 + m] = d;
+            } else if (kCout == 1) {
+                if (co == 0)
+                    out[wo + m * NTB + t] = d;
+            } else {
+                out[wo + (co * C + m) * NTB + t] = d;
+            }
+        }
+    float bs = ((red[0][4 * kT][lane] + red[1][4 * kT][lane]) + red[2][4 * kT][lane]) +
+               red[3][4 * kT][lane];
+    bs += __shfl_xor(bs, 16, 64);
+    bs += __shfl_xor(bs, 32, 64);
+    if (kk == 0 && (kCout != 1 || m == 0))
+        out[bo + m] = bs;
+}
+
+// grad[i] = sum over rows r of partial[r][i] in a fixed order: thread
+// (o, seg) sums rows seg, seg + 8, .. of output 32 blockIdx.x + o, and the
+// eight segments are added in order.
+__global__ void k_nn_reduce(const float* __restrict__ partial, int rows, int P,
+                            float* __restrict__ grad) {
+    __shared__ float red[8][32];
+    const int o = threadIdx.x & 31, seg = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + o;
+    float t = 0.f;
+    if (i < P) {
+#pragma unroll 8
+        for (int r = seg; r < rows; r += 8)
+            t += partial[(size_t)r * P + i];
+    }
+    red[seg][o] = t;
+    __syncthreads();
+    if (seg == 0 && i < P) {
+        float u = red[0][o];
+#pragma unroll
+        for (int k = 1; k < 8; ++k)
+            u += red[k][o];
+        grad[i] = u;
     }
 }
 
@@ -714,19 +945,33 @@ NNWs nn_ws_layout(int L, int max_batch) {
     o += up((size_t)max_batch * N * 4);
     w.logq = o;
     o += up((size_t)max_batch * 4);
-    w.chunks = nn_wgrad_chunks(L, max_batch);
+    w.zero = o;
+    o += up((size_t)C * 4);
+    w.rows = nn_grad_rows(L, max_batch);
     w.partial = o;
-    o += up((size_t)w.chunks * C * (C * NTB + 1) * 4);
+    o += up((size_t)w.rows * NNOff::P * 4);
     w.bytes = o;
     return w;
 }
 
 int nn_param_count() { return NNOff::P; }
 
-int nn_wgrad_chunks(int L, int B) {
-    const int64_t total = (int64_t)B * L * L;
-    return (int)((total + kNNWgradPerBlock - 1) / kNNWgradPerBlock);
+int nn_grad_rows(int L, int B) {
+    const int64_t tiles = ((int64_t)B * L * L + kTile - 1) / kTile;
+    const int64_t wgs = (tiles + 3) / 4;
+    return (int)(wgs < kNNGradBlocks ? wgs : kNNGradBlocks);
 }
+
+namespace {
+// Workgroups of 256 threads for a pass of one wave per 16-site tile.
+dim3 tile_grid(int total) {
+    const int tiles = (total + kTile - 1) / kTile;
+    const int wgs = (tiles + 3) / 4;
+    return dim3((unsigned)(wgs < 2048 ? wgs : 2048));
+}
+// One thread per 4 channels of a site.
+dim3 quad_grid(int total) { return dim3((unsigned)(((int64_t)total * 4 + 255) / 256)); }
+}  // namespace
 
 hipError_t launch_nn_round(const float* master, uint16_t* w, float* wexp, hipStream_t st) {
     hipLaunchKernelGGL(k_nn_round, dim3((NNOff::P + 255) / 256), dim3(256), 0, st, master, w, wexp,
@@ -740,13 +985,14 @@ hipError_t launch_nn_forward(const int8_t* s, int64_t stride, int B, int L, cons
     const float* wexp = reinterpret_cast<const float*>(ws + lay.wexp);
     float* h[3] = {reinterpret_cast<float*>(ws + lay.h[0]), reinterpret_cast<float*>(ws + lay.h[1]),
                    reinterpret_cast<float*>(ws + lay.h[2])};
-    const int64_t total = (int64_t)B * L * L;
-    const dim3 grid((unsigned)((total + 255) / 256));
-    hipLaunchKernelGGL(k_nn_fwd1, grid, dim3(256), 0, st, s, stride, B, L, sign, wexp, h[0]);
-    hipLaunchKernelGGL(k_nn_fwd_mid, grid, dim3(256), 0, st, h[0], B, L, wexp, NNOff::W2,
-                       NNOff::B2, h[1]);
-    hipLaunchKernelGGL(k_nn_fwd_mid, grid, dim3(256), 0, st, h[1], B, L, wexp, NNOff::W3,
-                       NNOff::B3, h[2]);
+    float* zero = reinterpret_cast<float*>(ws + lay.zero);
+    const int N = L * L, total = B * N;
+    hipLaunchKernelGGL(k_nn_fwd1, quad_grid(total), dim3(256), 0, st, s, stride, total, N, L, sign,
+                       wexp, h[0], zero);
+    hipLaunchKernelGGL(k_nn_fwd_mid, tile_grid(total), dim3(256), 0, st, h[0], zero, total, N, L,
+                       wexp, NNOff::W2, NNOff::B2, h[1]);
+    hipLaunchKernelGGL(k_nn_fwd_mid, tile_grid(total), dim3(256), 0, st, h[1], zero, total, N, L,
+                       wexp, NNOff::W3, NNOff::B3, h[2]);
     hipLaunchKernelGGL(k_nn_out, dim3(B), dim3(256), 0, st, h[2], s, stride, B, L, sign, wexp, logq,
                        with_dz ? reinterpret_cast<float*>(ws + lay.dz) : nullptr);
     return hipGetLastError();
@@ -761,39 +1007,34 @@ hipError_t launch_nn_backward(const int8_t* s, int64_t stride, int B, int L, con
     float* g[2] = {reinterpret_cast<float*>(ws + lay.g[0]), reinterpret_cast<float*>(ws + lay.g[1])};
     const float* dz = reinterpret_cast<const float*>(ws + lay.dz);
     float* partial = reinterpret_cast<float*>(ws + lay.partial);
-    const int64_t total = (int64_t)B * L * L;
-    const dim3 grid((unsigned)((total + 255) / 256));
-    const int chunks = nn_wgrad_chunks(L, B);
-    const int per = kNNWgradPerBlock / 256;
-    constexpr int KB = C * NTB + 1, KA = 4 + 1, K4 = C * NTB + 1;
+    const float* zero = reinterpret_cast<const float*>(ws + lay.zero);
+    const int N = L * L, total = B * N, P = NNOff::P;
+    // every layer's weight-gradient pass fills its parameters' columns of
+    // the same rows of partial, so one reduction gives the whole gradient
+    const dim3 rows(nn_grad_rows(L, B));
     if (loss)
         hipLaunchKernelGGL(k_nn_loss, dim3(1), dim3(256), 0, st,
                            reinterpret_cast<const float*>(ws + lay.logq), B, loss);
     // layer 4: weights from dz and h3, then the gradient into h3
-    hipLaunchKernelGGL((k_nn_wgrad<C, NTB>), dim3(chunks, 1), dim3(256), 0, st, dz, 1, h[2], s,
-                       stride, B, L, per, partial);
-    hipLaunchKernelGGL(k_nn_reduce, dim3((K4 + 255) / 256), dim3(256), 0, st, partial, chunks, 1, K4,
-                       grad, NNOff::W4, NNOff::B4);
-    hipLaunchKernelGGL(k_nn_bwd_out, grid, dim3(256), 0, st, dz, h[2], B, L, wexp, g[0]);
-    // layer 3: g[0] is the gradient at its pre-activation output
-    hipLaunchKernelGGL((k_nn_wgrad<C, NTB>), dim3(chunks, C), dim3(256), 0, st, g[0], C, h[1], s,
-                       stride, B, L, per, partial);
-    hipLaunchKernelGGL(k_nn_reduce, dim3((C * KB + 255) / 256), dim3(256), 0, st, partial, chunks, C,
-                       KB, grad, NNOff::W3, NNOff::B3);
-    hipLaunchKernelGGL(k_nn_bwd_mid, grid, dim3(256), 0, st, g[0], h[1], B, L, wexp, NNOff::W3,
-                       g[1]);
-    // layer 2
-    hipLaunchKernelGGL((k_nn_wgrad<C, NTB>), dim3(chunks, C), dim3(256), 0, st, g[1], C, h[0], s,
-                       stride, B, L, per, partial);
-    hipLaunchKernelGGL(k_nn_reduce, dim3((C * KB + 255) / 256), dim3(256), 0, st, partial, chunks, C,
-                       KB, grad, NNOff::W2, NNOff::B2);
-    hipLaunchKernelGGL(k_nn_bwd_mid, grid, dim3(256), 0, st, g[1], h[0], B, L, wexp, NNOff::W2,
+    hipLaunchKernelGGL((k_nn_wgrad<1, C>), rows, dim3(256), 0, st, dz, zero, h[2], s, stride, total,
+                       N, L, NNOff::W4, NNOff::B4, P, partial);
+    hipLaunchKernelGGL(k_nn_bwd_out, quad_grid(total), dim3(256), 0, st, dz, h[2], total, N, L, wexp,
                        g[0]);
+    // layer 3: g[0] is the gradient at its pre-activation output
+    hipLaunchKernelGGL((k_nn_wgrad<C, C>), rows, dim3(256), 0, st, g[0], zero, h[1], s, stride,
+                       total, N, L, NNOff::W3, NNOff::B3, P, partial);
+    hipLaunchKernelGGL(k_nn_bwd_mid, tile_grid(total), dim3(256), 0, st, g[0], zero, h[1], total, N,
+                       L, wexp, NNOff::W3, g[1]);
+    // layer 2
+    hipLaunchKernelGGL((k_nn_wgrad<C, C>), rows, dim3(256), 0, st, g[1], zero, h[0], s, stride,
+                       total, N, L, NNOff::W2, NNOff::B2, P, partial);
+    hipLaunchKernelGGL(k_nn_bwd_mid, tile_grid(total), dim3(256), 0, st, g[1], zero, h[0], total, N,
+                       L, wexp, NNOff::W2, g[0]);
     // layer 1 (input: the spins)
-    hipLaunchKernelGGL((k_nn_wgrad<1, 4>), dim3(chunks, C), dim3(256), 0, st, g[0], C, nullptr, s,
-                       stride, B, L, per, partial);
-    hipLaunchKernelGGL(k_nn_reduce, dim3((C * KA + 255) / 256), dim3(256), 0, st, partial, chunks, C,
-                       KA, grad, NNOff::W1, NNOff::B1);
+    hipLaunchKernelGGL((k_nn_wgrad<C, 1>), rows, dim3(256), 0, st, g[0], zero, nullptr, s, stride,
+                       total, N, L, NNOff::W1, NNOff::B1, P, partial);
+    hipLaunchKernelGGL(k_nn_reduce, dim3((P + 31) / 32), dim3(256), 0, st, partial, (int)rows.x, P,
+                       grad);
     return hipGetLastError();
 }
 
