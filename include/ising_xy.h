@@ -58,7 +58,9 @@ typedef struct ising_xy {
 
 /* Workspace of count lattices of side L: sweep index, accepted-rotation
  * counters, error word, the per-lattice energy sums of the large-lattice
- * sweep and, for L > 80, the cosine and sine of every angle (16 B per site).
+ * sweep and, for L > 80, the cosine and sine of every angle (16 B per site)
+ * and the hand-off slots of the band-tiled sweep (64 L bytes per band, for
+ * at most min(count L / 2, 2048) bands).
  * 0 for L or count out of range.  The library cannot check the size it is
  * given: a smaller workspace is undefined behaviour. */
 ISING_API size_t ising_xy_workspace_bytes(int32_t L, int32_t count);
@@ -71,9 +73,13 @@ ISING_API int ising_xy_init(const ising_xy *xy, int32_t start, void *hip_stream)
  * sweep index; E_trace_dev (device double[n][count], may be NULL)
  * receives H of every lattice after every sweep: H summed over the
  * lattice at the start of the call, plus the energy changes of the trials
- * accepted since (equal to a recount up to rounding).  Errors: invalid
- * description, beta negative or not finite, n < 0 -> ISING_E_INVALID;
- * device: workspace not initialised or t + n > 2^31 (see
+ * accepted since (equal to a recount up to rounding).  Fewer lattices
+ * than compute units with L > 32, or L > 80, run as bands of rows resident
+ * for the whole call (one launch), handing edge rows to each other; many
+ * lattices of L > 80 run one launch per half-sweep.  The chain is the same
+ * in every form.  Errors: invalid description, beta negative or not
+ * finite, n < 0 -> ISING_E_INVALID; device: workspace not initialised,
+ * t + n > 2^31, or a band waited too long for a neighbour (see
  * ising_xy_check_device_error). */
 ISING_API int ising_xy_sweep(const ising_xy *xy, double beta, int64_t n, double *E_trace_dev,
                              void *hip_stream);

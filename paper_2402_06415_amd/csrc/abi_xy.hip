@@ -117,9 +117,10 @@ int ising_xy_check_device_error(const ising_xy* xy, void* hip_stream) {
         const uint32_t zero = 0;
         HIP_TRY(hipMemcpyAsync(errp, &zero, 4, hipMemcpyHostToDevice, st), "clear error word");
         HIP_TRY(hipStreamSynchronize(st), "synchronise");
-        return set_error(ISING_E_STATE, "XY device error word 0x%x:%s%s", err,
+        return set_error(ISING_E_STATE, "XY device error word 0x%x:%s%s%s", err,
                          (err & ising::kXyErrNotInit) ? " workspace not initialised;" : "",
-                         (err & ising::kXyErrSweepIndex) ? " sweep index + n exceeds 2^31;" : "");
+                         (err & ising::kXyErrSweepIndex) ? " sweep index + n exceeds 2^31;" : "",
+                         (err & ising::kXyErrHandoff) ? " hand-off between bands timed out;" : "");
     }
     return ISING_OK;
 }

@@ -6,9 +6,9 @@
 // half-sweep that produced it plus one.  A reader polls its own word until
 // the tag is the one it expects, so each hand-off involves a single memory
 // location (relaxed agent-scope atomics: no cache write-back or
-// invalidation, no grid-wide barrier).  Waits are bounded: on time-out the
-// device error word is set and the word read last is used, so the kernel
-// still runs to completion.
+// invalidation, no grid-wide barrier).  Waits are bounded: on time-out
+// `code` is or-ed into the device error word and the word read last is
+// used, so the kernel still runs to completion.
 #pragma once
 
 #include "common.hpp"
@@ -16,7 +16,7 @@
 namespace ising {
 
 __device__ __forceinline__ uint32_t wait_slot(const unsigned long long* slot, uint32_t tag,
-                                              uint32_t limit, uint32_t* err) {
+                                              uint32_t limit, uint32_t* err, uint32_t code = 1u) {
     uint32_t spins = 0;
     unsigned long long v;
     for (;;) {
@@ -24,7 +24,7 @@ __device__ __forceinline__ uint32_t wait_slot(const unsigned long long* slot, ui
         if ((uint32_t)(v >> 32) == tag)
             break;
         if (++spins > limit) {
-            atomicOr(err, 1u);
+            atomicOr(err, code);
             break;
         }
         __builtin_amdgcn_s_sleep(1);

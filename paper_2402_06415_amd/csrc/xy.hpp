@@ -8,6 +8,7 @@ namespace ising {
 constexpr uint32_t kXyMagic = 0x31595849u;   // "IXY1"
 constexpr uint32_t kXyErrNotInit = 1u;
 constexpr uint32_t kXyErrSweepIndex = 4u;
+constexpr uint32_t kXyErrHandoff = 8u;  // a band waited too long for a neighbour
 constexpr size_t kXyAccepted = 256;          // uint64[count]: accepted rotations
 // double[2][count]: per-lattice energy sums of the global-memory sweep
 inline size_t xy_energy_sums_offset(int count) {

@@ -269,13 +269,19 @@ def test_invalid_spin_glasses_are_rejected_before_any_launch(kw, msg):
 
 
 def test_xy_workspace_bytes():
-    """The large-lattice sweep (L > 80) keeps 16 B of cosine and sine per site."""
+    """Above L = 32 the workspace adds 64 L bytes of hand-off slots per band
+    of the band-tiled form, for at most min(count L / 2, 2048) bands, and
+    above L = 80 16 B of cosine and sine per site (the per-half-sweep form)."""
     assert lib.ising_xy_workspace_bytes(1, 10) == 0
     assert lib.ising_xy_workspace_bytes(130, 10) == 0
     assert lib.ising_xy_workspace_bytes(32, 0) == 0
     assert lib.ising_xy_workspace_bytes(32, 4097) == 0
-    small = lib.ising_xy_workspace_bytes(80, 10)
+    small = lib.ising_xy_workspace_bytes(32, 10)
     assert small > 0 and small % 256 == 0
     assert lib.ising_xy_workspace_bytes(2, 10) == small
-    assert lib.ising_xy_workspace_bytes(82, 10) == small + 10 * 82 * 82 * 16
-    assert lib.ising_xy_workspace_bytes(128, 4096) >= 4096 * 128 * 128 * 16
+    assert lib.ising_xy_workspace_bytes(34, 10) == small + 10 * 17 * 64 * 34
+    assert lib.ising_xy_workspace_bytes(80, 10) == small + 10 * 40 * 64 * 80
+    trig = -(-10 * 82 * 82 * 16 // 256) * 256
+    assert lib.ising_xy_workspace_bytes(82, 10) == small + trig + 10 * 41 * 64 * 82
+    big = lib.ising_xy_workspace_bytes(128, 4096)
+    assert big == lib.ising_xy_workspace_bytes(2, 4096) + 4096 * 128 * 128 * 16 + 2048 * 64 * 128

@@ -3,8 +3,9 @@
 Both sides draw the same Philox trials and form the energy change in
 double precision without fused multiply-adds: the oracle as the sum of
 eight cosines of angle differences, the kernel through cached cos/sin of
-every angle and the angle-difference identity (in LDS up to L = 80, in
-global memory above).  The two agree to a few units in the last place, so the angles
+every angle and the angle-difference identity (in LDS, one workgroup per
+lattice or one per band of rows, or in global memory for many large
+lattices).  The two agree to a few units in the last place, so the angles
 must agree bit for bit: a decision could only differ where p lies that
 close to the acceptance probability (probability ~1e-15 per trial).  The
 energy trace is a recount at the start of each call plus the accepted
@@ -81,21 +82,44 @@ def test_xy_beta_cases(beta):
     _compare(8, 2, beta, 5, (6,), start="cold" if beta == 20.0 else "random")
 
 
-@pytest.mark.parametrize("L", [64, 80, 82, 84])
-def test_xy_cos_sin_cache_boundary(L):
-    """L = 80 is the largest side whose angles, cosines and sines fit LDS
-    together (150 KiB); L = 82 and 84 take the global-memory form, whose
-    cosines and sines are refilled from the angles at each of the two
-    calls."""
+@pytest.mark.parametrize("L", [34, 64, 80, 82, 84])
+def test_xy_band_tiled_form(L):
+    """Two lattices (fewer than compute units) of 32 < L <= 128 take the
+    band-tiled form: bands of rows resident for the whole call, the edge
+    rows' cosines and sines handed over through tagged slots, refilled from
+    the angles at each of the two calls.  L = 34 and 82 have only bands of
+    two rows (L/2 prime)."""
     _compare(L, 2, BETA_XY, 13, (4, 3), lid0=1)
+
+
+def test_xy_one_workgroup_form_above_l32():
+    """As many lattices as compute units keep one workgroup per lattice up
+    to L = 80 (angles, cosines and sines in LDS, 150 KiB at L = 80): three
+    sampled lattices of 48 equal the oracle's bit for bit."""
+    L, seed, lid0 = 48, 23, 3
+    count = torch.cuda.get_device_properties(0).multi_processor_count
+    say(f"xy one workgroup L={L} count={count}")
+    g = lib.XYLattices(L, count, seed=seed, lattice_id0=lid0, start="random")
+    picks = (0, count // 2, count - 1)
+    th = {j: oracle.xy_init(L, oracle.START_RANDOM, seed, lid0 + j) for j in picks}
+    t = 0
+    for n in (3, 2):
+        E = _host(g.sweep(BETA_XY, n))
+        for j in picks:
+            Eo, _ = oracle.xy_sweep(th[j], seed, lid0 + j, t, n, BETA_XY)
+            assert np.allclose(E[:, j], Eo, rtol=0, atol=1e-12 * 2 * L * L), j
+        t += n
+        got = _host(g.theta[list(picks)])
+        for k, j in enumerate(picks):
+            assert (got[k] == th[j]).all(), f"lattice {j} after sweep {t}"
+    g.check()
 
 
 @pytest.mark.parametrize("L", [32, 96])
 def test_xy_trace_does_not_change_the_chain(L):
     """Sweeping without an energy trace skips all energy work; the angles
     must equal the traced run's bit for bit, and the trace's last entry the
-    recount (workgroup-resident form at L = 32, global-memory form at
-    L = 96)."""
+    recount (workgroup-resident form at L = 32, band-tiled form at L = 96)."""
     say(f"xy no trace L={L}")
     a = lib.XYLattices(L, 3, seed=17, start="random")
     b = lib.XYLattices(L, 3, seed=17, start="random")
