@@ -885,15 +885,15 @@ def main():
             L, torch.cuda.get_device_properties(0).multi_processor_count)
         tiles = kernel_name != "k_halfsweep_bit1"
     else:
-        # int8: one resident workgroup up to L = 128, tiles of rows in LDS
-        # up to L = 4096 (L % 8 == 0), else a launch per half-sweep
+        # int8: tiles of rows in LDS for 64 < L <= 4096 (L % 8 == 0), else
+        # one resident workgroup up to L = 128, else a launch per half-sweep
         span = L % 8 == 0 and L * L < (1 << 31)  # the byte-parallel span kernel
         if args.global_halfsweep:
             kernel_name = "k_halfsweep_int8_quad" if span else "k_halfsweep_int8"
+        elif 64 < L <= 4096 and L % 8 == 0:
+            kernel_name = "k_sweep_int8_tiles"
         elif L <= 128:
             kernel_name = "k_sweep_int8_resident"
-        elif L % 8 == 0 and L <= 4096:
-            kernel_name = "k_sweep_int8_tiles"
         else:
             kernel_name = "k_halfsweep_int8_quad" if span else "k_halfsweep_int8"
         tiles = kernel_name in ("k_sweep_int8_resident", "k_sweep_int8_tiles")

@@ -107,8 +107,9 @@ def test_parity_workload_L16_spins_after_every_sweep():
     _compare_stepwise(16, "int8", 1, "cold", BC, 300)
 
 
-@pytest.mark.parametrize("L", [4, 6, 10, 14, 64, 128])
+@pytest.mark.parametrize("L", [4, 6, 10, 14, 64, 122])
 def test_int8_resident_kernel(L):
+    # up to L = 64, and sides up to 128 that are not multiples of 8
     _compare_stepwise(L, "int8", 3, "random", BC, 40, chunk=7)
 
 
@@ -120,12 +121,12 @@ def test_int8_global_halfsweep_kernel(L):
 
 
 @pytest.mark.parametrize("record", [True, False])
-@pytest.mark.parametrize("L", [136, 200, 256, 1024, 4096])
+@pytest.mark.parametrize("L", [72, 128, 136, 200, 256, 1024, 4096])
 def test_int8_tile_kernel(L, record):
-    """INT8 lattices above the single-workgroup size with L % 8 == 0 run the
-    persistent tile kernel (tiles of full rows as bytes in LDS, tagged halo
-    hand-off of the edge rows' new bytes): one-row tiles at L = 136 and 200,
-    taller ones from L = 512 on."""
+    """INT8 lattices above L = 64 with L % 8 == 0 run the persistent tile
+    kernel (tiles of full rows as bytes in LDS, tagged halo hand-off of the
+    edge rows' new bytes): one-row tiles from L = 72 (nine spans a row) to
+    256, taller ones from L = 512 on."""
     _compare_stepwise(L, "int8", 11, "random", BC, 7 if L >= 4096 else 12, chunk=4,
                       record=record)
 
