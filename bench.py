@@ -298,9 +298,12 @@ def bench_batched(args):
             profiled_traffic(kernel, "batch_int8_1024", "batch_kernels.hip")) \
         if nsw == 10_000 else None
     traffic = (prof["hbm_read_bytes_per_launch"] + prof["hbm_write_bytes_per_launch"]) if prof else None
+    value = attempts / (ms_per_step * 1e6)
+    # plane draws: one 32-site word per lane-update
+    valu_per_word, ceiling = valu_ceiling(prof, spins // 32 * nsw) if plane else (None, None)
     rec = {
         "metric": METRIC,
-        "value": round(attempts / (ms_per_step * 1e6), 3),
+        "value": round(value, 3),
         "unit": "spin-flip attempts/ns",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
@@ -395,7 +398,7 @@ def bench_learned(args):
         torch.cuda.synchronize()
         return out, a.elapsed_time(b)
 
-    snaps = wl["train_configs"] // chains
+    snaps = -(-wl["train_configs"] // chains)  # at least train_configs configurations
     data, gen_ms = timed(lambda: plain_configurations(L, beta, chains, 2000, snaps, 10, seed=101))
     batch = 1024
     net = lib.Net(L, max(batch, chains), params=nn_initial_params(7))
