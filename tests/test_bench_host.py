@@ -1,6 +1,7 @@
-"""Host-side logic of bench.py that runs without a GPU: the one-GPU rule and
+"""Host-side logic of bench.py that runs without a GPU: the one-GPU rule,
 the rule that a committed HBM-traffic record is used only while the kernel
-sources it was measured on are unchanged."""
+sources it was measured on are unchanged, and that its functions read only
+names that exist."""
 import glob
 import json
 import os
@@ -58,3 +59,30 @@ def test_committed_traffic_records_are_complete():
         assert len(rec["kernel_source_sha256"]) == 64, path
         assert rec["hbm_read_bytes_per_launch"] > 0 and rec["hbm_write_bytes_per_launch"] > 0
         assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
+
+
+def test_bench_functions_read_only_defined_names():
+    """Every name a function of bench.py reads from the module scope is
+    defined there or is a builtin: the workloads other than the default
+    run only on a GPU, so a name left undefined in one of them would
+    otherwise surface only there."""
+    import builtins
+    import symtable
+
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    top = symtable.symtable(src, "bench.py", "exec")
+    module_names = {s.get_name() for s in top.get_symbols() if s.is_assigned() or s.is_imported()}
+    known = module_names | set(dir(builtins))
+    missing = []
+
+    def walk(table):
+        for child in table.get_children():
+            if child.get_type() == "function":
+                for s in child.get_symbols():
+                    if (s.is_referenced() and s.is_global() and not s.is_assigned()
+                            and s.get_name() not in known):
+                        missing.append(f"{child.get_name()}: {s.get_name()}")
+            walk(child)
+
+    walk(top)
+    assert not missing, missing
