@@ -61,18 +61,21 @@ def test_committed_traffic_records_are_complete():
         assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
 
 
-def test_bench_functions_read_only_defined_names():
-    """Every name a function of bench.py reads from the module scope is
-    defined there or is a builtin: the workloads other than the default
-    run only on a GPU, so a name left undefined in one of them would
-    otherwise surface only there."""
+@pytest.mark.parametrize("rel", ["bench.py", "__graft_entry__.py"] + sorted(
+    os.path.relpath(f, ROOT) for f in glob.glob(os.path.join(ROOT, "paper_2402_06415_amd", "*.py"))
+    + glob.glob(os.path.join(ROOT, "oracle", "*.py"))))
+def test_functions_read_only_defined_names(rel):
+    """Every name a function reads from its module's scope is defined there
+    or is a builtin (Python's symbol tables): bench.py's workloads other than
+    the default run only on a GPU, so a name left undefined in one of them
+    would otherwise surface only there; the same holds for the package."""
     import builtins
     import symtable
 
-    src = open(os.path.join(ROOT, "bench.py")).read()
-    top = symtable.symtable(src, "bench.py", "exec")
+    src = open(os.path.join(ROOT, rel)).read()
+    top = symtable.symtable(src, rel, "exec")
     module_names = {s.get_name() for s in top.get_symbols() if s.is_assigned() or s.is_imported()}
-    known = module_names | set(dir(builtins))
+    known = module_names | set(dir(builtins)) | {"__file__", "__name__"}
     missing = []
 
     def walk(table):
