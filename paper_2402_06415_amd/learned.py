@@ -75,16 +75,25 @@ class LearnedChains:
         self.accepted = torch.zeros(self.count, dtype=torch.int32, device=dev)
         self.n_accepted = torch.zeros(self.count, dtype=torch.int64, device=dev)
         self.draw = 0
+        # the proposals do not depend on the chains' states: the k sweeps
+        # run on a second stream (default priority) while the caller's
+        # stream draws the proposals
+        self.side = torch.cuda.Stream(device=dev)
 
     def cycle(self, trace=None):
         """k sweeps (E, M after each into trace [k, count, 2] if given), then one proposal."""
         import torch
 
-        self.batch.sweep(self.k, moments=False, trace=trace)
-        self.net.logq(self.batch, out=self.lq_cur, symmetric=self.symmetric)
+        main = torch.cuda.current_stream()
+        # the sweeps follow the previous cycle's acceptance step
+        self.side.wait_stream(main)
+        with torch.cuda.stream(self.side):
+            self.batch.sweep(self.k, moments=False, trace=trace)
         # the sampler's log q is bitwise the one logq() would give the proposal
         self.net.sample(self.count, self.seed, chain0=self.lid0, draw=self.draw, out=self.prop,
                         logq=self.lq_prop, symmetric=self.symmetric)
+        main.wait_stream(self.side)
+        self.net.logq(self.batch, out=self.lq_cur, symmetric=self.symmetric)
         ising_batch_mh(self.batch.c, self.L, self.prop.data_ptr(), self.L * self.L,
                        self.lq_cur.data_ptr(), self.lq_prop.data_ptr(), self.beta.data_ptr(),
                        self.draw, self.accepted.data_ptr(), torch.cuda.current_stream().cuda_stream)
