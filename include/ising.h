@@ -74,8 +74,9 @@ enum ising_start { ISING_START_COLD_UP = 0, ISING_START_RANDOM = 1 };
  * they exist so that each variant can be tested and timed. */
 enum ising_flags {
     /* one launch per half-sweep reading the spins from global memory,
-     * instead of the resident single-workgroup (INT8, L <= 128) or the
-     * persistent tile-resident (BIT1) kernel */
+     * instead of the resident single-workgroup (INT8, L <= 64, or
+     * L <= 128 when L % 8 != 0) or the persistent tile-resident kernels
+     * (BIT1; INT8 with L % 8 == 0 up to L = 4096) */
     ISING_FLAG_GLOBAL_HALFSWEEP = 1u,
     /* BIT1: count the Philox blocks the sweeps draw (ising_rng_blocks), a
      * diagnostic that costs a few instructions per word; without it the
