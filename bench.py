@@ -428,15 +428,22 @@ def bench_learned(args):
 
     _, learn_ms = timed(run_cycles)
     trl = tr.cpu().numpy()
-    # the dominant kernel of a cycle: the wavefront evaluation (here log q_sym
-    # of the current states, the same kernel as the sampler), timed alone
+    # the dominant kernel of a cycle: the wavefront sampler (the proposals
+    # and their log q_sym), timed alone; then the whole-lattice evaluation
+    # of log q_sym of the current states
     reps = 20
+    prop = torch.empty((chains, L, L), dtype=torch.int8, device=dev)
     lq = torch.empty(chains, dtype=torch.float32, device=dev)
-    net.logq(lc.batch, out=lq, symmetric=True)
-    _, wave_ms = timed(lambda: [net.logq(lc.batch, out=lq, symmetric=True) for _ in range(reps)])
+    net.sample(chains, 17, 0, 0, out=prop, logq=lq, symmetric=True)
+    _, wave_ms = timed(lambda: [net.sample(chains, 17, 0, d, out=prop, logq=lq, symmetric=True)
+                                for d in range(reps)])
     wave_ms /= reps
-    wave_tflops = (chains * 2 * N * (NN_WAVE_BF16_MAC_PER_SITE + NN_WAVE_F32_MAC_PER_SITE) * 2
-                   / (wave_ms * 1e-3) / 1e12)
+    net.logq(lc.batch, out=lq, symmetric=True)
+    _, lattice_ms = timed(lambda: [net.logq(lc.batch, out=lq, symmetric=True) for _ in range(reps)])
+    lattice_ms /= reps
+    nn_flop = chains * 2 * N * (NN_WAVE_BF16_MAC_PER_SITE + NN_WAVE_F32_MAC_PER_SITE) * 2
+    wave_tflops = nn_flop / (wave_ms * 1e-3) / 1e12
+    lattice_tflops = nn_flop / (lattice_ms * 1e-3) / 1e12
     rate = float(lc.n_accepted.sum().cpu()) / (cycles * chains)
     lc.batch.check()
 
@@ -523,13 +530,24 @@ def bench_learned(args):
             "bound": "mfma",
             "achieved": round(wave_tflops, 3), "peak": BF16_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(wave_tflops / BF16_MATRIX_PEAK_TFLOPS, 4), "traffic": None,
-            "kernel": "k_nn_wave (log q_sym of the current states: 2 waves per configuration)",
+            "kernel": "k_nn_wave (sampling: the proposals and their log q_sym, "
+                      "2 waves per configuration)",
             "kernel_ms": round(wave_ms, 4),
             "work": f"{chains} configurations x 2 signs x {N} sites x "
                     f"({NN_WAVE_BF16_MAC_PER_SITE} bfloat16 + {NN_WAVE_F32_MAC_PER_SITE} "
                     "float32 multiply-adds)",
             "note": f"{3 * L - 2} dependent anti-diagonal steps per configuration: the kernel "
                     "is bound by the latency of a step, not by the matrix cores' rate",
+        },
+        "logq_roofline": {
+            "bound": "mfma",
+            "achieved": round(lattice_tflops, 3), "peak": BF16_MATRIX_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(lattice_tflops / BF16_MATRIX_PEAK_TFLOPS, 4),
+            "traffic": None,
+            "kernel": "k_nn_lattice (log q_sym of the current states, a layer at a time over "
+                      "the whole lattice in LDS)",
+            "kernel_ms": round(lattice_ms, 4),
+            "work": "as roofline",
         },
         "training_roofline": {
             "bound": "hbm",

@@ -70,11 +70,14 @@ ISING_API size_t ising_nn_workspace_bytes(int32_t L, int32_t channels, int32_t m
 ISING_API int ising_nn_round_weights(const ising_nn *net, void *hip_stream);
 
 /* log q(s) of `batch` configurations: configuration b is the int8 L x L
- * row-major +1/-1 array at s_dev + b * stride (bytes, >= L*L).  The sites
- * are evaluated by the sampler's own code with the given spins in place of
- * draws (teacher forcing), so that for a configuration written by
- * ising_nn_sample with the same `symmetric` the result is bitwise the
- * logq_out the sampler returned.  With symmetric = 1 the result is
+ * row-major +1/-1 array at s_dev + b * stride (bytes, >= L*L).  With the
+ * spins given (teacher forcing) the sites need no order: up to L = 32 each
+ * configuration is held in LDS whole and evaluated a layer at a time over
+ * all sites, above that by the sampler's own wavefront code.  Either way
+ * every site's products, roundings and the order of the sum over sites are
+ * the sampler's, so that for a configuration written by ising_nn_sample
+ * with the same `symmetric` the result is bitwise the logq_out the sampler
+ * returned.  With symmetric = 1 the result is
  * log q_sym(s) = log((q(s) + q(-s)) / 2), the Z2-symmetrised proposal
  * (sample from q, negate the whole lattice with probability 1/2).
  * logq_dev: device float32[batch].  Errors: batch outside 1..max_batch,

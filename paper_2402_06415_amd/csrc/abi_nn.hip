@@ -88,10 +88,19 @@ int ising_nn_logq(const ising_nn* net, const int8_t* s_dev, int64_t stride, int3
     if (symmetric != 0 && symmetric != 1)
         return set_error(ISING_E_INVALID, "symmetric must be 0 or 1");
     const ising::NNWs lay = ising::nn_ws_layout(net->L, net->max_batch);
-    HIP_TRY(ising::launch_nn_wave(reinterpret_cast<const float*>(ws_of(net) + lay.wexp), net->L,
-                                  batch, 0, symmetric, s_dev, stride, ising::Key{0u, 0u}, 0u, 0u,
-                                  nullptr, 0, logq_dev, reinterpret_cast<hipStream_t>(hip_stream)),
-            "nn logq");
+    const float* wexp = reinterpret_cast<const float*>(ws_of(net) + lay.wexp);
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    // the whole lattice in LDS where it fits, else the sampler's wavefront
+    // in teacher-forcing mode: the same bits either way
+    const size_t lds = ising::nn_lattice_lds_bytes(net->L);
+    if (lds && lds <= (size_t)ising::abi::device_max_lds())
+        HIP_TRY(ising::launch_nn_lattice(wexp, net->L, batch, symmetric, s_dev, stride, logq_dev,
+                                         ising::abi::device_cus(), st),
+                "nn logq");
+    else
+        HIP_TRY(ising::launch_nn_wave(wexp, net->L, batch, 0, symmetric, s_dev, stride,
+                                      ising::Key{0u, 0u}, 0u, 0u, nullptr, 0, logq_dev, st),
+                "nn logq");
     return ISING_OK;
 }
 

@@ -48,6 +48,16 @@ hipError_t launch_nn_wave(const float* wexp, int L, int B, int sample, int symme
                           const int8_t* s_in, int64_t in_stride, Key key, uint32_t chain0,
                           uint32_t draw, int8_t* s_out, int64_t out_stride, float* logq,
                           hipStream_t st);
+// Teacher-forced log q (log q_sym with symmetric = 1) of B configurations
+// held whole in LDS, a layer at a time over all sites: bitwise the result
+// of launch_nn_wave for the same configuration.  2 <= L <= kNNLatticeMaxL;
+// nn_lattice_lds_bytes gives its LDS per workgroup (0 outside that range).
+// grid: workgroups (one per CU), each taking configurations blockIdx,
+// blockIdx + grid, ...
+constexpr int kNNLatticeMaxL = 32;
+size_t nn_lattice_lds_bytes(int L);
+hipError_t launch_nn_lattice(const float* wexp, int L, int B, int symmetric, const int8_t* s_in,
+                             int64_t in_stride, float* logq, int grid, hipStream_t st);
 hipError_t launch_batch_mh(unsigned char* ws, int count, int8_t* spins, int L_prop,
                            const int8_t* prop, int64_t pstride, const float* lq_cur,
                            const float* lq_prop, const double* beta, Key key, uint32_t draw,

@@ -28,6 +28,8 @@ static_assert(NNOff::P == 2753, "parameter layout");
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -106,7 +108,14 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
 // [hi of channels 4c..4c+3, lo of the same] for c = 0..3, which its four
 // lanes write with one 16-byte store each at the end of the step.  Rows
 // share R = floor((L+1)/2) + 1 ring entries: row y + R starts after row
-// y + 1 has read the last columns of row y.
+// y + 1 has read the last columns of row y.  The ring is stored as four
+// planes, one per lane group kk, each [layer][column][ring row] of 16
+// bytes: the 16 lanes of a group serve consecutive rows, whose entries are
+// then 16 bytes apart in one column, and the columns of neighbouring rows
+// (x and x - 2) are 2R entries apart, an even number, so that the lanes'
+// 16-byte pieces fall on distinct banks.  The spins use row stride L + 3
+// for the same reason (rows one apart, columns two apart: 33 words at
+// L = 32).
 //
 // With `symmetric`, a second wave evaluates the negated configuration in
 // step with the first, and the result is log q_sym = log((q(s) + q(-s)) / 2).
@@ -134,10 +143,11 @@ __device__ __forceinline__ WaveSlot wave_slot(int s, int t, int L, int S) {
 
 constexpr int kSiteBytes = 64;  // 16 channels x (bf16 hi + bf16 lo)
 
-// Byte offset of the activations of site (y, x) of layer `layer` in the ring.
-__device__ __forceinline__ int act_at(int layer, int R, int y, int x) {
+// Byte offset of lane group kk's part of the activations of site (y, x) of
+// layer `layer` in the ring: planes of 3 layers x 4 columns x R rows.
+__device__ __forceinline__ int act_at(int layer, int kk, int R, int y, int x) {
     const int ry = y < R ? y : y - R;  // y mod R, as y < L < 2R
-    return ((layer * R + ry) * 4 + (x & 3)) * kSiteBytes;
+    return kk * (12 * R * 16) + ((layer * 4 + (x & 3)) * R + ry) * 16;
 }
 
 // log sigmoid(v) = -(max(-v, 0) + log1p(e^-|v|)), with log1p(e) taken as
@@ -149,16 +159,34 @@ __device__ __forceinline__ float log_sigmoid_hw(float v) {
     return -(fmaxf(-v, 0.f) + (__logf(u) - __fdividef((u - 1.f) - e, u)));
 }
 
+// Two float32 values rounded to bfloat16 (nearest even), packed: the first
+// in the low half.
+__device__ __forceinline__ uint32_t bf16_pair(float x, float y) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{x, y}, bf16x2));
+}
+
 // The four float32 activations of this lane's channels as the operand of
-// the next layer's centre tap: their hi terms, then their lo terms.
+// the next layer's centre tap: their hi terms hi = bf16(a), then their lo
+// terms bf16(a - hi) (a - hi is exact in float32).
 __device__ __forceinline__ bf16x8 act_terms(const f4& a) {
     bf16x8 r;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         r[v] = (__bf16)a[v];
-        r[4 + v] = (__bf16)(a[v] - (float)r[v]);  // a - hi is exact in float32
+        r[4 + v] = (__bf16)(a[v] - (float)r[v]);
     }
     return r;
+}
+
+// The same terms, two values per conversion, hi read back from the packed
+// bits: fewer instructions where many sites are converted at once.
+__device__ __forceinline__ bf16x8 act_terms_pk(const f4& a) {
+    const uint32_t h01 = bf16_pair(a[0], a[1]), h23 = bf16_pair(a[2], a[3]);
+    const uint32_t l01 = bf16_pair(a[0] - __uint_as_float(h01 << 16),
+                                   a[1] - __uint_as_float(h01 & 0xFFFF0000u));
+    const uint32_t l23 = bf16_pair(a[2] - __uint_as_float(h23 << 16),
+                                   a[3] - __uint_as_float(h23 & 0xFFFF0000u));
+    return __builtin_bit_cast(bf16x8, uint4{h01, h23, l01, l23});
 }
 
 // Operand A of tap t of a mask-B layer (weights at wo) for lane (m, kk):
@@ -185,10 +213,11 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
     extern __shared__ __align__(16) float sh[];  // 16-byte accesses of eight bfloat16 terms
     __shared__ float red[2];
     constexpr int S = 16 * T;
-    const int W2 = L + 2, R = (L + 1) / 2 + 1;
+    const int W2 = L + 3, R = (L + 1) / 2 + 1;
     const int sb_floats = (L * W2 + 3) & ~3;
-    const int layer_bytes = R * 4 * kSiteBytes;
-    float* sb = sh;  // [L][L + 2] spins as +-1.0 (unsigned), zero columns 0 and L + 1
+    const int layer_bytes = R * 4 * kSiteBytes;  // one layer of the four planes
+    const int layer_step = R * 4 * 16;             // one layer within a plane
+    float* sb = sh;  // [L][L + 3] spins as +-1.0 (unsigned), zero columns 0, L + 1, L + 2
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int m = lane & 15, kk = lane >> 4;
     // per wave: activations [3][R][4] sites of 64 bytes, then one zero site
@@ -253,9 +282,9 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
             for (int tp = 0; tp < 4; ++tp) {
                 const int yy = g[u].y + tap_dy(tp), xx = g[u].x + tap_dx(tp);
                 const bool ok = g[u].on && yy >= 0 && (unsigned)xx < (unsigned)L;
-                nb[u][tp] = ok ? act_at(0, R, yy, xx) + 16 * kk : zero_off;
+                nb[u][tp] = ok ? act_at(0, kk, R, yy, xx) : zero_off;
             }
-            own[u] = g[u].on ? act_at(0, R, g[u].y, g[u].x) + 16 * kk : junk_off;
+            own[u] = g[u].on ? act_at(0, kk, R, g[u].y, g[u].x) : junk_off;
             // index 0 is the zero column of row 0
             const int dy = kk < 3 ? -1 : 0, dx = kk < 3 ? kk - 1 : -1;
             const bool ok = g[u].on && g[u].y + dy >= 0;
@@ -284,7 +313,7 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
             for (int l = 0; l < 3; ++l)
 #pragma unroll
                 for (int tp = 0; tp < 4; ++tp) {
-                    const int o = nb[u][tp] == zero_off ? zero_off : nb[u][tp] + l * layer_bytes;
+                    const int o = nb[u][tp] == zero_off ? zero_off : nb[u][tp] + l * layer_step;
                     ta[u][l][tp] = *reinterpret_cast<const bf16x8*>(act + o);
                 }
         }
@@ -344,7 +373,7 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
 #pragma unroll
             for (int l = 0; l < 3; ++l)
                 *reinterpret_cast<bf16x8*>(act + (own[u] == junk_off ? junk_off
-                                                                      : own[u] + l * layer_bytes)) =
+                                                                      : own[u] + l * layer_step)) =
                     outs[u][l];
         if (sample) {
             // the second wave reads the spins the first one drew
@@ -379,6 +408,250 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
             r = fmaxf(x, y) + log1pf(expf(-fabsf(x - y))) - 0.69314718055994531f;
         }
         logq_out[b] = r;
+    }
+}
+
+// Teacher-forced log q of configurations that fit in LDS whole (L <= 32).
+//
+// With every spin given, nothing orders the sites: each layer is computed
+// for the whole lattice at once and its activations go to LDS for the taps
+// of the next layer.  The per-site arithmetic is k_nn_wave's: the same
+// operands in the same lanes, the same products in the same order (earlier
+// taps, then the centre tap from registers) and the same rounding of the
+// activations into hi and lo terms.  The log-likelihood terms are added in
+// k_nn_wave's order too: for L <= 32 the wavefront gives row slot s the
+// rows s and s + 16, summed in raster order from zero, and combines the 16
+// slots by a butterfly.  Here lane s (one sign) or s + 16 (the other) of
+// the first wave adds its slot's terms in that order, and the butterfly is
+// the same.  The result is therefore bitwise the wavefront's, and the
+// sampler's log q of a proposal is the one this kernel gives it.
+//
+// Wave w computes rows w and w + 16 as tiles of 16 columns (x0 = 0, 16):
+// kT = 4 tiles for L > 16, one for L <= 16.  A tile past the lattice (rows
+// w + 16 >= L) runs like the others on a harmless site and writes nothing,
+// so that a wave's tiles are straight-line code whose products and LDS
+// accesses interleave.  Grids in LDS carry a zero border, so that every
+// tap is one fixed offset from its site: row stride L + 1, a zero row above
+// row 0 and a zero column 0 that also serves as column L of the row above.
+// The spins are floats on such a grid; an activation buffer is four planes
+// (one per lane group kk: the hi and lo terms of channels 4 kk .. 4 kk + 3,
+// 16 bytes per site) of such grids, so that the 16 lanes of a group access
+// consecutive bytes, each plane padded to a multiple of kLatticePlaneAlign
+// bytes.  The first sign runs layer 1 -> A, 2 -> B, 3 -> A, 4 from A, the
+// second the other way round, so that its layer 1 may start while slower
+// waves still read A.  The weights of layers 2-4 are kept as bfloat16
+// [layer][tap][out][in] (layer 4: [tap][in]).  About 160 KB at L = 32: one
+// workgroup per CU, persistent over the batch, each configuration's spins
+// fetched into registers while the one before is evaluated.
+constexpr int kLatticePrefetch = 2;  // spins per thread: (L + 1)^2 <= 2 x 64 min(L, 16)
+constexpr int kLatticePlaneAlign = 256;
+
+// Row stride of the terms: a multiple of 4 floats past L (16-byte rows whose
+// padding reads as zeros), plus 4 to spread the rows over the banks.
+__host__ __device__ inline int lattice_term_stride(int L) { return ((L + 3) & ~3) + 4; }
+
+struct LatticeLds {
+    int grid;   // (L + 1)^2 entries per grid
+    int plane;  // bytes of one plane of an activation buffer
+    int wts;    // byte offsets: bfloat16 weights of layers 2-4
+    int par;    // float [64] layer-1 weights in lane order, [3][16] biases, bias of layer 4
+    int buf[2];
+    int junk;
+    int terms;  // float [2 signs][L][lattice_term_stride(L)]
+    int bytes;
+};
+__host__ __device__ inline LatticeLds lattice_lds(int L) {
+    LatticeLds d;
+    d.grid = (L + 1) * (L + 1);
+    d.plane = (16 * d.grid + kLatticePlaneAlign - 1) / kLatticePlaneAlign * kLatticePlaneAlign;
+    d.wts = (d.grid * 4 + 15) & ~15;  // the spins first
+    d.par = d.wts + (2 * NTB * C * C + NTB * C) * 2;
+    d.buf[0] = (d.par + (64 + 3 * C + 4) * 4 + kLatticePlaneAlign - 1) / kLatticePlaneAlign *
+               kLatticePlaneAlign;
+    d.buf[1] = d.buf[0] + 4 * d.plane;
+    d.junk = d.buf[1] + 4 * d.plane;
+    d.terms = d.junk + kSiteBytes;
+    d.bytes = d.terms + 2 * L * lattice_term_stride(L) * 4;
+    return d;
+}
+
+template <int kT>
+__global__ void __launch_bounds__(1024) k_nn_lattice(const float* __restrict__ wexp, int L, int B,
+                                                     int symmetric, const int8_t* __restrict__ s_in,
+                                                     int64_t in_stride, float* __restrict__ logq_out) {
+    extern __shared__ __align__(16) float sh[];
+    const LatticeLds d = lattice_lds(L);
+    const int L1 = L + 1, RS = lattice_term_stride(L);
+    char* base = reinterpret_cast<char*>(sh);
+    float* sb = sh;  // spins as +-1.0 (unsigned) on the bordered grid
+    uint16_t* wts = reinterpret_cast<uint16_t*>(base + d.wts);
+    float* par = reinterpret_cast<float*>(base + d.par);
+    float* terms = reinterpret_cast<float*>(base + d.terms);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int m = lane & 15, kk = lane >> 4;
+    // bfloat16 weights (exact: wexp holds bfloat16 values)
+    for (int i = threadIdx.x; i < 2 * NTB * C * C + NTB * C; i += blockDim.x) {
+        float v;
+        if (i < 2 * NTB * C * C) {
+            const int l = i / (NTB * C * C), t = (i / (C * C)) % NTB, co = (i / C) % C, ci = i % C;
+            v = wexp[(l == 0 ? NNOff::W2 : NNOff::W3) + (co * C + ci) * NTB + t];
+        } else {
+            const int j = i - 2 * NTB * C * C, t = j / C, ci = j % C;
+            v = wexp[NNOff::W4 + ci * NTB + t];
+        }
+        wts[i] = (uint16_t)(__float_as_uint(v) >> 16);
+    }
+    // operand A of layer 1 for lane (m, kk), then the biases of layers 1-4
+    for (int i = threadIdx.x; i < 64 + 3 * C + 1; i += blockDim.x)
+        par[i] = i < 64 ? wexp[NNOff::W1 + (i & 15) * 4 + (i >> 4)]
+                 : i < 64 + 3 * C
+                     ? wexp[(i < 64 + C ? NNOff::B1 : i < 64 + 2 * C ? NNOff::B2 : NNOff::B3) +
+                            (i - 64) % C]
+                     : wexp[NNOff::B4];
+    // the borders of every plane of both buffers, and the term padding
+    for (int i = threadIdx.x; i < 8 * (2 * L + 1); i += blockDim.x) {
+        const int p = i / (2 * L + 1), j = i % (2 * L + 1);
+        const int q = j <= L ? j : (j - L) * L1;
+        *reinterpret_cast<f4*>(base + ((p >> 2) ? d.buf[1] : d.buf[0]) + (p & 3) * d.plane +
+                               16 * q) = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int i = threadIdx.x; i < 2 * L * RS; i += blockDim.x)
+        terms[i] = 0.f;
+    // Tile i of wave w: row sy(i) = w + 16 (i >> 1), columns 16 (i & 1) + m.
+    // Grid index of this lane's site, or of the last site where there is
+    // none (its reads then stay inside the grid and its writes go to junk).
+    bool on[kT];
+    int q[kT];
+#pragma unroll
+    for (int i = 0; i < kT; ++i) {
+        const int y = w + 16 * (i >> 1), x = 16 * (i & 1) + m;
+        on[i] = y < L && x < L;
+        q[i] = on[i] ? (y + 1) * L1 + x + 1 : d.grid - 1;
+    }
+    // tap kk of mask A, and the four earlier taps of mask B, as offsets
+    const int qa = kk < 3 ? -L1 + kk - 1 : -1;
+    // spins of the next configuration, fetched a configuration ahead
+    float pre[kLatticePrefetch];
+    auto fetch = [&](int b) {
+#pragma unroll
+        for (int k = 0; k < kLatticePrefetch; ++k) {
+            const int i = threadIdx.x + k * blockDim.x;
+            const int y = i / L1 - 1, x = i % L1 - 1;
+            pre[k] = b < B && i < d.grid && y >= 0 && x >= 0
+                         ? (float)s_in[(int64_t)b * in_stride + y * L + x]
+                         : 0.f;
+        }
+    };
+    fetch(blockIdx.x);
+    const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    const int signs = symmetric ? 2 : 1;
+    const int pk = kk * d.plane;
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+#pragma unroll
+        for (int k = 0; k < kLatticePrefetch; ++k) {
+            const int i = threadIdx.x + k * blockDim.x;
+            if (i < d.grid)
+                sb[i] = pre[k];
+        }
+        fetch(b + gridDim.x);
+        __syncthreads();
+        for (int sg = 0; sg < signs; ++sg) {
+            const float sigma = sg == 0 ? 1.f : -1.f;
+            const int bA = sg == 0 ? d.buf[0] : d.buf[1], bB = sg == 0 ? d.buf[1] : d.buf[0];
+            bf16x8 prev[kT];
+            // layer 1 (mask A)
+            const float wa1 = par[lane];
+            const f4 bias1 = *reinterpret_cast<const f4*>(par + 64 + 4 * kk);
+#pragma unroll
+            for (int i = 0; i < kT; ++i) {
+                const float sp = sb[on[i] ? q[i] + qa : 0];
+                const f4 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa1, sigma * sp, zero4, 0, 0, 0);
+                f4 a;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    a[v] = fmaxf(acc[v] + bias1[v], 0.f);
+                prev[i] = act_terms_pk(a);
+                *reinterpret_cast<bf16x8*>(base + (on[i] ? bA + pk + 16 * q[i] : d.junk)) = prev[i];
+            }
+            __syncthreads();
+            // layers 2, 3 and 4 (mask B): the four earlier taps from the
+            // buffer the layer below wrote, the centre tap from registers
+#pragma unroll
+            for (int l = 1; l < 4; ++l) {
+                const int in_off = ((l & 1) ? bA : bB) + pk, out_off = ((l & 1) ? bB : bA) + pk;
+                // operand A of tap t: weights of channels 4 kk .. 4 kk + 3
+                // for output m (layer 4: its one output), once for the hi
+                // and once for the lo terms
+                bf16x8 wl[NTB];
+#pragma unroll
+                for (int t = 0; t < NTB; ++t) {
+                    const int o = l < 3 ? (((l - 1) * NTB + t) * C + m) * C + 4 * kk
+                                        : 2 * NTB * C * C + t * C + 4 * kk;
+                    const uint2 u = *reinterpret_cast<const uint2*>(wts + o);
+                    wl[t] = __builtin_bit_cast(bf16x8, uint4{u.x, u.y, u.x, u.y});
+                }
+                const f4 bl = *reinterpret_cast<const f4*>(par + 64 + (l < 3 ? l : 0) * C + 4 * kk);
+                const float bias4 = par[64 + 3 * C];
+#pragma unroll
+                for (int i = 0; i < kT; ++i) {
+                    bf16x8 ta[4];
+#pragma unroll
+                    for (int tp = 0; tp < 4; ++tp)
+                        ta[tp] = *reinterpret_cast<const bf16x8*>(
+                            base + in_off + 16 * (q[i] + tap_dy(tp) * L1 + tap_dx(tp)));
+                    f4 acc = zero4;
+#pragma unroll
+                    for (int tp = 0; tp < 4; ++tp)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl[tp], ta[tp], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl[4], prev[i], acc, 0, 0, 0);
+                    if (l < 3) {
+                        f4 a;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            a[v] = fmaxf(acc[v] + bl[v], 0.f);
+                        prev[i] = act_terms_pk(a);
+                        *reinterpret_cast<bf16x8*>(base + (on[i] ? out_off + 16 * q[i] : d.junk)) =
+                            prev[i];
+                    } else {
+                        const float z = acc[0] + bias4;
+                        const float t = log_sigmoid_hw(sigma * sb[q[i]] * z);
+                        if (on[i] && kk == 0)
+                            terms[(sg * L + w + 16 * (i >> 1)) * RS + 16 * (i & 1) + m] = t;
+                    }
+                }
+                if (l < 3)
+                    __syncthreads();
+            }
+        }
+        __syncthreads();
+        // lane s + 16 sg of the first wave: slot s of sign sg, its rows in
+        // raster order (the padding adds zeros), then the butterfly
+        if (w == 0) {
+            float tot = 0.f;
+            if (lane < 32)
+                for (int y = lane & 15; y < L; y += 16) {
+                    const f4* row = reinterpret_cast<const f4*>(terms + ((lane >> 4) * L + y) * RS);
+                    for (int x4 = 0; x4 < (L + 3) / 4; ++x4) {
+                        const f4 v = row[x4];
+                        tot += v[0];
+                        tot += v[1];
+                        tot += v[2];
+                        tot += v[3];
+                    }
+                }
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1)
+                tot += __shfl_xor(tot, off, 64);
+            const float r1 = __shfl(tot, 16, 64);
+            if (lane == 0 && logq_out) {
+                float r = tot;
+                if (symmetric) {
+                    const float x = tot, y = r1;
+                    r = fmaxf(x, y) + log1pf(expf(-fabsf(x - y))) - 0.69314718055994531f;
+                }
+                logq_out[b] = r;
+            }
+        }
     }
 }
 
@@ -1047,7 +1320,7 @@ hipError_t launch_nn_adam(float* master, float* m, float* v, const float* g, uin
 }
 
 size_t nn_wave_lds_bytes(int L, int symmetric) {
-    const size_t sb = ((size_t)L * (L + 2) + 3) & ~(size_t)3;
+    const size_t sb = ((size_t)L * (L + 3) + 3) & ~(size_t)3;
     const size_t R = (size_t)(L + 1) / 2 + 1;
     return sb * sizeof(float) +
            (size_t)(symmetric ? 2 : 1) * (3 * R * 4 + 2) * (size_t)kSiteBytes;
@@ -1068,6 +1341,32 @@ hipError_t launch_nn_wave(const float* wexp, int L, int B, int sample, int symme
                            in_stride, key, chain0, draw, s_out, out_stride, logq);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+size_t nn_lattice_lds_bytes(int L) {
+    if (L < 2 || L > kNNLatticeMaxL)
+        return 0;
+    return (size_t)lattice_lds(L).bytes;
+}
+
+hipError_t launch_nn_lattice(const float* wexp, int L, int B, int symmetric, const int8_t* s_in,
+                             int64_t in_stride, float* logq, int grid, hipStream_t st) {
+    const size_t lds = nn_lattice_lds_bytes(L);
+    if (!lds || grid < 1)
+        return hipErrorInvalidValue;
+    // wave w evaluates rows w and w + 16: L waves up to 16
+    const int waves = L < 16 ? L : 16;
+    const int threads = 64 * waves;
+    if ((L + 1) * (L + 1) > kLatticePrefetch * threads)
+        return hipErrorInvalidValue;
+    const dim3 g(grid < B ? grid : B);
+    if (L > 16)
+        hipLaunchKernelGGL(k_nn_lattice<4>, g, dim3(threads), lds, st, wexp, L, B, symmetric, s_in,
+                           in_stride, logq);
+    else
+        hipLaunchKernelGGL(k_nn_lattice<1>, g, dim3(threads), lds, st, wexp, L, B, symmetric, s_in,
+                           in_stride, logq);
     return hipGetLastError();
 }
 

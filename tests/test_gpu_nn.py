@@ -163,6 +163,23 @@ def test_sampler_matches_oracle(L, B, sym):
             assert abs(lq[b] - lqo[b]) <= 1e-5 * abs(lqo[b]) + 1e-3, (b, lq[b], lqo[b])
 
 
+@pytest.mark.parametrize("L,B", [(2, 5), (3, 7), (11, 9), (17, 6), (31, 4), (32, 513), (32, 1024)])
+@pytest.mark.parametrize("sym", [False, True])
+def test_logq_is_the_samplers_bitwise(L, B, sym):
+    """log q of sampled configurations, evaluated the whole lattice at a
+    time (L <= 32), is bitwise the log q the wavefront sampler returned:
+    odd sides (partial tiles and rows), batches above one configuration per
+    CU (each workgroup takes several, fetching the next one's spins ahead)."""
+    say(f"logq bitwise L={L} B={B} symmetric={sym}")
+    net, _ = _net(L, B, 13, scale=1.5)
+    s, lq = net.sample(B, (5 << 32) | 3, 11, 4, symmetric=sym)
+    lq_eval = _host(net.logq(s, symmetric=sym))
+    lq = _host(lq)
+    bad = np.flatnonzero(lq != lq_eval)
+    assert bad.size == 0, (bad[:5], lq[bad[:5]], lq_eval[bad[:5]])
+    assert np.isfinite(lq).all()
+
+
 def test_sampler_draws_from_q():
     """Frequencies of the 2^4 configurations of a 2 x 2 lattice over 2^15
     samples agree with q (chi-square, 15 degrees of freedom)."""
