@@ -43,7 +43,7 @@ hipError_t launch_nn_adam(float* master, float* m, float* v, const float* g, uin
 // evaluates the B configurations at s_in (teacher forcing); logq (may be
 // NULL in sampling) receives log q, or log q_sym with symmetric = 1.  The
 // two modes give the same bits for the same configuration.  L <= 64.
-size_t nn_wave_lds_bytes(int L, int symmetric);
+size_t nn_wave_lds_bytes(int L, int symmetric, int predraw);
 hipError_t launch_nn_wave(const float* wexp, int L, int B, int sample, int symmetric,
                           const int8_t* s_in, int64_t in_stride, Key key, uint32_t chain0,
                           uint32_t draw, int8_t* s_out, int64_t out_stride, float* logq,

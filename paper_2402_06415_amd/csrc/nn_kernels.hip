@@ -112,8 +112,11 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
 // planes, one per lane group kk, each [layer][column][ring row] of 16
 // bytes: the 16 lanes of a group serve consecutive rows, whose entries are
 // then 16 bytes apart in one column, and the columns of neighbouring rows
-// (x and x - 2) are 2R entries apart, an even number, so that the lanes'
-// 16-byte pieces fall on distinct banks.  The spins use row stride L + 3
+// (x and x - 2) are 2 (R + 2) entries apart, an even number, so that the
+// lanes' 16-byte pieces fall on distinct banks.  Each column has two rows
+// past the ring: row R is zero (read for taps outside the lattice) and row
+// R + 1 takes the writes of idle slots, so that every layer's access is
+// one offset from the layer-0 one.  The spins use row stride L + 3
 // for the same reason (rows one apart, columns two apart: 33 words at
 // L = 32).
 //
@@ -143,12 +146,9 @@ __device__ __forceinline__ WaveSlot wave_slot(int s, int t, int L, int S) {
 
 constexpr int kSiteBytes = 64;  // 16 channels x (bf16 hi + bf16 lo)
 
-// Byte offset of lane group kk's part of the activations of site (y, x) of
-// layer `layer` in the ring: planes of 3 layers x 4 columns x R rows.
-__device__ __forceinline__ int act_at(int layer, int kk, int R, int y, int x) {
-    const int ry = y < R ? y : y - R;  // y mod R, as y < L < 2R
-    return kk * (12 * R * 16) + ((layer * 4 + (x & 3)) * R + ry) * 16;
-}
+// Byte offset of ring row ry, column c of layer 0 in a plane of 3 layers x
+// 4 columns x Rp = R + 2 rows (24-bit products: full-rate multiplies).
+__device__ __forceinline__ int ring_at(int Rp, int ry, int c) { return (__mul24(c, Rp) + ry) * 16; }
 
 // log sigmoid(v) = -(max(-v, 0) + log1p(e^-|v|)), with log1p(e) taken as
 // log(u) - ((u - 1) - e) / u for u = 1 + e (the rounding of u corrected
@@ -206,25 +206,27 @@ __device__ __forceinline__ bf16x8 weights_tap(const float* wexp, int wo, int m, 
 
 template <int T>
 __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp, int L, int sample,
-                                                 int symmetric, const int8_t* s_in,
+                                                 int predraw, int symmetric, const int8_t* s_in,
                                                  int64_t in_stride, Key key, uint32_t chain0,
                                                  uint32_t draw, int8_t* s_out, int64_t out_stride,
                                                  float* logq_out) {
     extern __shared__ __align__(16) float sh[];  // 16-byte accesses of eight bfloat16 terms
     __shared__ float red[2];
     constexpr int S = 16 * T;
-    const int W2 = L + 3, R = (L + 1) / 2 + 1;
+    const int W2 = L + 3, R = (L + 1) / 2 + 1, Rp = R + 2;
     const int sb_floats = (L * W2 + 3) & ~3;
-    const int layer_bytes = R * 4 * kSiteBytes;  // one layer of the four planes
-    const int layer_step = R * 4 * 16;             // one layer within a plane
+    const int layer_step = Rp * 4 * 16;  // one layer within a plane
+    const int plane = 3 * layer_step;    // one lane group's plane
     float* sb = sh;  // [L][L + 3] spins as +-1.0 (unsigned), zero columns 0, L + 1, L + 2
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int m = lane & 15, kk = lane >> 4;
-    // per wave: activations [3][R][4] sites of 64 bytes, then one zero site
-    // (read for taps outside the lattice) and one junk site that absorbs
-    // the writes of idle slots
-    char* act = reinterpret_cast<char*>(sh + sb_floats) + w * (3 * layer_bytes + 2 * kSiteBytes);
-    const int zero_off = 3 * layer_bytes, junk_off = zero_off + kSiteBytes;
+    // per wave: the four planes of its ring; this lane's plane, and its
+    // zero and junk entries (column 0 of layer 0)
+    char* act = reinterpret_cast<char*>(sh + sb_floats) + w * (4 * plane) + kk * plane;
+    const int zero_off = R * 16, junk_off = (R + 1) * 16;
+    // with predraw, every site's uniform draw, taken before the first step
+    uint32_t* ru = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(sh + sb_floats) +
+                                               (blockDim.x >> 6) * (4 * plane));
     const float sigma = w == 0 ? 1.f : -1.f;
     const int b = blockIdx.x;
     for (int i = threadIdx.x; i < sb_floats; i += blockDim.x) {
@@ -234,8 +236,10 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
             v = (float)s_in[(int64_t)b * in_stride + y * L + xc - 1];
         sb[i] = v;
     }
-    if (lane < kSiteBytes / 4)
-        reinterpret_cast<float*>(act + zero_off)[lane] = 0.f;
+    // the zero row of each layer, in each lane group's plane
+    if (m == 0)
+        for (int l = 0; l < 3; ++l)
+            *reinterpret_cast<f4*>(act + zero_off + l * layer_step) = f4{0.f, 0.f, 0.f, 0.f};
     // matrix-core operands A: row co = m of every product
     const float wa1 = wexp[NNOff::W1 + m * 4 + kk];
     bf16x8 wa2[NTB], wa3[NTB], wa4[NTB];
@@ -261,6 +265,16 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
         const U4 o = philox4x32_10({0xFFFFFFFFu, chain, draw, kTagNNSample}, rk);
         out_sign = (o.x >> 31) ? -1.f : 1.f;
     }
+    // the draws do not depend on the network: with predraw they are all
+    // taken here, off the steps' critical path (block j serves sites 4j..4j+3)
+    if (predraw)
+        for (int j = threadIdx.x; 4 * j < L * L; j += blockDim.x) {
+            const U4 o = philox4x32_10({(uint32_t)j, chain, draw, kTagNNSample}, rk);
+            ru[4 * j] = o.x;
+            ru[4 * j + 1] = o.y;
+            ru[4 * j + 2] = o.z;
+            ru[4 * j + 3] = o.w;
+        }
     __syncthreads();
     float lq[T];
 #pragma unroll
@@ -278,18 +292,22 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
 #pragma unroll
         for (int u = 0; u < T; ++u) {
             g[u] = wave_slot(16 * u + m, t, L, S);
-#pragma unroll
-            for (int tp = 0; tp < 4; ++tp) {
-                const int yy = g[u].y + tap_dy(tp), xx = g[u].x + tap_dx(tp);
-                const bool ok = g[u].on && yy >= 0 && (unsigned)xx < (unsigned)L;
-                nb[u][tp] = ok ? act_at(0, kk, R, yy, xx) : zero_off;
-            }
-            own[u] = g[u].on ? act_at(0, kk, R, g[u].y, g[u].x) : junk_off;
+            const int y = g[u].y, x = g[u].x;
+            // ring rows of y and y - 1 (y < L < 2R); columns of x - 1, x, x + 1
+            const int ry = y < R ? y : y - R, ryu = y - 1 < R ? y - 1 : y - 1 - R;
+            const int cl = (x - 1) & 3, cm = x & 3, cr = (x + 1) & 3;
+            const bool up = g[u].on && y > 0, lf = x > 0, rt = x + 1 < L;
+            // the four earlier taps: (-1, -1), (-1, 0), (-1, +1), (0, -1)
+            nb[u][0] = up && lf ? ring_at(Rp, ryu, cl) : zero_off;
+            nb[u][1] = up ? ring_at(Rp, ryu, cm) : zero_off;
+            nb[u][2] = up && rt ? ring_at(Rp, ryu, cr) : zero_off;
+            nb[u][3] = g[u].on && lf ? ring_at(Rp, ry, cl) : zero_off;
+            own[u] = g[u].on ? ring_at(Rp, ry, cm) : junk_off;
             // index 0 is the zero column of row 0
             const int dy = kk < 3 ? -1 : 0, dx = kk < 3 ? kk - 1 : -1;
-            const bool ok = g[u].on && g[u].y + dy >= 0;
-            spin_in[u] = ok ? (g[u].y + dy) * W2 + g[u].x + dx + 1 : 0;
-            spin_at[u] = g[u].on ? g[u].y * W2 + g[u].x + 1 : 0;
+            const bool ok = g[u].on && y + dy >= 0;
+            spin_in[u] = ok ? __mul24(y + dy, W2) + x + dx + 1 : 0;
+            spin_at[u] = g[u].on ? __mul24(y, W2) + x + 1 : 0;
         }
         // the sampling draws of the step do not depend on z: taken first,
         // they overlap the products' latency
@@ -297,9 +315,13 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
         if (sample && w == 0) {
 #pragma unroll
             for (int u = 0; u < T; ++u) {
-                const int i = g[u].y * L + g[u].x;
-                const U4 o = philox4x32_10({(uint32_t)(i >> 2), chain, draw, kTagNNSample}, rk);
-                r[u] = u4_get(o, i & 3);
+                const int i = __mul24(g[u].y, L) + g[u].x;
+                if (predraw) {
+                    r[u] = ru[g[u].on ? i : 0];
+                } else {
+                    const U4 o = philox4x32_10({(uint32_t)(i >> 2), chain, draw, kTagNNSample}, rk);
+                    r[u] = u4_get(o, i & 3);
+                }
             }
         }
         // every LDS read of the step, before any of its writes: layer-1
@@ -312,10 +334,8 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
 #pragma unroll
             for (int l = 0; l < 3; ++l)
 #pragma unroll
-                for (int tp = 0; tp < 4; ++tp) {
-                    const int o = nb[u][tp] == zero_off ? zero_off : nb[u][tp] + l * layer_step;
-                    ta[u][l][tp] = *reinterpret_cast<const bf16x8*>(act + o);
-                }
+                for (int tp = 0; tp < 4; ++tp)
+                    ta[u][l][tp] = *reinterpret_cast<const bf16x8*>(act + nb[u][tp] + l * layer_step);
         }
         bf16x8 outs[T][3];
         float z[T];
@@ -372,9 +392,7 @@ __global__ void __launch_bounds__(128) k_nn_wave(const float* __restrict__ wexp,
         for (int u = 0; u < T; ++u)
 #pragma unroll
             for (int l = 0; l < 3; ++l)
-                *reinterpret_cast<bf16x8*>(act + (own[u] == junk_off ? junk_off
-                                                                      : own[u] + l * layer_step)) =
-                    outs[u][l];
+                *reinterpret_cast<bf16x8*>(act + own[u] + l * layer_step) = outs[u][l];
         if (sample) {
             // the second wave reads the spins the first one drew
             __syncthreads();
@@ -1319,11 +1337,11 @@ hipError_t launch_nn_adam(float* master, float* m, float* v, const float* g, uin
     return hipGetLastError();
 }
 
-size_t nn_wave_lds_bytes(int L, int symmetric) {
+size_t nn_wave_lds_bytes(int L, int symmetric, int predraw) {
     const size_t sb = ((size_t)L * (L + 3) + 3) & ~(size_t)3;
-    const size_t R = (size_t)(L + 1) / 2 + 1;
-    return sb * sizeof(float) +
-           (size_t)(symmetric ? 2 : 1) * (3 * R * 4 + 2) * (size_t)kSiteBytes;
+    const size_t Rp = (size_t)(L + 1) / 2 + 3;  // ring rows + a zero and a junk row
+    return sb * sizeof(float) + (size_t)(symmetric ? 2 : 1) * 4 * (3 * 4 * Rp * 16) +
+           (predraw ? (((size_t)L * L + 3) & ~(size_t)3) * sizeof(uint32_t) : 0);
 }
 
 hipError_t launch_nn_wave(const float* wexp, int L, int B, int sample, int symmetric,
@@ -1332,13 +1350,15 @@ hipError_t launch_nn_wave(const float* wexp, int L, int B, int sample, int symme
                           hipStream_t st) {
     const int rows = (L + 1) / 2;  // sites of one anti-diagonal, at most
     const dim3 block(symmetric ? 128 : 64);
-    const size_t lds = nn_wave_lds_bytes(L, symmetric);
+    // draws taken up front where their table is small (4 KB at L = 32)
+    const int predraw = sample && L <= 32;
+    const size_t lds = nn_wave_lds_bytes(L, symmetric, predraw);
     if (rows <= 16)
-        hipLaunchKernelGGL(k_nn_wave<1>, dim3(B), block, lds, st, wexp, L, sample, symmetric, s_in,
-                           in_stride, key, chain0, draw, s_out, out_stride, logq);
+        hipLaunchKernelGGL(k_nn_wave<1>, dim3(B), block, lds, st, wexp, L, sample, predraw,
+                           symmetric, s_in, in_stride, key, chain0, draw, s_out, out_stride, logq);
     else if (rows <= 32)
-        hipLaunchKernelGGL(k_nn_wave<2>, dim3(B), block, lds, st, wexp, L, sample, symmetric, s_in,
-                           in_stride, key, chain0, draw, s_out, out_stride, logq);
+        hipLaunchKernelGGL(k_nn_wave<2>, dim3(B), block, lds, st, wexp, L, sample, predraw,
+                           symmetric, s_in, in_stride, key, chain0, draw, s_out, out_stride, logq);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
