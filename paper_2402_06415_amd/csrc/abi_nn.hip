@@ -183,13 +183,10 @@ int ising_batch_mh(const ising_batch* b, int32_t L_prop, const int8_t* prop_dev,
         return set_error(ISING_E_INVALID, "prop_stride < L_prop^2");
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     unsigned char* ws = reinterpret_cast<unsigned char*>(b->workspace);
-    HIP_TRY(ising::launch_batch_prepare(ws, false, b->count, b->spins_bytes, b->max_L, 0,
-                                        ising::kPrepareMeasure, b->draws, st),
-            "batch prepare");
     const ising::Key key{(uint32_t)(b->seed & 0xFFFFFFFFu), (uint32_t)(b->seed >> 32)};
-    HIP_TRY(ising::launch_batch_mh(ws, b->count, b->spins, L_prop, prop_dev, prop_stride,
-                                   logq_cur_dev, logq_prop_dev, beta_dev, key, draw, accepted_dev,
-                                   st),
+    HIP_TRY(ising::launch_batch_mh(ws, b->count, b->spins_bytes, b->max_L, b->spins, L_prop,
+                                   prop_dev, prop_stride, logq_cur_dev, logq_prop_dev, beta_dev, key,
+                                   draw, accepted_dev, st),
             "batch mh");
     return ISING_OK;
 }

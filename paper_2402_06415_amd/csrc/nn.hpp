@@ -58,9 +58,11 @@ constexpr int kNNLatticeMaxL = 32;
 size_t nn_lattice_lds_bytes(int L);
 hipError_t launch_nn_lattice(const float* wexp, int L, int B, int symmetric, const int8_t* s_in,
                              int64_t in_stride, float* logq, int grid, hipStream_t st);
-hipError_t launch_batch_mh(unsigned char* ws, int count, int8_t* spins, int L_prop,
-                           const int8_t* prop, int64_t pstride, const float* lq_cur,
-                           const float* lq_prop, const double* beta, Key key, uint32_t draw,
-                           int32_t* accepted, hipStream_t st);
+// Metropolis-Hastings on the lattices of a batch; each workgroup checks its
+// own lattice's setup and descriptor (no prepare launch).
+hipError_t launch_batch_mh(unsigned char* ws, int count, uint64_t spins_bytes, int max_L,
+                           int8_t* spins, int L_prop, const int8_t* prop, int64_t pstride,
+                           const float* lq_cur, const float* lq_prop, const double* beta, Key key,
+                           uint32_t draw, int32_t* accepted, hipStream_t st);
 
 }  // namespace ising

@@ -1171,20 +1171,25 @@ __device__ __forceinline__ long long energy_to0(const int8_t* s, int L, long lon
 }
 
 // Independent-proposal Metropolis-Hastings, one workgroup per lattice.
-__global__ void k_batch_mh(unsigned char* ws, int count, int8_t* spins, int L_prop,
-                           const int8_t* prop, int64_t pstride, const float* lq_cur,
-                           const float* lq_prop, const double* beta, Key key, uint32_t draw,
-                           int32_t* accepted) {
+__global__ void k_batch_mh(unsigned char* ws, int count, uint64_t spins_bytes, int max_L,
+                           int8_t* spins, int L_prop, const int8_t* prop, int64_t pstride,
+                           const float* lq_cur, const float* lq_prop, const double* beta, Key key,
+                           uint32_t draw, int32_t* accepted) {
     __shared__ long long red[16];
     __shared__ int acc_s;
     const BatchHeaderView hv(ws);
-    if (*hv.ok == 0)
-        return;
     const int j = blockIdx.x;
     const BatchDesc d = reinterpret_cast<const BatchDesc*>(ws + BatchWs::desc_offset(count))[j];
-    if (d.L != L_prop) {
+    // the checks a sweep's prepare step makes, for this lattice: the batch
+    // is set up, its descriptor fits the spins buffer and max_L, and its
+    // side is the proposals'
+    const uint32_t* mc = reinterpret_cast<const uint32_t*>(ws + BatchWs::kMagic);
+    const bool set_up = mc[0] == kBatchMagic && mc[1] == (uint32_t)count;
+    const bool fits = d.L >= 8 && d.L <= max_L && (d.L & 7) == 0 && (d.off & 255u) == 0 &&
+                      d.off + (uint64_t)d.L * (uint64_t)d.L <= spins_bytes;
+    if (!set_up || !fits || d.L != L_prop) {
         if (threadIdx.x == 0) {
-            atomicOr(hv.err, kBatchErrShape);
+            atomicOr(hv.err, !set_up ? kBatchErrNotSetUp : !fits ? kBatchErrDescriptor : kBatchErrShape);
             if (accepted)
                 accepted[j] = 0;
         }
@@ -1390,12 +1395,12 @@ hipError_t launch_nn_lattice(const float* wexp, int L, int B, int symmetric, con
     return hipGetLastError();
 }
 
-hipError_t launch_batch_mh(unsigned char* ws, int count, int8_t* spins, int L_prop,
-                           const int8_t* prop, int64_t pstride, const float* lq_cur,
-                           const float* lq_prop, const double* beta, Key key, uint32_t draw,
-                           int32_t* accepted, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_mh, dim3(count), dim3(256), 0, st, ws, count, spins, L_prop, prop,
-                       pstride, lq_cur, lq_prop, beta, key, draw, accepted);
+hipError_t launch_batch_mh(unsigned char* ws, int count, uint64_t spins_bytes, int max_L,
+                           int8_t* spins, int L_prop, const int8_t* prop, int64_t pstride,
+                           const float* lq_cur, const float* lq_prop, const double* beta, Key key,
+                           uint32_t draw, int32_t* accepted, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_mh, dim3(count), dim3(256), 0, st, ws, count, spins_bytes, max_L,
+                       spins, L_prop, prop, pstride, lq_cur, lq_prop, beta, key, draw, accepted);
     return hipGetLastError();
 }
 

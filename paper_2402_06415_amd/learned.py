@@ -72,13 +72,37 @@ class LearnedChains:
         self.prop = torch.empty((self.count, L, L), dtype=torch.int8, device=dev)
         self.lq_cur = torch.empty(self.count, dtype=torch.float32, device=dev)
         self.lq_prop = torch.empty(self.count, dtype=torch.float32, device=dev)
-        self.accepted = torch.zeros(self.count, dtype=torch.int32, device=dev)
-        self.n_accepted = torch.zeros(self.count, dtype=torch.int64, device=dev)
+        # each cycle's acceptance flags go to a row of a ring, added to the
+        # per-chain totals once per ring (one reduction instead of one add
+        # per cycle) or when the totals are read
+        self._ring = torch.zeros((self._RING, self.count), dtype=torch.int32, device=dev)
+        self._rows = 0   # rows written since the last fold
+        self._last = self._RING - 1
+        self._n = torch.zeros(self.count, dtype=torch.int64, device=dev)
         self.draw = 0
         # the proposals do not depend on the chains' states: the k sweeps
         # run on a second stream (default priority) while the caller's
         # stream draws the proposals
         self.side = torch.cuda.Stream(device=dev)
+
+    _RING = 64
+
+    @property
+    def accepted(self):
+        """The last cycle's acceptance flags (int32 per chain, device)."""
+        return self._ring[self._last]
+
+    @property
+    def n_accepted(self):
+        """Accepted proposals per chain since construction or the last
+        zero_() of this tensor (int64, device)."""
+        self._fold()
+        return self._n
+
+    def _fold(self):
+        if self._rows:
+            self._n += self._ring[:self._rows].sum(0)
+            self._rows = 0
 
     def cycle(self, trace=None):
         """k sweeps (E, M after each into trace [k, count, 2] if given), then one proposal."""
@@ -94,8 +118,12 @@ class LearnedChains:
                         logq=self.lq_prop, symmetric=self.symmetric)
         main.wait_stream(self.side)
         self.net.logq(self.batch, out=self.lq_cur, symmetric=self.symmetric)
+        if self._rows == self._RING:
+            self._fold()
+        row = self._ring[self._rows]
         ising_batch_mh(self.batch.c, self.L, self.prop.data_ptr(), self.L * self.L,
                        self.lq_cur.data_ptr(), self.lq_prop.data_ptr(), self.beta.data_ptr(),
-                       self.draw, self.accepted.data_ptr(), torch.cuda.current_stream().cuda_stream)
-        self.n_accepted += self.accepted
+                       self.draw, row.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        self._last = self._rows
+        self._rows += 1
         self.draw += 1
