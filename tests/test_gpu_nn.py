@@ -180,6 +180,25 @@ def test_logq_is_the_samplers_bitwise(L, B, sym):
     assert np.isfinite(lq).all()
 
 
+@pytest.mark.parametrize("L", [12, 32, 40])
+def test_logq_reads_configurations_at_any_stride(L):
+    """Configurations spaced by a stride that is not L^2 (and not a multiple
+    of 4) give bitwise the log q of the same configurations packed densely,
+    in both forms of the evaluation (whole lattice for L <= 32, wavefront
+    above)."""
+    say(f"logq stride L={L}")
+    B, pad = 37, 13
+    net, _ = _net(L, B, 21, scale=1.5)
+    dense = torch.as_tensor(_configs(B, L, 8), device="cuda")
+    big = torch.zeros((B, L * L + pad), dtype=torch.int8, device="cuda")
+    big[:, 5:5 + L * L] = dense.reshape(B, L * L)
+    view = big.as_strided((B, L, L), (L * L + pad, L, 1), 5)
+    for sym in (False, True):
+        want = _host(net.logq(dense, symmetric=sym))
+        got = _host(net.logq(view, symmetric=sym))
+        assert (got == want).all(), (sym, np.flatnonzero(got != want)[:5])
+
+
 def test_sampler_draws_from_q():
     """Frequencies of the 2^4 configurations of a 2 x 2 lattice over 2^15
     samples agree with q (chi-square, 15 degrees of freedom)."""
