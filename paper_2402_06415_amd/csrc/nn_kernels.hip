@@ -74,7 +74,8 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
     wexp[i] = bf16_to_f32(h);
 }
 
-// Wavefront evaluation of the network, for sampling and for log q.
+// Wavefront evaluation of the network, for sampling and for log q (which
+// k_nn_lattice computes instead, with the same bits, up to L = 32).
 //
 // The factorisation is over sites in raster order, and the logits of site
 // (y, x) depend on the sites whose activations its taps read: (y-1, x-1),
@@ -118,7 +119,9 @@ __global__ void k_nn_adam(float* master, float* m, float* v, const float* g, uin
 // R + 1 takes the writes of idle slots, so that every layer's access is
 // one offset from the layer-0 one.  The spins use row stride L + 3
 // for the same reason (rows one apart, columns two apart: 33 words at
-// L = 32).
+// L = 32).  The draws do not depend on the network, so in sampling mode up
+// to L = 32 all of them are taken before the first step, into a table of
+// one 32-bit uniform per site after the rings (predraw).
 //
 // With `symmetric`, a second wave evaluates the negated configuration in
 // step with the first, and the result is log q_sym = log((q(s) + q(-s)) / 2).
