@@ -1069,28 +1069,38 @@ __global__ void __launch_bounds__(256) k_nn_wgrad(const float* __restrict__ g,
     if (t0 < t1) {
         RunSite q;
         q.start(t0 * kTile + kk, N, L);
-        for (int k4 = 4 * t0; k4 < 4 * t1; ++k4) {
-            const bool on = q.e < total;
-            const float a = kCout == 1 ? *(on && m == 0 ? g + q.e : zero)
-                                       : *(on ? g + (size_t)q.e * C + m : zero);
-            accb += a;
-            if constexpr (kIn == 1) {
-                const bool ok = on && m < 4 && q.tap_ok(m, L);
-                const float bv = (float)*(ok ? s + (int64_t)q.b * stride + q.p + off1
-                                             : reinterpret_cast<const int8_t*>(zero));
-                acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[0], 0, 0, 0);
-            } else {
-                float bv[NTB];
+        // kU steps of four sites at a time: every load of the kU steps is
+        // issued before their products, so that a wave keeps 6 kU loads in
+        // flight.  A step past the run loads the zero site: it adds exact
+        // zeros, and the sums are those of the step-by-step loop.
+        constexpr int kU = 4;
+        for (int k4 = 4 * t0; k4 < 4 * t1; k4 += kU) {
+            float a[kU], bv[kU][kT];
 #pragma unroll
-                for (int t = 0; t < NTB; ++t) {
-                    const bool ok = on && q.tap_ok(t, L);
-                    bv[t] = *(ok ? x + (size_t)(q.e + off[t]) * C + m : zero);
+            for (int u = 0; u < kU; ++u) {
+                const bool on = k4 + u < 4 * t1 && q.e < total;
+                a[u] = kCout == 1 ? *(on && m == 0 ? g + q.e : zero)
+                                  : *(on ? g + (size_t)q.e * C + m : zero);
+                if constexpr (kIn == 1) {
+                    const bool ok = on && m < 4 && q.tap_ok(m, L);
+                    bv[u][0] = (float)*(ok ? s + (int64_t)q.b * stride + q.p + off1
+                                           : reinterpret_cast<const int8_t*>(zero));
+                } else {
+#pragma unroll
+                    for (int t = 0; t < NTB; ++t) {
+                        const bool ok = on && q.tap_ok(t, L);
+                        bv[u][t] = *(ok ? x + (size_t)(q.e + off[t]) * C + m : zero);
+                    }
                 }
-#pragma unroll
-                for (int t = 0; t < NTB; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[t], acc[t], 0, 0, 0);
+                q.advance(4, N, L);
             }
-            q.advance(4, N, L);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                accb += a[u];
+#pragma unroll
+                for (int t = 0; t < kT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], bv[u][t], acc[t], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
