@@ -865,28 +865,45 @@ __global__ void __launch_bounds__(256) k_nn_fwd_mid(const float* __restrict__ hi
         return;
     RunSite q;
     q.start(t0 * kTile + m, N, L);
-    for (int tile = t0; tile < t1; ++tile) {
-        const bool on = q.e < total;
-        f4 hi = {0.f, 0.f, 0.f, 0.f}, mid = hi, lo = hi;
+    // the loads of kU tiles are issued before their products (a tile past
+    // the run reads the zero site and stores nothing)
+    constexpr int kU = 2;
+    for (int tile = t0; tile < t1; tile += kU) {
+        f4 src_v[kU][3][2];
+        int e[kU];
+        bool on[kU];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const bool ok = on && q.tap_ok(2 * j + (kk >> 1), L);
-            const f4* src = reinterpret_cast<const f4*>(
-                (ok ? hin + (size_t)(q.e + off[j]) * C : zero) + 8 * (kk & 1));
-            const f4 v0 = src[0], v1 = src[1];
-            bf16x8 bh, bm, bl;
-            split3_bf16(v0, v1, bh, bm, bl);
-            hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bh, hi, 0, 0, 0);
-            mid = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bm, mid, 0, 0, 0);
-            lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bl, lo, 0, 0, 0);
+        for (int u = 0; u < kU; ++u) {
+            on[u] = tile + u < t1 && q.e < total;
+            e[u] = q.e;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const bool ok = on[u] && q.tap_ok(2 * j + (kk >> 1), L);
+                const f4* src = reinterpret_cast<const f4*>(
+                    (ok ? hin + (size_t)(q.e + off[j]) * C : zero) + 8 * (kk & 1));
+                src_v[u][j][0] = src[0];
+                src_v[u][j][1] = src[1];
+            }
+            q.advance(kTile, N, L);
         }
-        f4 d = hi + (mid + lo) + bias;
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            d[v] = fmaxf(d[v], 0.f);
-        if (on)
-            *reinterpret_cast<f4*>(hout + (size_t)q.e * C + 4 * kk) = d;
-        q.advance(kTile, N, L);
+        for (int u = 0; u < kU; ++u) {
+            f4 hi = {0.f, 0.f, 0.f, 0.f}, mid = hi, lo = hi;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                bf16x8 bh, bm, bl;
+                split3_bf16(src_v[u][j][0], src_v[u][j][1], bh, bm, bl);
+                hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bh, hi, 0, 0, 0);
+                mid = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bm, mid, 0, 0, 0);
+                lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bl, lo, 0, 0, 0);
+            }
+            f4 d = hi + (mid + lo) + bias;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                d[v] = fmaxf(d[v], 0.f);
+            if (on[u])
+                *reinterpret_cast<f4*>(hout + (size_t)e[u] * C + 4 * kk) = d;
+        }
     }
 }
 
@@ -1004,30 +1021,47 @@ __global__ void __launch_bounds__(256) k_nn_bwd_mid(const float* __restrict__ go
         return;
     RunSite q;
     q.start(t0 * kTile + m, N, L);
-    for (int tile = t0; tile < t1; ++tile) {
-        const bool on = q.e < total;
-        f4 hi = {0.f, 0.f, 0.f, 0.f}, mid = hi, lo = hi;
+    // the loads of kU tiles are issued before their products (a tile past
+    // the run reads the zero site and stores nothing)
+    constexpr int kU = 2;
+    for (int tile = t0; tile < t1; tile += kU) {
+        f4 src_v[kU][3][2], h[kU];
+        int e[kU];
+        bool on[kU];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const bool ok = on && q.tap_ok_rev(2 * j + (kk >> 1), L);
-            const f4* src = reinterpret_cast<const f4*>(
-                (ok ? gout + (size_t)(q.e + off[j]) * C : zero) + 8 * (kk & 1));
-            const f4 v0 = src[0], v1 = src[1];
-            bf16x8 bh, bm, bl;
-            split3_bf16(v0, v1, bh, bm, bl);
-            hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bh, hi, 0, 0, 0);
-            mid = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bm, mid, 0, 0, 0);
-            lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bl, lo, 0, 0, 0);
-        }
-        if (on) {
-            f4 d = hi + (mid + lo);
-            const f4 h = *reinterpret_cast<const f4*>(hprev + (size_t)q.e * C + 4 * kk);
+        for (int u = 0; u < kU; ++u) {
+            on[u] = tile + u < t1 && q.e < total;
+            e[u] = q.e;
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                d[v] = h[v] > 0.f ? d[v] : 0.f;
-            *reinterpret_cast<f4*>(gprev + (size_t)q.e * C + 4 * kk) = d;
+            for (int j = 0; j < 3; ++j) {
+                const bool ok = on[u] && q.tap_ok_rev(2 * j + (kk >> 1), L);
+                const f4* src = reinterpret_cast<const f4*>(
+                    (ok ? gout + (size_t)(q.e + off[j]) * C : zero) + 8 * (kk & 1));
+                src_v[u][j][0] = src[0];
+                src_v[u][j][1] = src[1];
+            }
+            h[u] = *reinterpret_cast<const f4*>(on[u] ? hprev + (size_t)q.e * C + 4 * kk : zero);
+            q.advance(kTile, N, L);
         }
-        q.advance(kTile, N, L);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            f4 hi = {0.f, 0.f, 0.f, 0.f}, mid = hi, lo = hi;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                bf16x8 bh, bm, bl;
+                split3_bf16(src_v[u][j][0], src_v[u][j][1], bh, bm, bl);
+                hi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bh, hi, 0, 0, 0);
+                mid = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bm, mid, 0, 0, 0);
+                lo = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[j], bl, lo, 0, 0, 0);
+            }
+            if (on[u]) {
+                f4 d = hi + (mid + lo);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    d[v] = h[u][v] > 0.f ? d[v] : 0.f;
+                *reinterpret_cast<f4*>(gprev + (size_t)e[u] * C + 4 * kk) = d;
+            }
+        }
     }
 }
 
