@@ -301,10 +301,11 @@ int ising_batch_check_device_error(const ising_batch* b, void* hip_stream) {
         HIP_TRY(hipMemcpyAsync(errp, &zero, sizeof zero, hipMemcpyHostToDevice, st),
                 "clear error word");
         HIP_TRY(hipStreamSynchronize(st), "synchronise");
-        return set_error(ISING_E_STATE, "batch device error word 0x%x:%s%s%s%s", err,
+        return set_error(ISING_E_STATE, "batch device error word 0x%x:%s%s%s%s%s", err,
                          (err & ising::kBatchErrNotSetUp) ? " workspace not set up for this batch;" : "",
                          (err & ising::kBatchErrDescriptor) ? " descriptor outside spins or max_L;" : "",
                          (err & ising::kBatchErrSweepIndex) ? " sweep index + n exceeds 2^31;" : "",
+                         (err & ising::kBatchErrShape) ? " a lattice's side differs from the proposals';" : "",
                          (err & ising::kBatchErrDraws) ? " draw mode differs from setup's;" : "");
     }
     return ISING_OK;

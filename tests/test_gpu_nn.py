@@ -263,3 +263,36 @@ def test_mh_rejects_lattices_of_another_side():
     assert _host(acc)[1] == 0
     with pytest.raises(lib.IsingError):
         b.check()
+
+
+def test_mh_checks_the_batch_itself():
+    """The acceptance step validates its batch without a separate prepare
+    launch: with the workspace's setup word cleared from the host it changes
+    no lattice, reports 0 for every chain and raises the not-set-up error;
+    a lattice of the wrong side names the side in the error."""
+    say("mh not set up")
+    b = lib.Batch([8, 8], [0.4, 0.4], seed=1, start="cold")
+    before = _host(b.spins).copy()
+    prop = -torch.ones((2, 8, 8), dtype=torch.int8, device="cuda")
+    z = torch.zeros(2, dtype=torch.float32, device="cuda")
+    be = torch.zeros(2, dtype=torch.float64, device="cuda")  # beta = 0: every move accepted
+    acc = torch.full((2,), 7, dtype=torch.int32, device="cuda")
+    magic = b.workspace[0:4].clone()
+    b.workspace[0:4] = 0
+    lib.ising_batch_mh(b.c, 8, prop.data_ptr(), 64, z.data_ptr(), z.data_ptr(), be.data_ptr(), 0,
+                       acc.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert (_host(acc) == 0).all()
+    assert (_host(b.spins) == before).all()
+    with pytest.raises(lib.IsingError, match="not set up"):
+        b.check()
+    # restored, the same call accepts both moves
+    b.workspace[0:4] = magic
+    lib.ising_batch_mh(b.c, 8, prop.data_ptr(), 64, z.data_ptr(), z.data_ptr(), be.data_ptr(), 0,
+                       acc.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert (_host(acc) == 1).all()
+    b.check()
+    c = lib.Batch([8, 16], [0.4, 0.4], seed=1, start="cold")
+    lib.ising_batch_mh(c.c, 8, prop.data_ptr(), 64, z.data_ptr(), z.data_ptr(), be.data_ptr(), 0,
+                       acc.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    with pytest.raises(lib.IsingError, match="side differs"):
+        c.check()
