@@ -409,6 +409,7 @@ def bench_learned(args):
     # plain chains, equilibrated
     T = 20000
     plain = lib.Batch([L] * chains, [beta] * chains, seed=201, start="random", device=dev)
+    plain.autotune()  # the best launch shape for the plain chain too
     plain.sweep(2000, moments=False)
     tr = torch.empty((T, chains, 2), dtype=torch.int64, device=dev)
     _, plain_ms = timed(lambda: plain.sweep(T, moments=False, trace=tr))

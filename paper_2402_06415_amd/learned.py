@@ -66,6 +66,10 @@ class LearnedChains:
         assert self.count <= net.max_batch and net.L == L
         self.batch = Batch([L] * self.count, betas, seed=seed, lattice_id0=lattice_id0,
                            start=start, device=device)
+        # the sweeps' launch shape, timed on scratch spins (the chain is the
+        # same under every shape): the default suits large lattices, and a
+        # leaner one also leaves more of each CU to the sampler beside it
+        self.batch.autotune()
         dev = self.batch.device
         self.seed, self.lid0 = seed, lattice_id0
         self.beta = torch.as_tensor(np.asarray(betas, np.float64), device=dev)
