@@ -914,13 +914,19 @@ __global__ void __launch_bounds__(256) k_nn_fwd_mid(const float* __restrict__ hi
 __global__ void k_nn_out(const float* __restrict__ h3, const int8_t* s, int64_t stride, int B, int L,
                          float sign, const float* __restrict__ w, float* logq, float* dz) {
     __shared__ float red[16];
+    // the layer's 80 weights and its bias, read from LDS by every lane (kept
+    // in scalar registers they overflowed them)
+    __shared__ float w4[C * NTB + 1];
+    for (int i = threadIdx.x; i < C * NTB + 1; i += blockDim.x)
+        w4[i] = w[NNOff::W4 + i];
+    __syncthreads();
     const int N = L * L, b = blockIdx.x;
     const float* xb = h3 + (size_t)b * N * C;
     const int8_t* sb = s + (int64_t)b * stride;
     float lq = 0.f;
     for (int p = threadIdx.x; p < N; p += blockDim.x) {
         const TSite q{p / L, p % L};
-        float z = w[NNOff::B4];
+        float z = w4[C * NTB];  // B4 follows W4
 #pragma unroll
         for (int t = 0; t < NTB; ++t) {
             if (!tinside(q, L, tap_dy(t), tap_dx(t)))
@@ -932,7 +938,7 @@ __global__ void k_nn_out(const float* __restrict__ h3, const int8_t* s, int64_t 
                 const f4 a = src[c4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    z = fmaf(w[NNOff::W4 + (4 * c4 + c) * NTB + t], a[c], z);
+                    z = fmaf(w4[(4 * c4 + c) * NTB + t], a[c], z);
             }
         }
         const float sp = sign * (float)sb[p];
