@@ -1,6 +1,7 @@
 // Kernels of the learned whole-lattice proposal: the masked-convolution
-// autoregressive network (forward, backward, Adam, incremental sampling)
-// and the Metropolis-Hastings acceptance of whole-lattice proposals.
+// autoregressive network (training: forward, backward, Adam; the wavefront
+// sampler; log q of given configurations, a whole lattice at a time) and
+// the Metropolis-Hastings acceptance of whole-lattice proposals.
 //
 // The network's parameters are bfloat16; the kernels read the float32
 // expansion of those bfloat16 values (`wexp`, exactly the same numbers) and
